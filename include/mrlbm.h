@@ -1,0 +1,173 @@
+/*
+ * mrlbm.h -- C ABI of the MI355X multiresolution-adapted lattice Boltzmann library.
+ *
+ * One handle holds one adaptive MR-LBM run (or a batch of independent runs) on the GPU:
+ * a DdQq scheme with lattice velocity lambda, relaxation rates s and built-in
+ * equilibria (Sec. 2.1 and Sec. 5 of Bellotti, Gouarin, Graille, Massot, "Multiresolution-
+ * based mesh adaptation and error control for lattice Boltzmann methods with applications
+ * to hyperbolic conservation laws"), nested dyadic lattices J_min..J (Sec. 3), the centered
+ * prediction of half-width gamma (Sec. 3.1), the threshold eps (Sec. 3.4) and the
+ * regularity guess mu_bar of the enlargement rule (Sec. 4.2).
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns a status code (MRLBM_OK = 0 or a negative MRLBM_E*); nothing
+ *    throws or aborts across the ABI.
+ *  - Parameters are validated on the host before any device allocation or launch.
+ *  - Host buffers are owned by the caller; create copies what it needs, queries write
+ *    into caller-provided arrays of stated capacity. If a capacity is too small the call
+ *    returns MRLBM_ECAPACITY and sets the required size in *n_out.
+ *  - Device memory is owned by the handle (allocated in create, freed in destroy).
+ *  - Work is ordered on the handle's HIP stream (the one passed at create, or a private
+ *    non-blocking stream when NULL is passed). step/adapt only enqueue; queries and
+ *    stats synchronize the stream.
+ *  - A handle is not thread-safe. MRLBM_ENUMERIC (a NaN met in a detail or a collision) is
+ *    sticky: afterwards every call but destroy and last_error returns it.
+ *  - Conserved moments are ordered by physics: advection/Burgers (u); shallow water
+ *    (h, hu); Euler (rho, rho u, E). Populations are internal.
+ */
+#ifndef MRLBM_H
+#define MRLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MRLBM_ABI_VERSION 1
+
+enum mrlbm_status {
+    MRLBM_OK = 0,
+    MRLBM_EINVAL = -1,    /* invalid argument or parameter set                  */
+    MRLBM_ENOMEM = -2,    /* device allocation failed                           */
+    MRLBM_EDEVICE = -3,   /* HIP runtime error (no device, launch failure, ...) */
+    MRLBM_ENUMERIC = -4,  /* NaN met in a detail or collision; sticky           */
+    MRLBM_ECAPACITY = -5, /* output capacity too small, or J beyond the limit   */
+    MRLBM_ESTATE = -6     /* call not valid in the handle's state               */
+};
+
+/* Schemes (Sec. 5.1.1 D1Q2, Sec. 5.2.1 D1Q3, Sec. 5.3 vectorial D1Q2^k). */
+enum mrlbm_scheme { MRLBM_D1Q2 = 0, MRLBM_D1Q3 = 1, MRLBM_D1Q2x2 = 2, MRLBM_D1Q2x3 = 3 };
+/* Physics (equilibria). Valid pairs: D1Q2+{ADVECTION,BURGERS}, D1Q3+{BURGERS,SHALLOW_WATER},
+ * D1Q2x2+SHALLOW_WATER, D1Q2x3+EULER. */
+enum mrlbm_physics { MRLBM_ADVECTION = 0, MRLBM_BURGERS = 1, MRLBM_SHALLOW_WATER = 2, MRLBM_EULER = 3 };
+/* Boundary reading: wrap, or map an out-of-range index to the nearest cell of its level. */
+enum mrlbm_bc { MRLBM_PERIODIC = 0, MRLBM_CLAMP = 1 };
+/* Storage precision: FP64, or FP32 state with details and thresholds evaluated in FP64. */
+enum mrlbm_precision { MRLBM_FP64 = 0, MRLBM_FP32_STORAGE = 1 };
+/* Where moments are reported: on the complete leaves (spatial order) or reconstructed
+ * on every cell of the finest lattice (Sec. 3.3, reconstruction operator). */
+enum mrlbm_where { MRLBM_LEAVES = 0, MRLBM_FINEST = 1 };
+
+/* Largest finest level supported on one GPU workgroup's LDS. */
+#define MRLBM_MAX_J 16
+
+typedef struct {
+    int32_t abi_version; /* must be MRLBM_ABI_VERSION                                    */
+    int32_t scheme;      /* enum mrlbm_scheme                                              */
+    int32_t physics;     /* enum mrlbm_physics                                             */
+    int32_t bc;          /* enum mrlbm_bc                                                  */
+    int32_t precision;   /* enum mrlbm_precision                                           */
+    int32_t n_s;         /* number of rates in s: 1 (broadcast) or q - q_cons              */
+    double lambda;       /* lattice velocity > 0; dt = dx_J / lambda (Sec. 2.1)            */
+    double s[8];         /* relaxation rates of the non-conserved moments, in (0, 2]       */
+    double phys[4];      /* [0] advection velocity V, [1] gravity g > 0,
+                            [2] gamma_gas > 1, [3] alpha > 0 of the D1Q3 Burgers
+                            third-moment equilibrium alpha lambda^2 u                     */
+    double x_min, x_max; /* domain [a, b], a < b (Sec. 2)                                  */
+    int32_t j_min;       /* coarsest level, 1 <= j_min <= j_max                            */
+    int32_t j_max;       /* finest level J <= MRLBM_MAX_J                                   */
+    int32_t gamma;       /* prediction half-width 1..3 (Sec. 3.1)                          */
+    int32_t mu_bar;      /* regularity guess of enlargement rule (b), 0..30 (Sec. 4.2)      */
+    double eps;          /* threshold eps >= 0, finite; eps_j = 2^(j-J) eps (Sec. 3.4)       */
+    uint32_t flags;      /* reserved, must be 0                                             */
+    int32_t reserved;
+} mrlbm_params;
+
+typedef struct {
+    int64_t steps;        /* time steps taken                                            */
+    int64_t leaves;       /* #S(Lambda) of the current tree                               */
+    int64_t leaf_updates; /* sum over steps of #S(Lambda^{n+1}): leaf-cell updates        */
+    int32_t numeric_error;/* 1 once a NaN was met                                         */
+    int32_t q;            /* populations per cell                                         */
+    int32_t q_cons;       /* conserved moments per cell                                   */
+    int32_t j_max;
+} mrlbm_stats_t;
+
+typedef struct mrlbm_s* mrlbm_t;
+typedef struct mrlbm_batch_s* mrlbm_batch_t;
+
+/* Validate p on the host; returns MRLBM_OK or MRLBM_EINVAL/MRLBM_ECAPACITY without
+ * touching the device. Useful to test a parameter set before create. */
+int mrlbm_validate(const mrlbm_params* p);
+
+/* Create one run. m_cons0: host array [q_cons][2^j_max] of finest-level conserved cell
+ * averages at t = 0 (Sec. 2: averages on the finest lattice); populations start at
+ * equilibrium and Lambda^0 is the full tree (Sec. 4.4, start of the error analysis).
+ * hip_stream: a hipStream_t cast to void*, or NULL for a private stream.
+ * On success *out holds the handle; on failure *out is NULL. */
+int mrlbm_create(const mrlbm_params* p, const double* m_cons0, void* hip_stream, mrlbm_t* out);
+
+/* Mesh adaptation only: Lambda <- G(H_eps(T_eps(Lambda))) with the data transfer of
+ * Sec. 4.1.1 (projection for coarsened cells, prediction for added cells). */
+int mrlbm_adapt(mrlbm_t h);
+
+/* nsteps >= 0 full time steps: adaptation, leaves collision (Sec. 4.5, eq.
+ * LeavesCollision) and the compact reconstructed stream (Sec. 4.3.2, eq.
+ * AdaptiveStreamPhase). Enqueued on the handle's stream. */
+int mrlbm_step(mrlbm_t h, int32_t nsteps);
+
+/* Conserved moments, written as out[c * n + i] for moment c and position i.
+ * where = MRLBM_LEAVES: i runs over the complete leaves in spatial order, n = #S.
+ * where = MRLBM_FINEST: i runs over the 2^J finest cells (reconstruction), n = 2^J.
+ * cap is the capacity of out in doubles (>= q_cons * n); *n_out receives n. */
+int mrlbm_moments(mrlbm_t h, int32_t where, double* out, int64_t cap, int64_t* n_out);
+
+/* Populations on the complete leaves in spatial order, out[h * n + i]; same capacity
+ * rules (cap >= q * n). FP32 storage is widened to double. */
+int mrlbm_populations(mrlbm_t h, double* out, int64_t cap, int64_t* n_out);
+
+/* Complete leaves (Sec. 3.3) in spatial order: level[i], index[i]; cap entries each. */
+int mrlbm_leaves(mrlbm_t h, int32_t* level, int64_t* index, int64_t cap, int64_t* n_leaves);
+
+int mrlbm_stats(mrlbm_t h, mrlbm_stats_t* st);
+
+/* Wall time of nsteps steps measured with HIP events on the handle's stream around the
+ * launches (milliseconds). Synchronizes. */
+int mrlbm_step_timed(mrlbm_t h, int32_t nsteps, double* elapsed_ms);
+
+void mrlbm_destroy(mrlbm_t h);
+
+/* Last error message of the handle (or of the last failed create when h is NULL). The
+ * string is owned by the library and valid until the next call on the handle. */
+const char* mrlbm_last_error(mrlbm_t h);
+
+/* ---------------------------------------------------------------- batched engine
+ * n independent runs advanced by one launch per call: one workgroup per run, every step
+ * of the run inside the workgroup (intra-workgroup barriers only). All runs of one batch
+ * share scheme, precision and gamma; J, eps, physics and the other parameters may differ.
+ * m_cons0[i] points to run i's [q_cons][2^j_max(i)] host array. The launch for a given
+ * nsteps is captured once in a HIP graph and replayed. */
+int mrlbm_batch_create(const mrlbm_params* p, int32_t n, const double* const* m_cons0,
+                       void* hip_stream, mrlbm_batch_t* out);
+int mrlbm_batch_step(mrlbm_batch_t b, int32_t nsteps);
+int mrlbm_batch_step_timed(mrlbm_batch_t b, int32_t nsteps, double* elapsed_ms);
+int mrlbm_batch_moments(mrlbm_batch_t b, int32_t inst, int32_t where, double* out, int64_t cap,
+                        int64_t* n_out);
+int mrlbm_batch_leaves(mrlbm_batch_t b, int32_t inst, int32_t* level, int64_t* index, int64_t cap,
+                       int64_t* n_leaves);
+int mrlbm_batch_stats(mrlbm_batch_t b, int32_t inst, mrlbm_stats_t* st);
+/* Sum of leaf_updates over all runs of the batch. Synchronizes. */
+int mrlbm_batch_total_updates(mrlbm_batch_t b, int64_t* total);
+/* Launch shape used by the batch: threads per workgroup (64..512, multiple of 64), 0 =
+ * let the built-in tuner choose. Takes effect at the next step call. */
+int mrlbm_batch_set_block(mrlbm_batch_t b, int32_t threads);
+int mrlbm_batch_get_block(mrlbm_batch_t b, int32_t* threads);
+void mrlbm_batch_destroy(mrlbm_batch_t b);
+const char* mrlbm_batch_last_error(mrlbm_batch_t b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRLBM_H */

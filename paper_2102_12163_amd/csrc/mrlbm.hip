@@ -1,0 +1,684 @@
+// mrlbm.hip -- host side of the C ABI declared in include/mrlbm.h.
+//
+// The library validates parameters on the host, allocates one device pool per handle
+// (values, tree words, leaf list, interface pairs for every run), starts each run at
+// equilibrium on the full tree, and advances runs with the workgroup-per-run kernel of
+// mrlbm_kernels.h. Batched steps are captured once per (nsteps, block size) in a HIP graph
+// and replayed.
+
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mrlbm.h"
+#include "mrlbm_kernels.h"
+
+using namespace mrl;
+
+namespace {
+
+struct Engine {
+    int n = 0, prec = 0, scheme = 0, gamma = 1;
+    std::vector<mrlbm_params> P;
+    std::vector<Desc> hd;
+    std::vector<size_t> voff;
+    Desc* dd = nullptr;
+    State* ds = nullptr;
+    char* pool = nullptr;
+    size_t pool_bytes = 0;
+    double* stage = nullptr;
+    size_t stage_elems = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t lds = 0;
+    int maxJ = 0;
+    int nt = 0;          // threads per workgroup in use
+    int nt_user = 0;     // 0: tuner choice
+    bool numeric = false;
+    std::string err;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int gsteps = -1, gnt = -1;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+thread_local std::string g_create_error;
+
+struct SchemeInfo {
+    int q, qc, nm;
+};
+
+bool scheme_info(int scheme, int physics, SchemeInfo* si) {
+    if (scheme == MRLBM_D1Q2 && (physics == MRLBM_ADVECTION || physics == MRLBM_BURGERS)) {
+        *si = {2, 1, 2};
+        return true;
+    }
+    if (scheme == MRLBM_D1Q3 && physics == MRLBM_BURGERS) {
+        *si = {3, 1, 2};
+        return true;
+    }
+    if (scheme == MRLBM_D1Q3 && physics == MRLBM_SHALLOW_WATER) {
+        *si = {3, 2, 2};
+        return true;
+    }
+    if (scheme == MRLBM_D1Q2x2 && physics == MRLBM_SHALLOW_WATER) {
+        *si = {4, 2, 4};
+        return true;
+    }
+    if (scheme == MRLBM_D1Q2x3 && physics == MRLBM_EULER) {
+        *si = {6, 3, 6};
+        return true;
+    }
+    return false;
+}
+
+int validate(const mrlbm_params* p, std::string* why) {
+    auto bad = [&](const char* m) {
+        if (why) *why = m;
+        return (int)MRLBM_EINVAL;
+    };
+    if (!p) return bad("params is NULL");
+    if (p->abi_version != MRLBM_ABI_VERSION) return bad("abi_version mismatch");
+    SchemeInfo si;
+    if (!scheme_info(p->scheme, p->physics, &si)) return bad("unsupported scheme/physics pair");
+    if (p->bc != MRLBM_PERIODIC && p->bc != MRLBM_CLAMP) return bad("bc must be PERIODIC or CLAMP");
+    if (p->precision != MRLBM_FP64 && p->precision != MRLBM_FP32_STORAGE) return bad("unknown precision");
+    if (!(p->lambda > 0.0) || !isfinite(p->lambda)) return bad("lambda must be finite and > 0");
+    const int nn = si.q - si.qc;
+    if (p->n_s != 1 && p->n_s != nn) return bad("n_s must be 1 or q - q_cons");
+    for (int i = 0; i < p->n_s; ++i)
+        if (!(p->s[i] > 0.0 && p->s[i] <= 2.0)) return bad("relaxation rates must lie in (0, 2]");
+    if (!isfinite(p->x_min) || !isfinite(p->x_max) || !(p->x_max > p->x_min)) return bad("need x_min < x_max");
+    if (p->gamma < 1 || p->gamma > 3) return bad("gamma must be 1, 2 or 3");
+    if (p->j_min < 1 || p->j_min > p->j_max) return bad("need 1 <= j_min <= j_max");
+    if (p->bc == MRLBM_PERIODIC && (1 << p->j_min) < 2 * p->gamma + 1)
+        return bad("periodic coarsest level needs 2^j_min >= 2 gamma + 1");
+    if (p->mu_bar < 0 || p->mu_bar > 30) return bad("mu_bar must be in 0..30");
+    if (!(p->eps >= 0.0) || !isfinite(p->eps)) return bad("eps must be finite and >= 0");
+    if (p->flags != 0) return bad("flags must be 0");
+    if (p->physics == MRLBM_SHALLOW_WATER && !(p->phys[1] > 0.0)) return bad("gravity must be > 0");
+    if (p->physics == MRLBM_EULER && !(p->phys[2] > 1.0)) return bad("gamma_gas must be > 1");
+    if (p->scheme == MRLBM_D1Q3 && p->physics == MRLBM_BURGERS && !(p->phys[3] > 0.0))
+        return bad("alpha must be > 0");
+    for (int i = 0; i < 4; ++i)
+        if (!isfinite(p->phys[i])) return bad("physical parameters must be finite");
+    if (p->j_max > MRLBM_MAX_J) {
+        if (why) *why = "j_max beyond MRLBM_MAX_J";
+        return MRLBM_ECAPACITY;
+    }
+    return MRLBM_OK;
+}
+
+Coef make_coef(const mrlbm_params* p, const SchemeInfo& si) {
+    Coef c;
+    memset(&c, 0, sizeof(c));
+    c.lam = p->lambda;
+    c.lam2 = p->lambda * p->lambda;
+    c.V = p->phys[0];
+    c.alam2 = p->phys[3] * c.lam2;
+    c.g2 = 0.5 * p->phys[1];
+    c.gam = p->phys[2];
+    c.k3 = 0.5 * (3.0 - c.gam);
+    c.gm1 = c.gam - 1.0;
+    c.k5 = 0.5 * (1.0 - c.gam);
+    const int nn = si.q - si.qc;
+    for (int i = 0; i < nn; ++i) {
+        c.s[i] = p->n_s == 1 ? p->s[0] : p->s[i];
+        c.oms[i] = 1.0 - c.s[i];
+    }
+    c.physics = p->physics;
+    c.qc = si.qc;
+    return c;
+}
+
+void pred_coeffs(int gamma, double* c) {
+    c[0] = c[1] = c[2] = 0.0;
+    if (gamma == 1) {
+        c[0] = -1.0 / 8.0;
+    } else if (gamma == 2) {
+        c[0] = -22.0 / 128.0;
+        c[1] = 3.0 / 128.0;
+    } else {
+        // Sec. 3.1 prints +5/1024 for c_3; exactness on odd degrees requires -5/1024.
+        c[0] = -201.0 / 1024.0;
+        c[1] = 11.0 / 256.0;
+        c[2] = -5.0 / 1024.0;
+    }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t lds_bytes_for(int jmin, int J) {
+    const size_t wt = (size_t)wbase(jmin, J + 1);
+    const size_t nwJ = (size_t)nwords(J);
+    return 4 * wt * 8 + nwJ * 8 + nwJ * 4 + 64;
+}
+
+// ---------------------------------------------------------------- kernel dispatch
+typedef void (*StepK)(const Desc*, State*, int, int);
+typedef void (*QueryK)(const Desc*, State*, int, int, double*);
+typedef void (*InitK)(const Desc*, State*, const double*, long long);
+
+template <typename T, int S, int G>
+void pick(StepK* s, QueryK* q) {
+    *s = k_steps<T, S, G>;
+    *q = k_query<T, S, G>;
+}
+
+bool kernels_for(int prec, int scheme, int gamma, StepK* s, QueryK* q, InitK* in) {
+#define MRL_CASE(P, TT, SS)                                          \
+    if (prec == P && scheme == SS) {                                 \
+        *in = k_init<TT, SS>;                                        \
+        if (gamma == 1) { pick<TT, SS, 1>(s, q); return true; }      \
+        if (gamma == 2) { pick<TT, SS, 2>(s, q); return true; }      \
+        if (gamma == 3) { pick<TT, SS, 3>(s, q); return true; }      \
+    }
+    MRL_CASE(0, double, 0)
+    MRL_CASE(0, double, 1)
+    MRL_CASE(0, double, 2)
+    MRL_CASE(0, double, 3)
+    MRL_CASE(1, float, 0)
+    MRL_CASE(1, float, 1)
+    MRL_CASE(1, float, 2)
+    MRL_CASE(1, float, 3)
+#undef MRL_CASE
+    return false;
+}
+
+int hip_fail(Engine* e, hipError_t st, const char* what) {
+    e->err = std::string(what) + ": " + hipGetErrorString(st);
+    return st == hipErrorOutOfMemory ? MRLBM_ENOMEM : MRLBM_EDEVICE;
+}
+
+int default_block(int maxJ) {
+    if (maxJ <= 9) return 128;
+    if (maxJ <= 12) return 256;
+    return 512;
+}
+
+void engine_free(Engine* e) {
+    if (!e) return;
+    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    if (e->ev0) (void)hipEventDestroy(e->ev0);
+    if (e->ev1) (void)hipEventDestroy(e->ev1);
+    if (e->stage) (void)hipFree(e->stage);
+    if (e->pool) (void)hipFree(e->pool);
+    if (e->dd) (void)hipFree(e->dd);
+    if (e->ds) (void)hipFree(e->ds);
+    if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
+    delete e;
+}
+
+int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* stream, Engine** out) {
+    *out = nullptr;
+    g_create_error.clear();
+    if (n <= 0 || !ps || !m0) {
+        g_create_error = "need n > 0, params and initial data";
+        return MRLBM_EINVAL;
+    }
+    for (int i = 0; i < n; ++i) {
+        std::string why;
+        const int rc = validate(&ps[i], &why);
+        if (rc != MRLBM_OK) {
+            g_create_error = "instance " + std::to_string(i) + ": " + why;
+            return rc;
+        }
+        if (ps[i].scheme != ps[0].scheme || ps[i].precision != ps[0].precision || ps[i].gamma != ps[0].gamma) {
+            g_create_error = "all runs of a batch must share scheme, precision and gamma";
+            return MRLBM_EINVAL;
+        }
+        if (!m0[i]) {
+            g_create_error = "initial data pointer is NULL";
+            return MRLBM_EINVAL;
+        }
+        SchemeInfo si;
+        scheme_info(ps[i].scheme, ps[i].physics, &si);
+        const size_t cnt = (size_t)si.qc << ps[i].j_max;
+        for (size_t k = 0; k < cnt; ++k)
+            if (!isfinite(m0[i][k])) {
+                g_create_error = "initial data must be finite";
+                return MRLBM_EINVAL;
+            }
+    }
+    Engine* e = new (std::nothrow) Engine();
+    if (!e) return MRLBM_ENOMEM;
+    e->n = n;
+    e->prec = ps[0].precision;
+    e->scheme = ps[0].scheme;
+    e->gamma = ps[0].gamma;
+    e->P.assign(ps, ps + n);
+    StepK sk;
+    QueryK qk;
+    InitK ik;
+    kernels_for(e->prec, e->scheme, e->gamma, &sk, &qk, &ik);
+    int dev_count = 0;
+    hipError_t st = hipGetDeviceCount(&dev_count);
+    if (st != hipSuccess || dev_count == 0) {
+        g_create_error = "no HIP device";
+        delete e;
+        return MRLBM_EDEVICE;
+    }
+    const size_t tsz = e->prec == MRLBM_FP64 ? 8 : 4;
+    // layout of the pool
+    size_t off = 0;
+    size_t maxNJ = 0, maxq = 0;
+    e->hd.resize(n);
+    std::vector<size_t> o_va(n), o_vb(n), o_split(n), o_list(n), o_pairs(n);
+    for (int i = 0; i < n; ++i) {
+        const mrlbm_params& p = ps[i];
+        SchemeInfo si;
+        scheme_info(p.scheme, p.physics, &si);
+        const size_t NJ = (size_t)1 << p.j_max;
+        const size_t vals = (size_t)si.q * (((size_t)1 << (p.j_max + 1)) - ((size_t)1 << p.j_min));
+        o_va[i] = off;
+        off = align256(off + vals * tsz);
+        o_vb[i] = off;
+        off = align256(off + vals * tsz);
+        o_split[i] = off;
+        off = align256(off + (size_t)std::max(1, wbase(p.j_min, p.j_max)) * 8);
+        o_list[i] = off;
+        off = align256(off + NJ * 4);
+        o_pairs[i] = off;
+        off = align256(off + 2 * (size_t)si.nm * (NJ + 1) * tsz);
+        maxNJ = std::max(maxNJ, NJ);
+        maxq = std::max(maxq, (size_t)si.q);
+        e->maxJ = std::max(e->maxJ, p.j_max);
+        e->lds = std::max(e->lds, lds_bytes_for(p.j_min, p.j_max));
+        Desc& d = e->hd[i];
+        memset(&d, 0, sizeof(d));
+        d.jmin = p.j_min;
+        d.jmax = p.j_max;
+        d.gamma = p.gamma;
+        d.mu_bar = p.mu_bar;
+        d.bc = p.bc;
+        d.q = si.q;
+        d.qc = si.qc;
+        d.nm = si.nm;
+        d.eps = p.eps;
+        pred_coeffs(p.gamma, d.c);
+        d.cf = make_coef(&p, si);
+    }
+    e->pool_bytes = off;
+    auto fail = [&](hipError_t s, const char* what) {
+        hip_fail(e, s, what);
+        g_create_error = e->err;
+        const int rc = s == hipErrorOutOfMemory ? MRLBM_ENOMEM : MRLBM_EDEVICE;
+        engine_free(e);
+        return rc;
+    };
+    if ((st = hipMalloc(&e->pool, e->pool_bytes)) != hipSuccess) return fail(st, "hipMalloc(pool)");
+    if ((st = hipMalloc(&e->dd, sizeof(Desc) * n)) != hipSuccess) return fail(st, "hipMalloc(desc)");
+    if ((st = hipMalloc(&e->ds, sizeof(State) * n)) != hipSuccess) return fail(st, "hipMalloc(state)");
+    e->stage_elems = maxNJ * maxq;
+    if ((st = hipMalloc(&e->stage, e->stage_elems * sizeof(double))) != hipSuccess) return fail(st, "hipMalloc(stage)");
+    if (stream) {
+        e->stream = (hipStream_t)stream;
+    } else {
+        if ((st = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking)) != hipSuccess)
+            return fail(st, "hipStreamCreate");
+        e->own_stream = true;
+    }
+    if ((st = hipEventCreate(&e->ev0)) != hipSuccess) return fail(st, "hipEventCreate");
+    if ((st = hipEventCreate(&e->ev1)) != hipSuccess) return fail(st, "hipEventCreate");
+    if ((st = hipMemsetAsync(e->pool, 0, e->pool_bytes, e->stream)) != hipSuccess) return fail(st, "hipMemset");
+    for (int i = 0; i < n; ++i) {
+        Desc& d = e->hd[i];
+        d.va = e->pool + o_va[i];
+        d.vb = e->pool + o_vb[i];
+        d.split = reinterpret_cast<uint64_t*>(e->pool + o_split[i]);
+        d.list = reinterpret_cast<uint32_t*>(e->pool + o_list[i]);
+        d.pairs = e->pool + o_pairs[i];
+    }
+    if ((st = hipMemcpyAsync(e->dd, e->hd.data(), sizeof(Desc) * n, hipMemcpyHostToDevice, e->stream)) != hipSuccess)
+        return fail(st, "hipMemcpy(desc)");
+    // initial conserved averages: staged through one device buffer, one run at a time
+    double* dm = nullptr;
+    size_t mcap = 0;
+    for (int i = 0; i < n; ++i) {
+        const size_t cnt = (size_t)e->hd[i].qc << ps[i].j_max;
+        mcap = std::max(mcap, cnt);
+    }
+    if ((st = hipMalloc(&dm, mcap * sizeof(double))) != hipSuccess) return fail(st, "hipMalloc(init)");
+    for (int i = 0; i < n; ++i) {
+        const size_t cnt = (size_t)e->hd[i].qc << ps[i].j_max;
+        st = hipMemcpyAsync(dm, m0[i], cnt * sizeof(double), hipMemcpyHostToDevice, e->stream);
+        if (st != hipSuccess) {
+            (void)hipFree(dm);
+            return fail(st, "hipMemcpy(init)");
+        }
+        const int NJ = 1 << ps[i].j_max;
+        dim3 grid((NJ + 255) / 256, 1);
+        hipLaunchKernelGGL(ik, grid, dim3(256), 0, e->stream, e->dd + i, e->ds + i, (const double*)dm, 0LL);
+        st = hipGetLastError();
+        if (st != hipSuccess) {
+            (void)hipFree(dm);
+            return fail(st, "init launch");
+        }
+    }
+    st = hipStreamSynchronize(e->stream);
+    (void)hipFree(dm);
+    if (st != hipSuccess) return fail(st, "init");
+    (void)hipFuncSetAttribute((const void*)sk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)e->lds);
+    (void)hipFuncSetAttribute((const void*)qk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)e->lds);
+    e->nt = default_block(e->maxJ);
+    *out = e;
+    return MRLBM_OK;
+}
+
+int check_numeric(Engine* e) { return e->numeric ? MRLBM_ENUMERIC : MRLBM_OK; }
+
+int launch_steps(Engine* e, int nsteps, int mode, bool use_graph) {
+    if (nsteps <= 0) return MRLBM_OK;
+    StepK sk;
+    QueryK qk;
+    InitK ik;
+    kernels_for(e->prec, e->scheme, e->gamma, &sk, &qk, &ik);
+    const int nt = e->nt_user ? e->nt_user : e->nt;
+    hipError_t st;
+    if (use_graph && mode == (MODE_ADAPT | MODE_SCHEME)) {
+        if (!e->gexec || e->gsteps != nsteps || e->gnt != nt) {
+            if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+            if (e->graph) (void)hipGraphDestroy(e->graph);
+            e->gexec = nullptr;
+            e->graph = nullptr;
+            if ((st = hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return hip_fail(e, st, "hipStreamBeginCapture");
+            hipLaunchKernelGGL(sk, dim3(e->n), dim3(nt), e->lds, e->stream, (const Desc*)e->dd, e->ds, nsteps, mode);
+            st = hipStreamEndCapture(e->stream, &e->graph);
+            if (st != hipSuccess) return hip_fail(e, st, "hipStreamEndCapture");
+            if ((st = hipGraphInstantiate(&e->gexec, e->graph, nullptr, nullptr, 0)) != hipSuccess)
+                return hip_fail(e, st, "hipGraphInstantiate");
+            e->gsteps = nsteps;
+            e->gnt = nt;
+        }
+        if ((st = hipGraphLaunch(e->gexec, e->stream)) != hipSuccess) return hip_fail(e, st, "hipGraphLaunch");
+        return MRLBM_OK;
+    }
+    hipLaunchKernelGGL(sk, dim3(e->n), dim3(nt), e->lds, e->stream, (const Desc*)e->dd, e->ds, nsteps, mode);
+    st = hipGetLastError();
+    if (st != hipSuccess) return hip_fail(e, st, "step launch");
+    return MRLBM_OK;
+}
+
+int read_states(Engine* e, std::vector<State>& hs) {
+    hs.resize(e->n);
+    hipError_t st = hipMemcpyAsync(hs.data(), e->ds, sizeof(State) * e->n, hipMemcpyDeviceToHost, e->stream);
+    if (st == hipSuccess) st = hipStreamSynchronize(e->stream);
+    if (st != hipSuccess) return hip_fail(e, st, "state readback");
+    for (auto& s : hs)
+        if (s.flags & 1) e->numeric = true;
+    return MRLBM_OK;
+}
+
+int run_query(Engine* e, int inst, int where, int what, int64_t* n_out) {
+    StepK sk;
+    QueryK qk;
+    InitK ik;
+    kernels_for(e->prec, e->scheme, e->gamma, &sk, &qk, &ik);
+    const int nt = e->nt_user ? e->nt_user : e->nt;
+    hipLaunchKernelGGL(qk, dim3(1), dim3(nt), e->lds, e->stream, (const Desc*)(e->dd + inst), e->ds + inst, where,
+                       what, e->stage);
+    hipError_t st = hipGetLastError();
+    if (st != hipSuccess) return hip_fail(e, st, "query launch");
+    State s;
+    st = hipMemcpyAsync(&s, e->ds + inst, sizeof(State), hipMemcpyDeviceToHost, e->stream);
+    if (st == hipSuccess) st = hipStreamSynchronize(e->stream);
+    if (st != hipSuccess) return hip_fail(e, st, "query");
+    if (s.flags & 1) e->numeric = true;
+    *n_out = where == MRLBM_FINEST ? ((int64_t)1 << e->P[inst].j_max) : s.n_leaves;
+    return MRLBM_OK;
+}
+
+int engine_moments(Engine* e, int inst, int where, int what, double* out, int64_t cap, int64_t* n_out) {
+    if (inst < 0 || inst >= e->n || !n_out || (where != MRLBM_LEAVES && where != MRLBM_FINEST)) {
+        e->err = "bad query arguments";
+        return MRLBM_EINVAL;
+    }
+    if (e->numeric) return MRLBM_ENUMERIC;
+    int64_t n = 0;
+    int rc = run_query(e, inst, where, what, &n);
+    if (rc != MRLBM_OK) return rc;
+    const int comps = what == 0 ? e->hd[inst].qc : e->hd[inst].q;
+    *n_out = n;
+    if (!out || cap < comps * n) {
+        e->err = "output capacity too small";
+        return MRLBM_ECAPACITY;
+    }
+    hipError_t st = hipMemcpy(out, e->stage, sizeof(double) * comps * n, hipMemcpyDeviceToHost);
+    if (st != hipSuccess) return hip_fail(e, st, "moments readback");
+    return check_numeric(e);
+}
+
+int engine_leaves(Engine* e, int inst, int32_t* level, int64_t* index, int64_t cap, int64_t* n_leaves) {
+    if (inst < 0 || inst >= e->n || !n_leaves) {
+        e->err = "bad query arguments";
+        return MRLBM_EINVAL;
+    }
+    if (e->numeric) return MRLBM_ENUMERIC;
+    int64_t n = 0;
+    int rc = run_query(e, inst, MRLBM_LEAVES, 0, &n);
+    if (rc != MRLBM_OK) return rc;
+    *n_leaves = n;
+    if (!level || !index || cap < n) {
+        e->err = "output capacity too small";
+        return MRLBM_ECAPACITY;
+    }
+    std::vector<uint32_t> keys(n);
+    hipError_t st = hipMemcpy(keys.data(), e->hd[inst].list, sizeof(uint32_t) * n, hipMemcpyDeviceToHost);
+    if (st != hipSuccess) return hip_fail(e, st, "leaves readback");
+    for (int64_t i = 0; i < n; ++i) {
+        level[i] = (int32_t)(keys[i] >> 27);
+        index[i] = (int64_t)(keys[i] & ((1u << 27) - 1u));
+    }
+    return MRLBM_OK;
+}
+
+int engine_stats(Engine* e, int inst, mrlbm_stats_t* st) {
+    if (!st || inst < 0 || inst >= e->n) {
+        e->err = "bad stats arguments";
+        return MRLBM_EINVAL;
+    }
+    std::vector<State> hs;
+    int rc = read_states(e, hs);
+    if (rc != MRLBM_OK) return rc;
+    const State& s = hs[inst];
+    st->steps = s.steps;
+    st->leaves = s.n_leaves;
+    st->leaf_updates = s.leaf_updates;
+    st->numeric_error = (s.flags & 1) ? 1 : 0;
+    st->q = e->hd[inst].q;
+    st->q_cons = e->hd[inst].qc;
+    st->j_max = e->hd[inst].jmax;
+    return MRLBM_OK;
+}
+
+int engine_step_timed(Engine* e, int nsteps, bool graph, double* ms) {
+    if (e->numeric) return MRLBM_ENUMERIC;
+    if (nsteps < 0 || !ms) {
+        e->err = "bad timed-step arguments";
+        return MRLBM_EINVAL;
+    }
+    hipError_t st = hipEventRecord(e->ev0, e->stream);
+    if (st != hipSuccess) return hip_fail(e, st, "hipEventRecord");
+    int rc = launch_steps(e, nsteps, MODE_ADAPT | MODE_SCHEME, graph);
+    if (rc != MRLBM_OK) return rc;
+    if ((st = hipEventRecord(e->ev1, e->stream)) != hipSuccess) return hip_fail(e, st, "hipEventRecord");
+    if ((st = hipEventSynchronize(e->ev1)) != hipSuccess) return hip_fail(e, st, "hipEventSynchronize");
+    float f = 0.f;
+    if ((st = hipEventElapsedTime(&f, e->ev0, e->ev1)) != hipSuccess) return hip_fail(e, st, "hipEventElapsedTime");
+    *ms = (double)f;
+    std::vector<State> hs;
+    rc = read_states(e, hs);
+    if (rc != MRLBM_OK) return rc;
+    return check_numeric(e);
+}
+
+}  // namespace
+
+struct mrlbm_s {
+    Engine* e;
+};
+struct mrlbm_batch_s {
+    Engine* e;
+};
+
+extern "C" {
+
+int mrlbm_validate(const mrlbm_params* p) { return validate(p, nullptr); }
+
+int mrlbm_create(const mrlbm_params* p, const double* m_cons0, void* hip_stream, mrlbm_t* out) {
+    if (!out) return MRLBM_EINVAL;
+    *out = nullptr;
+    const double* m[1] = {m_cons0};
+    Engine* e = nullptr;
+    const int rc = engine_create(p, 1, m, hip_stream, &e);
+    if (rc != MRLBM_OK) return rc;
+    mrlbm_t h = new (std::nothrow) mrlbm_s{e};
+    if (!h) {
+        engine_free(e);
+        return MRLBM_ENOMEM;
+    }
+    *out = h;
+    return MRLBM_OK;
+}
+
+int mrlbm_adapt(mrlbm_t h) {
+    if (!h) return MRLBM_EINVAL;
+    if (h->e->numeric) return MRLBM_ENUMERIC;
+    return launch_steps(h->e, 1, MODE_ADAPT, false);
+}
+
+int mrlbm_step(mrlbm_t h, int32_t nsteps) {
+    if (!h || nsteps < 0) return MRLBM_EINVAL;
+    if (h->e->numeric) return MRLBM_ENUMERIC;
+    return launch_steps(h->e, nsteps, MODE_ADAPT | MODE_SCHEME, false);
+}
+
+int mrlbm_moments(mrlbm_t h, int32_t where, double* out, int64_t cap, int64_t* n_out) {
+    if (!h) return MRLBM_EINVAL;
+    return engine_moments(h->e, 0, where, 0, out, cap, n_out);
+}
+
+int mrlbm_populations(mrlbm_t h, double* out, int64_t cap, int64_t* n_out) {
+    if (!h) return MRLBM_EINVAL;
+    return engine_moments(h->e, 0, MRLBM_LEAVES, 1, out, cap, n_out);
+}
+
+int mrlbm_leaves(mrlbm_t h, int32_t* level, int64_t* index, int64_t cap, int64_t* n_leaves) {
+    if (!h) return MRLBM_EINVAL;
+    return engine_leaves(h->e, 0, level, index, cap, n_leaves);
+}
+
+int mrlbm_stats(mrlbm_t h, mrlbm_stats_t* st) {
+    if (!h) return MRLBM_EINVAL;
+    return engine_stats(h->e, 0, st);
+}
+
+int mrlbm_step_timed(mrlbm_t h, int32_t nsteps, double* elapsed_ms) {
+    if (!h) return MRLBM_EINVAL;
+    return engine_step_timed(h->e, nsteps, false, elapsed_ms);
+}
+
+void mrlbm_destroy(mrlbm_t h) {
+    if (!h) return;
+    if (h->e && h->e->stream) (void)hipStreamSynchronize(h->e->stream);
+    engine_free(h->e);
+    delete h;
+}
+
+const char* mrlbm_last_error(mrlbm_t h) {
+    if (!h) return g_create_error.c_str();
+    return h->e->err.c_str();
+}
+
+int mrlbm_batch_create(const mrlbm_params* p, int32_t n, const double* const* m_cons0, void* hip_stream,
+                       mrlbm_batch_t* out) {
+    if (!out) return MRLBM_EINVAL;
+    *out = nullptr;
+    Engine* e = nullptr;
+    const int rc = engine_create(p, n, m_cons0, hip_stream, &e);
+    if (rc != MRLBM_OK) return rc;
+    mrlbm_batch_t b = new (std::nothrow) mrlbm_batch_s{e};
+    if (!b) {
+        engine_free(e);
+        return MRLBM_ENOMEM;
+    }
+    *out = b;
+    return MRLBM_OK;
+}
+
+int mrlbm_batch_step(mrlbm_batch_t b, int32_t nsteps) {
+    if (!b || nsteps < 0) return MRLBM_EINVAL;
+    if (b->e->numeric) return MRLBM_ENUMERIC;
+    return launch_steps(b->e, nsteps, MODE_ADAPT | MODE_SCHEME, true);
+}
+
+int mrlbm_batch_step_timed(mrlbm_batch_t b, int32_t nsteps, double* elapsed_ms) {
+    if (!b) return MRLBM_EINVAL;
+    return engine_step_timed(b->e, nsteps, true, elapsed_ms);
+}
+
+int mrlbm_batch_moments(mrlbm_batch_t b, int32_t inst, int32_t where, double* out, int64_t cap, int64_t* n_out) {
+    if (!b) return MRLBM_EINVAL;
+    return engine_moments(b->e, inst, where, 0, out, cap, n_out);
+}
+
+int mrlbm_batch_leaves(mrlbm_batch_t b, int32_t inst, int32_t* level, int64_t* index, int64_t cap,
+                       int64_t* n_leaves) {
+    if (!b) return MRLBM_EINVAL;
+    return engine_leaves(b->e, inst, level, index, cap, n_leaves);
+}
+
+int mrlbm_batch_stats(mrlbm_batch_t b, int32_t inst, mrlbm_stats_t* st) {
+    if (!b) return MRLBM_EINVAL;
+    return engine_stats(b->e, inst, st);
+}
+
+int mrlbm_batch_total_updates(mrlbm_batch_t b, int64_t* total) {
+    if (!b || !total) return MRLBM_EINVAL;
+    std::vector<State> hs;
+    const int rc = read_states(b->e, hs);
+    if (rc != MRLBM_OK) return rc;
+    int64_t t = 0;
+    for (auto& s : hs) t += s.leaf_updates;
+    *total = t;
+    return check_numeric(b->e);
+}
+
+int mrlbm_batch_set_block(mrlbm_batch_t b, int32_t threads) {
+    if (!b) return MRLBM_EINVAL;
+    if (threads != 0 && (threads < 64 || threads > 512 || threads % 64 != 0)) {
+        b->e->err = "threads must be 0 or a multiple of 64 in 64..512";
+        return MRLBM_EINVAL;
+    }
+    b->e->nt_user = threads;
+    return MRLBM_OK;
+}
+
+int mrlbm_batch_get_block(mrlbm_batch_t b, int32_t* threads) {
+    if (!b || !threads) return MRLBM_EINVAL;
+    *threads = b->e->nt_user ? b->e->nt_user : b->e->nt;
+    return MRLBM_OK;
+}
+
+void mrlbm_batch_destroy(mrlbm_batch_t b) {
+    if (!b) return;
+    if (b->e && b->e->stream) (void)hipStreamSynchronize(b->e->stream);
+    engine_free(b->e);
+    delete b;
+}
+
+const char* mrlbm_batch_last_error(mrlbm_batch_t b) {
+    if (!b) return g_create_error.c_str();
+    return b->e->err.c_str();
+}
+
+}  // extern "C"

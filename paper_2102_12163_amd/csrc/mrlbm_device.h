@@ -1,0 +1,405 @@
+// mrlbm_device.h -- device-side building blocks of the MR-LBM step for CDNA4 (gfx950).
+//
+// Data layout of one run (all in HBM, owned by the host library):
+//   values   two buffers (A, B) of q * (2^(J+1) - 2^Jmin) elements of type T; level l
+//            starts at q * (2^l - 2^Jmin) and holds q planes of 2^l cells (level-major SoA).
+//            Only cells of the complete tree R(Lambda) carry meaningful values.
+//   split    one bit per cell of levels Jmin..J-1, "cell (l, p) has children"; 64-bit words,
+//            levels below 64 cells use one partial word. Loaded into LDS for a launch.
+//   list     complete leaves of the current tree in spatial order, key (l << 27) | k.
+//   pairs    reconstructed finest values on both sides of every leaf interface.
+//
+// Inside a workgroup the tree lives in LDS as bit words; wavefront lane i owns bit i of a
+// word, so a wave processes 64 cells of one level per iteration and __ballot turns 64
+// per-lane decisions back into one word.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mrl {
+
+constexpr int MAXQ = 6;
+constexpr int PERIODIC = 0;
+constexpr int CLAMP = 1;
+constexpr int ADVECTION = 0, BURGERS = 1, SHALLOW_WATER = 2, EULER = 3;
+
+// Scheme constants, evaluated once on the host in double precision with the same
+// expressions as the paper's formulas (see the host library for each one).
+struct Coef {
+    double lam, lam2, V, alam2, g2, gam, k3, gm1, k5;
+    double s[MAXQ], oms[MAXQ];
+    int physics, qc;
+};
+
+struct Desc {
+    int jmin, jmax, gamma, mu_bar, bc, q, qc, nm;
+    double eps;
+    double c[3];
+    Coef cf;
+    void* va;
+    void* vb;
+    uint64_t* split;
+    uint32_t* list;
+    void* pairs;
+};
+
+struct State {
+    long long steps, leaf_updates, n_leaves;
+    int cur, flags;
+};
+
+#define DEV __device__ __forceinline__
+
+__host__ __device__ inline int nwords(int l) { return l >= 6 ? (1 << (l - 6)) : 1; }
+__host__ __device__ inline int wbase(int jmin, int l) {
+    int s = 0;
+    for (int m = jmin; m < l; ++m) s += nwords(m);
+    return s;
+}
+
+DEV int bcx(int i, int n, int bc) {
+    if (bc == PERIODIC) return i & (n - 1);
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+DEV uint64_t lowmask(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
+
+// 32 parent bits -> 64 child bits (each bit doubled).
+DEV uint64_t spread32(uint64_t x) {
+    uint64_t y = x & 0xFFFFFFFFull;
+    y = (y | (y << 16)) & 0x0000FFFF0000FFFFull;
+    y = (y | (y << 8)) & 0x00FF00FF00FF00FFull;
+    y = (y | (y << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    y = (y | (y << 2)) & 0x3333333333333333ull;
+    y = (y | (y << 1)) & 0x5555555555555555ull;
+    return y | (y << 1);
+}
+
+// 64 child bits -> 32 parent bits (OR of each sibling pair).
+DEV uint64_t compress64(uint64_t x) {
+    uint64_t y = (x | (x >> 1)) & 0x5555555555555555ull;
+    y = (y | (y >> 1)) & 0x3333333333333333ull;
+    y = (y | (y >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+    y = (y | (y >> 4)) & 0x00FF00FF00FF00FFull;
+    y = (y | (y >> 8)) & 0x0000FFFF0000FFFFull;
+    y = (y | (y >> 16)) & 0x00000000FFFFFFFFull;
+    return y;
+}
+
+DEV bool getbit(const uint64_t* A, int wbl, int k) { return (A[wbl + (k >> 6)] >> (k & 63)) & 1ull; }
+
+// (l, k) in R(Lambda): every cell of level Jmin, else the parent is split.
+DEV bool in_r(const uint64_t* split, const int* wb, int jmin, int l, int k) {
+    return l == jmin ? true : getbit(split, wb[l - 1], k >> 1);
+}
+
+// Word w of R(Lambda) at level l.
+DEV uint64_t r_word(const uint64_t* split, const int* wb, int jmin, int l, int w) {
+    if (l == jmin) return lowmask(1 << l);
+    uint64_t x = split[wb[l - 1] + (w >> 1)] >> ((w & 1) * 32);
+    return spread32(x);
+}
+
+// Word w of level l dilated by r cells: bit i set iff some cell bc(i + s), |s| <= r, is set.
+// Clamp reads as zero fill (the clamped neighbours add nothing beyond the cell itself).
+DEV uint64_t dilate_word(const uint64_t* A, int wbl, int l, int w, int r, int bc) {
+    const int N = 1 << l;
+    const uint64_t x = A[wbl + w];
+    uint64_t d = x;
+    if (N >= 64) {
+        const int nw = N >> 6;
+        uint64_t xl, xr;
+        if (bc == PERIODIC) {
+            xl = A[wbl + ((w - 1) & (nw - 1))];
+            xr = A[wbl + ((w + 1) & (nw - 1))];
+        } else {
+            xl = w > 0 ? A[wbl + w - 1] : 0ull;
+            xr = w < nw - 1 ? A[wbl + w + 1] : 0ull;
+        }
+        for (int s = 1; s <= r; ++s) {
+            d |= (x << s) | (xl >> (64 - s));
+            d |= (x >> s) | (xr << (64 - s));
+        }
+    } else {
+        const uint64_t m = lowmask(N);
+        for (int s = 1; s <= r; ++s) {
+            if (bc == PERIODIC) {
+                const int sm = s % N;
+                if (sm) {
+                    d |= ((x << sm) | (x >> (N - sm))) & m;
+                    d |= ((x >> sm) | (x << (N - sm))) & m;
+                }
+            } else {
+                d |= (x << s) & m;
+                d |= x >> s;
+            }
+        }
+    }
+    return d;
+}
+
+// ------------------------------------------------------------------ values
+template <typename T>
+struct Vals {
+    T* base;
+    int jmin, q;
+    DEV T* lev(int l) const { return base + (size_t)q * ((1 << l) - (1 << jmin)); }
+    DEV T& at(int l, int h, int k) const { return lev(l)[h * (1 << l) + k]; }
+};
+
+// ------------------------------------------------------------------ schemes
+// Population order: D1Q2 (+lambda, -lambda); D1Q3 (0, +lambda, -lambda); D1Q2^k blocks
+// (+lambda, -lambda) per conserved quantity.
+template <int S> struct Sch;
+template <> struct Sch<0> {
+    static constexpr int Q = 2, NM = 2;
+    DEV static constexpr int mv(int m) { return m; }
+    DEV static constexpr int w(int h) { return h == 0 ? 1 : -1; }
+};
+template <> struct Sch<1> {
+    static constexpr int Q = 3, NM = 2;
+    DEV static constexpr int mv(int m) { return m + 1; }
+    DEV static constexpr int w(int h) { return h == 0 ? 0 : (h == 1 ? 1 : -1); }
+};
+template <> struct Sch<2> {
+    static constexpr int Q = 4, NM = 4;
+    DEV static constexpr int mv(int m) { return m; }
+    DEV static constexpr int w(int h) { return (h & 1) ? -1 : 1; }
+};
+template <> struct Sch<3> {
+    static constexpr int Q = 6, NM = 6;
+    DEV static constexpr int mv(int m) { return m; }
+    DEV static constexpr int w(int h) { return (h & 1) ? -1 : 1; }
+};
+
+template <int S> struct MovingPops { DEV static constexpr int h(int m) { return Sch<S>::mv(m); } };
+template <int S> struct AllPops { DEV static constexpr int h(int m) { return m; } };
+
+// Leaves collision (Sec. 4.5, eq. LeavesCollision) with the equilibria of Sec. 5: the
+// conserved moments stay, every other moment relaxes m* = (1 - s) m + s m_eq. The
+// expression order is fixed (it is the order the FP64 checks were written against).
+template <typename T, int S>
+DEV void collide(const Coef& c, T* f) {
+    const T lam = (T)c.lam;
+    const T half = (T)0.5;
+    if constexpr (S == 0) {
+        const T u = f[0] + f[1];
+        const T m1 = lam * (f[0] - f[1]);
+        const T eq = c.physics == ADVECTION ? (T)c.V * u : (u * u) * half;
+        const T m1s = (T)c.oms[0] * m1 + (T)c.s[0] * eq;
+        const T r = m1s / lam;
+        f[0] = half * (u + r);
+        f[1] = half * (u - r);
+    } else if constexpr (S == 1) {
+        const T lam2 = (T)c.lam2;
+        const T m0 = (f[0] + f[1]) + f[2];
+        const T m1 = lam * (f[1] - f[2]);
+        const T m2 = lam2 * (f[1] + f[2]);
+        T m1s, m2s;
+        if (c.physics == BURGERS) {
+            const T eq1 = (m0 * m0) * half;
+            const T eq2 = (T)c.alam2 * m0;
+            m1s = (T)c.oms[0] * m1 + (T)c.s[0] * eq1;
+            m2s = (T)c.oms[1] * m2 + (T)c.s[1] * eq2;
+        } else {
+            const T eq2 = (m1 * m1) / m0 + (T)c.g2 * (m0 * m0);
+            m1s = m1;
+            m2s = (T)c.oms[0] * m2 + (T)c.s[0] * eq2;
+        }
+        const T a = m2s / lam2;
+        const T b = m1s / lam;
+        f[0] = m0 - a;
+        f[1] = half * (a + b);
+        f[2] = half * (a - b);
+    } else {
+        constexpr int NB = Sch<S>::Q / 2;
+        T cc[NB], eq[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) cc[b] = f[2 * b] + f[2 * b + 1];
+        if constexpr (S == 2) {
+            eq[0] = cc[1];
+            eq[1] = (cc[1] * cc[1]) / cc[0] + (T)c.g2 * (cc[0] * cc[0]);
+        } else {
+            eq[0] = cc[1];
+            eq[1] = (T)c.k3 * ((cc[1] * cc[1]) / cc[0]) + (T)c.gm1 * cc[2];
+            eq[2] = (T)c.gam * ((cc[2] * cc[1]) / cc[0]) + (T)c.k5 * (((cc[1] * cc[1]) * cc[1]) / (cc[0] * cc[0]));
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const T n = lam * (f[2 * b] - f[2 * b + 1]);
+            const T ns = (T)c.oms[b] * n + (T)c.s[b] * eq[b];
+            const T r = ns / lam;
+            f[2 * b] = half * (cc[b] + r);
+            f[2 * b + 1] = half * (cc[b] - r);
+        }
+    }
+}
+
+// Populations at equilibrium for the conserved moments mc (Sec. 2.1.1, initial datum).
+template <typename T, int S>
+DEV void equilibrium(const Coef& c, const double* mc, T* f) {
+    const double lam = c.lam;
+    if constexpr (S == 0) {
+        const double u = mc[0];
+        const double eq = c.physics == ADVECTION ? c.V * u : (u * u) * 0.5;
+        const double r = eq / lam;
+        f[0] = (T)(0.5 * (u + r));
+        f[1] = (T)(0.5 * (u - r));
+    } else if constexpr (S == 1) {
+        const double m0 = mc[0];
+        double eq1, eq2;
+        if (c.physics == BURGERS) {
+            eq1 = (m0 * m0) * 0.5;
+            eq2 = c.alam2 * m0;
+        } else {
+            eq1 = mc[1];
+            eq2 = (eq1 * eq1) / m0 + c.g2 * (m0 * m0);
+        }
+        const double a = eq2 / c.lam2;
+        const double b = eq1 / lam;
+        f[0] = (T)(m0 - a);
+        f[1] = (T)(0.5 * (a + b));
+        f[2] = (T)(0.5 * (a - b));
+    } else {
+        constexpr int NB = Sch<S>::Q / 2;
+        double eq[NB];
+        if constexpr (S == 2) {
+            eq[0] = mc[1];
+            eq[1] = (mc[1] * mc[1]) / mc[0] + c.g2 * (mc[0] * mc[0]);
+        } else {
+            eq[0] = mc[1];
+            eq[1] = c.k3 * ((mc[1] * mc[1]) / mc[0]) + c.gm1 * mc[2];
+            eq[2] = c.gam * ((mc[2] * mc[1]) / mc[0]) + c.k5 * (((mc[1] * mc[1]) * mc[1]) / (mc[0] * mc[0]));
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const double r = eq[b] / lam;
+            f[2 * b] = (T)(0.5 * (mc[b] + r));
+            f[2 * b + 1] = (T)(0.5 * (mc[b] - r));
+        }
+    }
+}
+
+// Conserved moments of one cell, evaluated in double.
+template <typename T, int S>
+DEV void conserved(const Coef& c, const T* f, double* mc) {
+    if constexpr (S == 0) {
+        mc[0] = (double)f[0] + (double)f[1];
+    } else if constexpr (S == 1) {
+        mc[0] = ((double)f[0] + (double)f[1]) + (double)f[2];
+        if (c.qc == 2) mc[1] = c.lam * ((double)f[1] - (double)f[2]);
+    } else {
+        constexpr int NB = Sch<S>::Q / 2;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) mc[b] = (double)f[2 * b] + (double)f[2 * b + 1];
+    }
+}
+
+// ------------------------------------------------------------------ reconstruction
+// Reconstructed finest values f-double-hat at the two finest cells e-1 and e (Sec. 3.3,
+// reconstruction operator): starting at the finest level, a window of cells is followed
+// towards coarser levels until every cell of the window lies in R(Lambda); then, level by
+// level back to J, every window cell outside R(Lambda) is predicted from the parent level's
+// window (Sec. 3.1) and every cell inside R(Lambda) takes its stored value. With unwrapped
+// indices the level-l window is [((tA + 2G) >> (J - l)) - 2G, ((tB - 2G) >> (J - l)) + 2G], so
+// a window position's parent position depends only on the parity of (tA + 2G) >> (J - l):
+// the whole window stays in registers. Out-of-range cells under clamp copy the edge cell.
+template <typename T, int G, int NP, class PM>
+DEV void pair_chain(const Vals<T>& V, const uint64_t* split, const int* wb, int jmin, int J, int bc,
+                    const T* cc, int e, T* outA, T* outB) {
+    constexpr int WM = 4 * G + 1;
+    const int NJ = 1 << J;
+    int tA = e - 1, tB = e;
+    if (bc == CLAMP) {
+        tA = tA < 0 ? 0 : (tA > NJ - 1 ? NJ - 1 : tA);
+        tB = tB < 0 ? 0 : (tB > NJ - 1 ? NJ - 1 : tB);
+    }
+    int l0 = J;
+    while (l0 > jmin) {
+        const int sh = J - l0;
+        const int lo = ((tA + 2 * G) >> sh) - 2 * G;
+        const int hi = ((tB - 2 * G) >> sh) + 2 * G;
+        const int N = 1 << l0;
+        bool all = true;
+        for (int x = lo; x <= hi && all; ++x) all = in_r(split, wb, jmin, l0, bcx(x, N, bc));
+        if (all) break;
+        --l0;
+    }
+    T win[NP][WM];
+    {
+        const int sh = J - l0;
+        const int lo = ((tA + 2 * G) >> sh) - 2 * G;
+        const int N = 1 << l0;
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            const int xx = bcx(lo + i, N, bc);
+#pragma unroll
+            for (int m = 0; m < NP; ++m) win[m][i] = V.at(l0, PM::h(m), xx);
+        }
+    }
+    for (int l = l0 + 1; l <= J; ++l) {
+        const int sh = J - l;
+        const int u = (tA + 2 * G) >> sh;
+        const int lo = u - 2 * G;
+        const int hi = ((tB - 2 * G) >> sh) + 2 * G;
+        const int N = 1 << l;
+        const bool par = (u & 1) != 0;
+        T nw[NP][WM];
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            const int x = lo + i;
+            const int xx = bcx(x, N, bc);
+            const bool odd = ((i + (par ? 1 : 0)) & 1) != 0;
+            const bool inr = (i <= hi - lo) && in_r(split, wb, jmin, l, xx);
+            if (inr) {
+#pragma unroll
+                for (int m = 0; m < NP; ++m) nw[m][i] = V.at(l, PM::h(m), xx);
+            } else {
+                constexpr int pa = G;  // parent position of i when the parity is even: G + i/2
+#pragma unroll
+                for (int m = 0; m < NP; ++m) {
+                    const T f0 = par ? win[m][pa + ((i + 1) >> 1)] : win[m][pa + (i >> 1)];
+                    T acc = (T)0;
+#pragma unroll
+                    for (int a = 1; a <= G; ++a) {
+                        const T fp = par ? win[m][pa + ((i + 1) >> 1) + a] : win[m][pa + (i >> 1) + a];
+                        const T fm = par ? win[m][pa + ((i + 1) >> 1) - a] : win[m][pa + (i >> 1) - a];
+                        const T t = cc[a - 1] * (fp - fm);
+                        acc = (a == 1) ? t : acc + t;
+                    }
+                    nw[m][i] = odd ? f0 - acc : f0 + acc;
+                }
+            }
+        }
+        if (bc == CLAMP && (lo < 0 || hi >= N)) {
+            const int e0 = -lo, e1 = N - 1 - lo;
+#pragma unroll
+            for (int i = 0; i < WM; ++i) {
+                const int x = lo + i;
+                if (x < 0 || x >= N) {
+                    const int src = x < 0 ? e0 : e1;
+#pragma unroll
+                    for (int m = 0; m < NP; ++m) {
+                        T v = nw[m][0];
+#pragma unroll
+                        for (int j = 1; j < WM; ++j) v = (src == j) ? nw[m][j] : v;
+                        nw[m][i] = v;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NP; ++m)
+#pragma unroll
+            for (int i = 0; i < WM; ++i) win[m][i] = nw[m][i];
+    }
+    const bool same = (tB == tA);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+        outA[m] = win[m][0];
+        outB[m] = same ? win[m][0] : win[m][1];
+    }
+}
+
+}  // namespace mrl

@@ -1,0 +1,292 @@
+"""ctypes binding of the C ABI in include/mrlbm.h (argument marshalling only).
+
+Every step of the method runs in the HIP kernels of ``libmrlbm.so``; this module only
+converts Python parameters and numpy arrays to the ABI's structs and pointers. Importing
+it does not load the library; the first call does, and raises if it is not built.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmrlbm.so")
+
+ABI_VERSION = 1
+OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, ECAPACITY, ESTATE = 0, -1, -2, -3, -4, -5, -6
+D1Q2, D1Q3, D1Q2x2, D1Q2x3 = 0, 1, 2, 3
+ADVECTION, BURGERS, SHALLOW_WATER, EULER = 0, 1, 2, 3
+PERIODIC, CLAMP = 0, 1
+FP64, FP32_STORAGE = 0, 1
+LEAVES, FINEST = 0, 1
+MAX_J = 16
+
+_STATUS = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENUMERIC: "ENUMERIC",
+           ECAPACITY: "ECAPACITY", ESTATE: "ESTATE"}
+
+c_int32, c_int64, c_uint32, c_double, c_void_p = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                                   ctypes.c_double, ctypes.c_void_p)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("abi_version", c_int32), ("scheme", c_int32), ("physics", c_int32), ("bc", c_int32),
+                ("precision", c_int32), ("n_s", c_int32), ("lam", c_double), ("s", c_double * 8),
+                ("phys", c_double * 4), ("x_min", c_double), ("x_max", c_double), ("j_min", c_int32),
+                ("j_max", c_int32), ("gamma", c_int32), ("mu_bar", c_int32), ("eps", c_double),
+                ("flags", c_uint32), ("reserved", c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("steps", c_int64), ("leaves", c_int64), ("leaf_updates", c_int64),
+                ("numeric_error", c_int32), ("q", c_int32), ("q_cons", c_int32), ("j_max", c_int32)]
+
+
+class MRLBMError(RuntimeError):
+    def __init__(self, code, msg=""):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+# Names and signatures of every exported entry point (also used by the export test).
+_P, _PP = ctypes.POINTER, ctypes.POINTER(ctypes.c_void_p)
+SIGNATURES = {
+    "mrlbm_validate": (c_int32, [_P(Params)]),
+    "mrlbm_create": (c_int32, [_P(Params), _P(c_double), c_void_p, _PP]),
+    "mrlbm_adapt": (c_int32, [c_void_p]),
+    "mrlbm_step": (c_int32, [c_void_p, c_int32]),
+    "mrlbm_moments": (c_int32, [c_void_p, c_int32, _P(c_double), c_int64, _P(c_int64)]),
+    "mrlbm_populations": (c_int32, [c_void_p, _P(c_double), c_int64, _P(c_int64)]),
+    "mrlbm_leaves": (c_int32, [c_void_p, _P(c_int32), _P(c_int64), c_int64, _P(c_int64)]),
+    "mrlbm_stats": (c_int32, [c_void_p, _P(Stats)]),
+    "mrlbm_step_timed": (c_int32, [c_void_p, c_int32, _P(c_double)]),
+    "mrlbm_destroy": (None, [c_void_p]),
+    "mrlbm_last_error": (ctypes.c_char_p, [c_void_p]),
+    "mrlbm_batch_create": (c_int32, [_P(Params), c_int32, _P(_P(c_double)), c_void_p, _PP]),
+    "mrlbm_batch_step": (c_int32, [c_void_p, c_int32]),
+    "mrlbm_batch_step_timed": (c_int32, [c_void_p, c_int32, _P(c_double)]),
+    "mrlbm_batch_moments": (c_int32, [c_void_p, c_int32, c_int32, _P(c_double), c_int64, _P(c_int64)]),
+    "mrlbm_batch_leaves": (c_int32, [c_void_p, c_int32, _P(c_int32), _P(c_int64), c_int64, _P(c_int64)]),
+    "mrlbm_batch_stats": (c_int32, [c_void_p, c_int32, _P(Stats)]),
+    "mrlbm_batch_total_updates": (c_int32, [c_void_p, _P(c_int64)]),
+    "mrlbm_batch_set_block": (c_int32, [c_void_p, c_int32]),
+    "mrlbm_batch_get_block": (c_int32, [c_void_p, _P(c_int32)]),
+    "mrlbm_batch_destroy": (None, [c_void_p]),
+    "mrlbm_batch_last_error": (ctypes.c_char_p, [c_void_p]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmrlbm.so from the package directory; raise if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(c_double))
+
+
+def make_params(p):
+    """Params struct from a dict with keys scheme, physics, bc, precision, lam, s, phys,
+    x_min, x_max, jmin, jmax, gamma, mu_bar, eps (the workload dictionaries)."""
+    s = list(np.atleast_1d(np.asarray(p.get("s", [1.0]), dtype=np.float64)))
+    phys = list(p.get("phys", [0.0, 1.0, 1.4, 0.9])) + [0.0] * 4
+    P = Params()
+    P.abi_version = p.get("abi_version", ABI_VERSION)
+    P.scheme = p["scheme"]
+    P.physics = p["physics"]
+    P.bc = p.get("bc", PERIODIC)
+    P.precision = p.get("precision", FP64)
+    P.n_s = len(s)
+    P.lam = p["lam"]
+    for i, v in enumerate(s[:8]):
+        P.s[i] = v
+    for i in range(4):
+        P.phys[i] = phys[i]
+    P.x_min = p.get("x_min", -1.0)
+    P.x_max = p.get("x_max", 1.0)
+    P.j_min = p["jmin"]
+    P.j_max = p["jmax"]
+    P.gamma = p.get("gamma", 1)
+    P.mu_bar = p.get("mu_bar", 0)
+    P.eps = p["eps"]
+    P.flags = p.get("flags", 0)
+    return P
+
+
+def validate(p):
+    P = p if isinstance(p, Params) else make_params(p)
+    return lib().mrlbm_validate(ctypes.byref(P))
+
+
+def _check(rc, msgfn):
+    if rc != OK:
+        raise MRLBMError(rc, msgfn())
+
+
+class MRLBM:
+    """One adaptive run on the GPU."""
+
+    def __init__(self, params, m_cons0, stream=None):
+        L = lib()
+        self.P = params if isinstance(params, Params) else make_params(params)
+        m = np.ascontiguousarray(m_cons0, dtype=np.float64)
+        h = ctypes.c_void_p()
+        rc = L.mrlbm_create(ctypes.byref(self.P), _dptr(m), stream, ctypes.byref(h))
+        _check(rc, lambda: L.mrlbm_last_error(None).decode())
+        self.h = h
+        st = self.stats()
+        self.q, self.qc, self.jmax = st["q"], st["q_cons"], st["j_max"]
+
+    def _err(self):
+        return lib().mrlbm_last_error(self.h).decode()
+
+    def adapt(self):
+        _check(lib().mrlbm_adapt(self.h), self._err)
+
+    def step(self, n=1):
+        _check(lib().mrlbm_step(self.h, int(n)), self._err)
+
+    def step_timed(self, n):
+        ms = c_double()
+        _check(lib().mrlbm_step_timed(self.h, int(n), ctypes.byref(ms)), self._err)
+        return ms.value
+
+    def moments(self, where=LEAVES):
+        n = c_int64()
+        rc = lib().mrlbm_moments(self.h, where, None, 0, ctypes.byref(n))
+        if rc not in (OK, ECAPACITY):
+            _check(rc, self._err)
+        out = np.empty(self.qc * max(n.value, 1))
+        _check(lib().mrlbm_moments(self.h, where, _dptr(out), out.size, ctypes.byref(n)), self._err)
+        return out[: self.qc * n.value].reshape(self.qc, n.value)
+
+    def populations(self):
+        n = c_int64()
+        rc = lib().mrlbm_populations(self.h, None, 0, ctypes.byref(n))
+        if rc not in (OK, ECAPACITY):
+            _check(rc, self._err)
+        out = np.empty(self.q * max(n.value, 1))
+        _check(lib().mrlbm_populations(self.h, _dptr(out), out.size, ctypes.byref(n)), self._err)
+        return out[: self.q * n.value].reshape(self.q, n.value)
+
+    def leaves(self):
+        n = c_int64()
+        rc = lib().mrlbm_leaves(self.h, None, None, 0, ctypes.byref(n))
+        if rc not in (OK, ECAPACITY):
+            _check(rc, self._err)
+        lv = np.empty(max(n.value, 1), dtype=np.int32)
+        ix = np.empty(max(n.value, 1), dtype=np.int64)
+        _check(lib().mrlbm_leaves(self.h, lv.ctypes.data_as(ctypes.POINTER(c_int32)),
+                                  ix.ctypes.data_as(ctypes.POINTER(c_int64)), lv.size, ctypes.byref(n)), self._err)
+        return lv[: n.value], ix[: n.value]
+
+    def stats(self):
+        s = Stats()
+        _check(lib().mrlbm_stats(self.h, ctypes.byref(s)), self._err)
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mrlbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent runs advanced by one launch per step call."""
+
+    def __init__(self, params_list, m_cons_list, stream=None):
+        L = lib()
+        n = len(params_list)
+        arr = (Params * n)()
+        for i, p in enumerate(params_list):
+            arr[i] = p if isinstance(p, Params) else make_params(p)
+        self._m = [np.ascontiguousarray(m, dtype=np.float64) for m in m_cons_list]
+        ptrs = (ctypes.POINTER(c_double) * n)(*[_dptr(m) for m in self._m])
+        h = ctypes.c_void_p()
+        rc = L.mrlbm_batch_create(arr, n, ptrs, stream, ctypes.byref(h))
+        _check(rc, lambda: L.mrlbm_batch_last_error(None).decode())
+        self.h = h
+        self.n = n
+        self._qc = []
+        for i in range(n):
+            self._qc.append(self.stats(i)["q_cons"])
+
+    def _err(self):
+        return lib().mrlbm_batch_last_error(self.h).decode()
+
+    def step(self, nsteps=1):
+        _check(lib().mrlbm_batch_step(self.h, int(nsteps)), self._err)
+
+    def step_timed(self, nsteps):
+        ms = c_double()
+        _check(lib().mrlbm_batch_step_timed(self.h, int(nsteps), ctypes.byref(ms)), self._err)
+        return ms.value
+
+    def moments(self, inst, where=LEAVES):
+        n = c_int64()
+        qc = self._qc[inst]
+        rc = lib().mrlbm_batch_moments(self.h, inst, where, None, 0, ctypes.byref(n))
+        if rc not in (OK, ECAPACITY):
+            _check(rc, self._err)
+        out = np.empty(qc * max(n.value, 1))
+        _check(lib().mrlbm_batch_moments(self.h, inst, where, _dptr(out), out.size, ctypes.byref(n)), self._err)
+        return out[: qc * n.value].reshape(qc, n.value)
+
+    def leaves(self, inst):
+        n = c_int64()
+        rc = lib().mrlbm_batch_leaves(self.h, inst, None, None, 0, ctypes.byref(n))
+        if rc not in (OK, ECAPACITY):
+            _check(rc, self._err)
+        lv = np.empty(max(n.value, 1), dtype=np.int32)
+        ix = np.empty(max(n.value, 1), dtype=np.int64)
+        _check(lib().mrlbm_batch_leaves(self.h, inst, lv.ctypes.data_as(ctypes.POINTER(c_int32)),
+                                        ix.ctypes.data_as(ctypes.POINTER(c_int64)), lv.size, ctypes.byref(n)),
+               self._err)
+        return lv[: n.value], ix[: n.value]
+
+    def stats(self, inst):
+        s = Stats()
+        _check(lib().mrlbm_batch_stats(self.h, inst, ctypes.byref(s)), self._err)
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def total_updates(self):
+        t = c_int64()
+        _check(lib().mrlbm_batch_total_updates(self.h, ctypes.byref(t)), self._err)
+        return t.value
+
+    def set_block(self, threads):
+        _check(lib().mrlbm_batch_set_block(self.h, int(threads)), self._err)
+
+    def get_block(self):
+        t = c_int32()
+        _check(lib().mrlbm_batch_get_block(self.h, ctypes.byref(t)), self._err)
+        return t.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mrlbm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
