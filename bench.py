@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Leaf-cell updates/s of the MR-LBM hot path on one MI355X.
+
+Workload (the D1Q3 Burgers family at full size): D1Q3 scheme with m2^eq = 0.9 lambda^2 u,
+lambda = 1, periodic [-1, 1], J_min = 2, J = 14 (16384 finest cells), gamma = 1,
+mu_bar = 0; the sweep s in {1.5, 1.9} x eps in {1e-2, 1e-3, 1e-4}, with ``--seeds``
+seeded initial data per pair (Riemann data + sine, see workloads.burgers). All runs
+advance together in the batched engine (one workgroup per run, one launch per call); a
+"step" is one time step of every run. T = 0.4 is 3277 steps: warmup + timed steps add up
+to that by default.
+
+Reported next to the throughput:
+* roofline of the step kernel: algorithmic bytes (2 q s_b + 8 per leaf-cell update: read
+  and write the populations once, a 4-byte leaf key read and written) per launch over the
+  launch time measured with HIP events on the library's stream; peak 8 TB/s HBM;
+* the plain adaptive step: the same kind of run advanced by one launch per time step
+  and run, for comparison;
+* the error check: delta = ||M_ref - m_hathat||_1 on the conserved moment against an
+  eps = 0 run of the same library (the uniform finest-grid scheme, bit for bit), as delta/eps;
+* the CPU baseline: the FP64 oracle (plain numpy, one thread) on a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+Q = 3  # D1Q3
+
+
+def b_alg(q, prec):
+    sb = 8 if prec == 0 else 4
+    return 2 * q * sb + 8
+
+
+def instances(seeds, prec):
+    out = []
+    for s in (1.5, 1.9):
+        for eps in (1e-2, 1e-3, 1e-4):
+            for seed in range(seeds):
+                p, mc = W.burgers(seed, jmax=14, eps=eps, s=s)
+                p["precision"] = prec
+                out.append((p, mc))
+    return out
+
+
+def delta_check(mrlbm, cases, nsteps):
+    """delta/eps of a few runs against the eps = 0 run (the uniform scheme)."""
+    worst = 0.0
+    rows = []
+    for p, mc in cases:
+        a = mrlbm.MRLBM(p, mc)
+        r = mrlbm.MRLBM(dict(p, eps=0.0), mc)
+        a.step(nsteps)
+        r.step(nsteps)
+        ma = a.moments(mrlbm.FINEST)
+        mr = r.moments(mrlbm.FINEST)
+        dx = (p["x_max"] - p["x_min"]) / ma.shape[1]
+        d = float(dx * np.sum(np.abs(ma[0] - mr[0])))
+        rows.append({"s": p["s"][0], "eps": p["eps"], "delta": d, "delta_over_eps": d / p["eps"],
+                     "leaves": a.stats()["leaves"]})
+        worst = max(worst, d / p["eps"])
+        a.close()
+        r.close()
+    return worst, rows
+
+
+def plain_step_rate(mrlbm, cases, nsteps):
+    """One launch per time step and run (the plain adaptive step), all runs on one stream."""
+    runs = [mrlbm.MRLBM(p, mc) for p, mc in cases]
+    for r in runs:
+        r.step(5)
+    for r in runs:
+        r.stats()
+    u0 = sum(r.stats()["leaf_updates"] for r in runs)
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        for r in runs:
+            r.step(1)
+    u1 = sum(r.stats()["leaf_updates"] for r in runs)  # stats synchronizes
+    dt = time.perf_counter() - t0
+    for r in runs:
+        r.close()
+    return (u1 - u0) / dt, dt
+
+
+def cpu_baseline(sample_steps):
+    """The FP64 oracle, as it stands, on one run of the workload (s = 1.9, eps = 1e-4)."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    from oracle.adaptive import AdaptiveMRLBM
+    from oracle.lattice import scheme_from_params
+    p, mc = W.burgers(0, jmax=14, eps=1e-4, s=1.9)
+    a = AdaptiveMRLBM(scheme_from_params(p), p["jmin"], p["jmax"], p["gamma"], p["eps"], p["mu_bar"],
+                      p["bc"], mc)
+    t0 = time.perf_counter()
+    a.step(sample_steps)
+    dt = time.perf_counter() - t0
+    return {"value": a.leaf_updates / dt, "unit": "leaf-cell updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one D1Q3 Burgers run (J=14, s=1.9, eps=1e-4, seed 0), first {sample_steps} steps, "
+                      f"{a.leaf_updates} leaf-cell updates in {dt:.2f} s, single-threaded numpy",
+            "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
+
+
+def copy_probe(nbytes):
+    """Plain device-to-device copy of known size, for scaling rocprofv3 FETCH/WRITE counters."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3227)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--seeds", type=int, default=8, help="seeded runs per (s, eps) pair")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: tuner)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=2500)
+    ap.add_argument("--no-extras", action="store_true", help="skip the plain-step and delta checks")
+    ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
+    args = ap.parse_args()
+
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the batched engine shards runs "
+              f"across GPUs by design but this build measures one MI355X", file=sys.stderr)
+        return 2
+
+    from paper_2102_12163_amd import mrlbm
+
+    prec = 0 if args.precision == "fp64" else 1
+    cases = instances(args.seeds, prec)
+    print(f"[bench] {len(cases)} runs, warmup {args.warmup}, timed {args.steps}", file=sys.stderr, flush=True)
+    batch = mrlbm.Batch([c[0] for c in cases], [c[1] for c in cases])
+    if args.block:
+        batch.set_block(args.block)
+    if args.warmup:
+        batch.step(args.warmup)
+    u0 = batch.total_updates()
+    ms = batch.step_timed(args.steps)
+    u1 = batch.total_updates()
+    upd = u1 - u0
+    value = upd / (ms / 1e3)
+    leaves_now = [batch.stats(i)["leaves"] for i in range(len(cases))]
+    block = batch.get_block()
+    batch.close()
+    print(f"[bench] timed region {ms:.1f} ms, {upd} leaf-cell updates", file=sys.stderr, flush=True)
+
+    bpu = b_alg(Q, prec)
+    achieved = upd * bpu / (ms / 1e3) / 1e9
+    result = {
+        "metric": "leaf-cell updates/s and % HBM roofline at error<=C*eps vs plain adaptive step",
+        "value": value,
+        "unit": "leaf-cell updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == 0 else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "D1Q3 Burgers, J_min=2 J=14 (16384 cells), gamma=1, periodic [-1,1], "
+                        "s in {1.5,1.9} x eps in {1e-2,1e-3,1e-4}, batched runs",
+            "runs": len(cases), "seeds_per_pair": args.seeds, "finest_cells": 16384,
+            "threads_per_workgroup": block, "form": "batched engine, one launch for all timed steps",
+            "mean_leaves_per_run": float(np.mean(leaves_now)),
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_steps<double,1,1>" if prec == 0 else "k_steps<float,1,1>",
+            "bytes_per_update": bpu,
+        },
+    }
+    if not args.no_extras:
+        one = [c for c in cases if c[0]["eps"] == 1e-4][:1] * 1
+        rate_plain, _ = plain_step_rate(mrlbm, one, 300)
+        rate_plain_all, _ = plain_step_rate(mrlbm, cases[:: max(1, len(cases) // 12)], 100)
+        result["plain_step"] = {
+            "one_run_updates_per_s": rate_plain,
+            "per_run_launches_updates_per_s": rate_plain_all,
+            "batched_speedup_vs_per_run_launches": value / rate_plain_all,
+        }
+        sample = [c for c in cases if c[0]["s"][0] == 1.9 and c[0]["eps"] in (1e-3, 1e-4)][:: args.seeds]
+        worst, rows = delta_check(mrlbm, sample, args.warmup + args.steps)
+        result["error_check"] = {"max_delta_over_eps": worst, "runs": rows,
+                                 "reference": "eps=0 run of the same library (uniform finest scheme)"}
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(args.cpu_sample_steps)
+    print(json.dumps(result))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
