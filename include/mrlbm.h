@@ -92,6 +92,7 @@ typedef struct {
     int32_t q;            /* populations per cell                                         */
     int32_t q_cons;       /* conserved moments per cell                                   */
     int32_t j_max;
+    int64_t tree_cells;   /* #R(Lambda): cells of the complete tree (leaves + split cells) */
 } mrlbm_stats_t;
 
 typedef struct mrlbm_s* mrlbm_t;
@@ -163,6 +164,12 @@ int mrlbm_batch_total_updates(mrlbm_batch_t b, int64_t* total);
  * let the built-in tuner choose. Takes effect at the next step call. */
 int mrlbm_batch_set_block(mrlbm_batch_t b, int32_t threads);
 int mrlbm_batch_get_block(mrlbm_batch_t b, int32_t* threads);
+/* On-chip capacity: a run keeps the values of its tree in the workgroup's LDS while the tree
+ * has at most this many cells of R(Lambda), and in its HBM arrays otherwise (same results).
+ * cells = -1: the largest capacity the device's LDS allows (default); 0: always HBM.
+ * get_capacity returns the capacity in use. */
+int mrlbm_batch_set_capacity(mrlbm_batch_t b, int32_t cells);
+int mrlbm_batch_get_capacity(mrlbm_batch_t b, int32_t* cells);
 void mrlbm_batch_destroy(mrlbm_batch_t b);
 const char* mrlbm_batch_last_error(mrlbm_batch_t b);
 

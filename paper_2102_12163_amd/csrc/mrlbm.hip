@@ -37,7 +37,11 @@ struct Engine {
     size_t stage_elems = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    size_t lds = 0;
+    size_t lds = 0;        // dynamic LDS of the step kernel (bytes)
+    size_t lds_query = 0;  // dynamic LDS of the query kernel
+    int cap = 0, capS = 0; // on-chip capacity in R(Lambda) cells and in leaves
+    size_t lds_budget = 0; // LDS bytes one workgroup may use
+    int cap_user = -1;     // user limit on the on-chip capacity (-1: none)
     int maxJ = 0;
     int nt = 0;          // threads per workgroup in use
     int nt_user = 0;     // 0: tuner choice
@@ -45,7 +49,7 @@ struct Engine {
     std::string err;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    int gsteps = -1, gnt = -1;
+    int gsteps = -1, gnt = -1, gcap = -1;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -155,14 +159,39 @@ void pred_coeffs(int gamma, double* c) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t lds_bytes_for(int jmin, int J) {
-    const size_t wt = (size_t)wbase(jmin, J + 1);
-    const size_t nwJ = (size_t)nwords(J);
-    return 4 * wt * 8 + nwJ * 8 + nwJ * 4 + 64;
+// Largest on-chip capacity (cells of R(Lambda)) whose LDS layout fits the budget for every
+// run of the batch; never more than the full tree of the largest run.
+void choose_capacity(Engine* e) {
+    int cg_max = 0;
+    for (auto& d : e->hd) cg_max = std::max(cg_max, (1 << (d.jmax + 1)) - (1 << d.jmin));
+    const int tsz = e->prec == MRLBM_FP64 ? 8 : 4;
+    auto total = [&](int cap) {
+        size_t t = 0;
+        for (auto& d : e->hd) {
+            const int capS = cap > 0 ? cap / 2 + (1 << d.jmin) : 0;
+            t = std::max(t, (size_t)make_layout(d.jmin, d.jmax, cap, capS, d.q, d.nm, tsz).total);
+        }
+        return t;
+    };
+    int lo = 0, hi = cg_max;
+    if (e->cap_user >= 0) hi = std::min(hi, e->cap_user);
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (total(mid) <= e->lds_budget) lo = mid;
+        else hi = mid - 1;
+    }
+    e->cap = lo;
+    int jmin_min = 30;
+    for (auto& d : e->hd) jmin_min = std::min(jmin_min, d.jmin);
+    e->capS = lo > 0 ? lo / 2 + (1 << jmin_min) : 0;
+    e->lds = total(lo);
+    size_t q = 0;
+    for (auto& d : e->hd) q = std::max(q, (size_t)make_layout(d.jmin, d.jmax, 0, 0, d.q, d.nm, tsz).total);
+    e->lds_query = q;
 }
 
 // ---------------------------------------------------------------- kernel dispatch
-typedef void (*StepK)(const Desc*, State*, int, int);
+typedef void (*StepK)(const Desc*, State*, int, int, int, int);
 typedef void (*QueryK)(const Desc*, State*, int, int, double*);
 typedef void (*InitK)(const Desc*, State*, const double*, long long);
 
@@ -291,7 +320,6 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
         maxNJ = std::max(maxNJ, NJ);
         maxq = std::max(maxq, (size_t)si.q);
         e->maxJ = std::max(e->maxJ, p.j_max);
-        e->lds = std::max(e->lds, lds_bytes_for(p.j_min, p.j_max));
         Desc& d = e->hd[i];
         memset(&d, 0, sizeof(d));
         d.jmin = p.j_min;
@@ -366,8 +394,14 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
     st = hipStreamSynchronize(e->stream);
     (void)hipFree(dm);
     if (st != hipSuccess) return fail(st, "init");
+    int dev = 0, maxlds = 65536;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    // static LDS of the kernels (word bases, counters) is below 1 KB
+    e->lds_budget = (size_t)std::max(0, maxlds - 1024);
+    choose_capacity(e);
     (void)hipFuncSetAttribute((const void*)sk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)e->lds);
-    (void)hipFuncSetAttribute((const void*)qk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)e->lds);
+    (void)hipFuncSetAttribute((const void*)qk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)e->lds_query);
     e->nt = default_block(e->maxJ);
     *out = e;
     return MRLBM_OK;
@@ -384,25 +418,28 @@ int launch_steps(Engine* e, int nsteps, int mode, bool use_graph) {
     const int nt = e->nt_user ? e->nt_user : e->nt;
     hipError_t st;
     if (use_graph && mode == (MODE_ADAPT | MODE_SCHEME)) {
-        if (!e->gexec || e->gsteps != nsteps || e->gnt != nt) {
+        if (!e->gexec || e->gsteps != nsteps || e->gnt != nt || e->gcap != e->cap) {
             if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
             if (e->graph) (void)hipGraphDestroy(e->graph);
             e->gexec = nullptr;
             e->graph = nullptr;
             if ((st = hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
                 return hip_fail(e, st, "hipStreamBeginCapture");
-            hipLaunchKernelGGL(sk, dim3(e->n), dim3(nt), e->lds, e->stream, (const Desc*)e->dd, e->ds, nsteps, mode);
+            hipLaunchKernelGGL(sk, dim3(e->n), dim3(nt), e->lds, e->stream, (const Desc*)e->dd, e->ds, nsteps, mode,
+                               e->cap, e->capS);
             st = hipStreamEndCapture(e->stream, &e->graph);
             if (st != hipSuccess) return hip_fail(e, st, "hipStreamEndCapture");
             if ((st = hipGraphInstantiate(&e->gexec, e->graph, nullptr, nullptr, 0)) != hipSuccess)
                 return hip_fail(e, st, "hipGraphInstantiate");
             e->gsteps = nsteps;
             e->gnt = nt;
+            e->gcap = e->cap;
         }
         if ((st = hipGraphLaunch(e->gexec, e->stream)) != hipSuccess) return hip_fail(e, st, "hipGraphLaunch");
         return MRLBM_OK;
     }
-    hipLaunchKernelGGL(sk, dim3(e->n), dim3(nt), e->lds, e->stream, (const Desc*)e->dd, e->ds, nsteps, mode);
+    hipLaunchKernelGGL(sk, dim3(e->n), dim3(nt), e->lds, e->stream, (const Desc*)e->dd, e->ds, nsteps, mode, e->cap,
+                       e->capS);
     st = hipGetLastError();
     if (st != hipSuccess) return hip_fail(e, st, "step launch");
     return MRLBM_OK;
@@ -424,8 +461,8 @@ int run_query(Engine* e, int inst, int where, int what, int64_t* n_out) {
     InitK ik;
     kernels_for(e->prec, e->scheme, e->gamma, &sk, &qk, &ik);
     const int nt = e->nt_user ? e->nt_user : e->nt;
-    hipLaunchKernelGGL(qk, dim3(1), dim3(nt), e->lds, e->stream, (const Desc*)(e->dd + inst), e->ds + inst, where,
-                       what, e->stage);
+    hipLaunchKernelGGL(qk, dim3(1), dim3(nt), e->lds_query, e->stream, (const Desc*)(e->dd + inst), e->ds + inst,
+                       where, what, e->stage);
     hipError_t st = hipGetLastError();
     if (st != hipSuccess) return hip_fail(e, st, "query launch");
     State s;
@@ -497,6 +534,7 @@ int engine_stats(Engine* e, int inst, mrlbm_stats_t* st) {
     st->q = e->hd[inst].q;
     st->q_cons = e->hd[inst].qc;
     st->j_max = e->hd[inst].jmax;
+    st->tree_cells = s.n_r;
     return MRLBM_OK;
 }
 
@@ -660,6 +698,19 @@ int mrlbm_batch_set_block(mrlbm_batch_t b, int32_t threads) {
         return MRLBM_EINVAL;
     }
     b->e->nt_user = threads;
+    return MRLBM_OK;
+}
+
+int mrlbm_batch_set_capacity(mrlbm_batch_t b, int32_t cells) {
+    if (!b || cells < -1) return MRLBM_EINVAL;
+    b->e->cap_user = cells;
+    choose_capacity(b->e);
+    return MRLBM_OK;
+}
+
+int mrlbm_batch_get_capacity(mrlbm_batch_t b, int32_t* cells) {
+    if (!b || !cells) return MRLBM_EINVAL;
+    *cells = b->e->cap;
     return MRLBM_OK;
 }
 

@@ -1,13 +1,13 @@
 // mrlbm_device.h -- device-side building blocks of the MR-LBM step for CDNA4 (gfx950).
 //
-// Data layout of one run (all in HBM, owned by the host library):
-//   values   two buffers (A, B) of q * (2^(J+1) - 2^Jmin) elements of type T; level l
-//            starts at q * (2^l - 2^Jmin) and holds q planes of 2^l cells (level-major SoA).
-//            Only cells of the complete tree R(Lambda) carry meaningful values.
+// Data layout of one run (home copy in HBM, owned by the host library):
+//   values   two compact arrays of q planes x (2^(J+1) - 2^Jmin) slots of type T; the
+//            cells of R(Lambda) occupy slots 0..#R-1, level by level (see rank_of).
 //   split    one bit per cell of levels Jmin..J-1, "cell (l, p) has children"; 64-bit words,
-//            levels below 64 cells use one partial word. Loaded into LDS for a launch.
+//            levels below 64 cells use one partial word.
 //   list     complete leaves of the current tree in spatial order, key (l << 27) | k.
-//   pairs    reconstructed finest values on both sides of every leaf interface.
+//   pairs    reconstructed finest values on both sides of every leaf interface (used when
+//            a run does not fit the workgroup's LDS).
 //
 // Inside a workgroup the tree lives in LDS as bit words; wavefront lane i owns bit i of a
 // word, so a wave processes 64 cells of one level per iteration and __ballot turns 64
@@ -46,7 +46,10 @@ struct Desc {
 
 struct State {
     long long steps, leaf_updates, n_leaves;
-    int cur, flags;
+    int cur;    // which HBM value array holds the home copy
+    int flags;  // bit 0: NaN met
+    int n_r;    // #R(Lambda) of the current tree
+    int pad;
 };
 
 #define DEV __device__ __forceinline__
@@ -138,15 +141,6 @@ DEV uint64_t dilate_word(const uint64_t* A, int wbl, int l, int w, int r, int bc
     }
     return d;
 }
-
-// ------------------------------------------------------------------ values
-template <typename T>
-struct Vals {
-    T* base;
-    int jmin, q;
-    DEV T* lev(int l) const { return base + (size_t)q * ((1 << l) - (1 << jmin)); }
-    DEV T& at(int l, int h, int k) const { return lev(l)[h * (1 << l) + k]; }
-};
 
 // ------------------------------------------------------------------ schemes
 // Population order: D1Q2 (+lambda, -lambda); D1Q3 (0, +lambda, -lambda); D1Q2^k blocks
@@ -296,50 +290,68 @@ DEV void conserved(const Coef& c, const T* f, double* mc) {
     }
 }
 
+// ------------------------------------------------------------------ compact storage
+// Values of one tree are stored compactly: the cells of R(Lambda) are numbered level by
+// level and, inside a level, by index (their "slot"); population h of slot s lives at
+// p[h * stride + s]. R holds the R(Lambda) bits per 64-bit word and RP the number of
+// R(Lambda) cells in all words before a word, so slot(l, k) = RP[w] + popcount of the R
+// bits below k in its word w.
+DEV int rank_of(const uint64_t* R, const uint32_t* RP, const int* wb, int l, int k) {
+    const int w = wb[l] + (k >> 6);
+    return (int)RP[w] + __popcll(R[w] & ((1ull << (k & 63)) - 1ull));
+}
+DEV bool rbit(const uint64_t* R, const int* wb, int l, int k) { return (R[wb[l] + (k >> 6)] >> (k & 63)) & 1ull; }
+
+template <typename T, typename P>
+struct VP {
+    P* p;
+    int stride;
+    DEV T ld(int h, int s) const { return (T)p[h * stride + s]; }
+    DEV void st(int h, int s, T v) const { p[h * stride + s] = v; }
+};
+
 // ------------------------------------------------------------------ reconstruction
-// Reconstructed finest values f-double-hat at the two finest cells e-1 and e (Sec. 3.3,
-// reconstruction operator): starting at the finest level, a window of cells is followed
+// Reconstructed values f-double-hat at cells tA and tB (tB = tA or tA + 1) of level L
+// (Sec. 3.3, reconstruction operator): starting at level L, a window of cells is followed
 // towards coarser levels until every cell of the window lies in R(Lambda); then, level by
-// level back to J, every window cell outside R(Lambda) is predicted from the parent level's
+// level back to L, every window cell outside R(Lambda) is predicted from the parent level's
 // window (Sec. 3.1) and every cell inside R(Lambda) takes its stored value. With unwrapped
-// indices the level-l window is [((tA + 2G) >> (J - l)) - 2G, ((tB - 2G) >> (J - l)) + 2G], so
-// a window position's parent position depends only on the parity of (tA + 2G) >> (J - l):
+// indices the level-l window is [((tA + 2G) >> (L - l)) - 2G, ((tB - 2G) >> (L - l)) + 2G], so
+// a window position's parent position depends only on the parity of (tA + 2G) >> (L - l):
 // the whole window stays in registers. Out-of-range cells under clamp copy the edge cell.
-template <typename T, int G, int NP, class PM>
-DEV void pair_chain(const Vals<T>& V, const uint64_t* split, const int* wb, int jmin, int J, int bc,
-                    const T* cc, int e, T* outA, T* outB) {
+// Under clamp the targets must already be in range.
+template <typename T, int G, int NP, class PM, class V>
+DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, const int* wb, int jmin, int L, int bc,
+               const T* cc, int tA, int tB, T* outA, T* outB) {
     constexpr int WM = 4 * G + 1;
-    const int NJ = 1 << J;
-    int tA = e - 1, tB = e;
-    if (bc == CLAMP) {
-        tA = tA < 0 ? 0 : (tA > NJ - 1 ? NJ - 1 : tA);
-        tB = tB < 0 ? 0 : (tB > NJ - 1 ? NJ - 1 : tB);
-    }
-    int l0 = J;
+    int l0 = L;
     while (l0 > jmin) {
-        const int sh = J - l0;
+        const int sh = L - l0;
         const int lo = ((tA + 2 * G) >> sh) - 2 * G;
         const int hi = ((tB - 2 * G) >> sh) + 2 * G;
         const int N = 1 << l0;
         bool all = true;
-        for (int x = lo; x <= hi && all; ++x) all = in_r(split, wb, jmin, l0, bcx(x, N, bc));
+        for (int x = lo; x <= hi && all; ++x) all = rbit(R, wb, l0, bcx(x, N, bc));
         if (all) break;
         --l0;
     }
     T win[NP][WM];
     {
-        const int sh = J - l0;
+        const int sh = L - l0;
         const int lo = ((tA + 2 * G) >> sh) - 2 * G;
+        const int hi = ((tB - 2 * G) >> sh) + 2 * G;
         const int N = 1 << l0;
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
             const int xx = bcx(lo + i, N, bc);
+            const bool ok = (i <= hi - lo) && rbit(R, wb, l0, xx);
+            const int s = ok ? rank_of(R, RP, wb, l0, xx) : 0;
 #pragma unroll
-            for (int m = 0; m < NP; ++m) win[m][i] = V.at(l0, PM::h(m), xx);
+            for (int m = 0; m < NP; ++m) win[m][i] = ok ? Vx.ld(PM::h(m), s) : (T)0;
         }
     }
-    for (int l = l0 + 1; l <= J; ++l) {
-        const int sh = J - l;
+    for (int l = l0 + 1; l <= L; ++l) {
+        const int sh = L - l;
         const int u = (tA + 2 * G) >> sh;
         const int lo = u - 2 * G;
         const int hi = ((tB - 2 * G) >> sh) + 2 * G;
@@ -351,12 +363,13 @@ DEV void pair_chain(const Vals<T>& V, const uint64_t* split, const int* wb, int 
             const int x = lo + i;
             const int xx = bcx(x, N, bc);
             const bool odd = ((i + (par ? 1 : 0)) & 1) != 0;
-            const bool inr = (i <= hi - lo) && in_r(split, wb, jmin, l, xx);
+            const bool inr = (i <= hi - lo) && rbit(R, wb, l, xx);
             if (inr) {
+                const int s = rank_of(R, RP, wb, l, xx);
 #pragma unroll
-                for (int m = 0; m < NP; ++m) nw[m][i] = V.at(l, PM::h(m), xx);
+                for (int m = 0; m < NP; ++m) nw[m][i] = Vx.ld(PM::h(m), s);
             } else {
-                constexpr int pa = G;  // parent position of i when the parity is even: G + i/2
+                constexpr int pa = G;  // parent position of i for even parity: G + i/2
 #pragma unroll
                 for (int m = 0; m < NP; ++m) {
                     const T f0 = par ? win[m][pa + ((i + 1) >> 1)] : win[m][pa + (i >> 1)];

@@ -1,9 +1,15 @@
 // mrlbm_kernels.h -- the per-run workgroup engine: every phase of an MR-LBM time step as a
 // block-cooperative function, and the kernels built from them.
 //
-// One workgroup advances one run (one instance of a batch); phases are separated by
-// workgroup barriers only, so a launch of K steps for B runs is a single grid of B
-// workgroups with no inter-workgroup synchronization.
+// One workgroup advances one run (one instance of a batch) through all the steps of a
+// launch; phases are separated by workgroup barriers only, so a launch of K steps for B
+// runs is a single grid of B workgroups with no inter-workgroup synchronization.
+//
+// During a launch the run lives on chip: the tree as bit words in LDS, the values of R(Lambda)
+// compactly in LDS (slots, see rank_of) as long as the tree fits the LDS capacity chosen by
+// the host. A step whose tree does not fit keeps its values in the run's HBM arrays instead
+// (same compact layout, generic pointers); the next step moves back on chip when it fits.
+// The home copy in HBM is read at launch start and written at launch end.
 #pragma once
 
 #include "mrlbm_device.h"
@@ -12,25 +18,83 @@ namespace mrl {
 
 enum : int { MODE_ADAPT = 1, MODE_SCHEME = 2 };
 
+template <typename T> struct LdsT;
+template <> struct LdsT<double> { typedef __attribute__((address_space(3))) double type; };
+template <> struct LdsT<float> { typedef __attribute__((address_space(3))) float type; };
+
+// Byte offsets of the dynamic LDS of one workgroup.
+struct Layout {
+    int wt, nwJ, cap, capS;
+    unsigned bits, E, VA, VB, PP, rp, scanE, LL, wl, total;
+};
+__host__ __device__ inline unsigned al16(unsigned x) { return (x + 15u) & ~15u; }
+__host__ __device__ inline Layout make_layout(int jmin, int J, int cap, int capS, int q, int nm, int tsz) {
+    Layout L;
+    L.wt = wbase(jmin, J + 1);
+    L.nwJ = nwords(J);
+    L.cap = cap;
+    L.capS = capS;
+    unsigned o = 0;
+    L.bits = o;
+    o = al16(o + 5u * (unsigned)L.wt * 8u);
+    L.E = o;
+    o = al16(o + (unsigned)L.nwJ * 8u);
+    L.VA = o;
+    o = al16(o + (unsigned)q * (unsigned)cap * (unsigned)tsz);
+    L.VB = o;
+    o = al16(o + (unsigned)q * (unsigned)cap * (unsigned)tsz);
+    L.PP = o;
+    o = al16(o + 2u * (unsigned)nm * (unsigned)(capS > 0 ? capS + 1 : 0) * (unsigned)tsz);
+    L.rp = o;
+    o = al16(o + 2u * (unsigned)(L.wt + 1) * 4u);
+    L.scanE = o;
+    o = al16(o + (unsigned)L.nwJ * 4u);
+    L.LL = o;
+    o = al16(o + (unsigned)capS * 4u);
+    L.wl = o;
+    o = al16(o + 3u * (unsigned)L.wt * 2u);
+    L.total = o;
+    return L;
+}
+
+// Per-level word lists: the words of level l that carry set bits are
+// list[wb[l] .. wb[l] + count[l]) (any order inside a level).
+struct WordList {
+    uint16_t* w;
+    int* c;
+};
+
 template <typename T, int S, int G>
 struct Block {
     static constexpr int Q = Sch<S>::Q;
     static constexpr int NM = Sch<S>::NM;
+    typedef typename LdsT<T>::type LT;
 
     const Desc& d;
     int tid, NT, lane, wave, nwaves;
-    int jmin, J, bc;
-    int* wb;             // word base per level (LDS)
-    uint64_t* split;     // current tree bits, levels jmin..J (LDS)
-    uint64_t* nsplit;    // next tree bits
-    uint64_t* keep;      // T_eps result
-    uint64_t* ruleb;     // enlargement rule (b) hits
-    uint64_t* E;         // finest-level leaf left edges
-    uint32_t* scan;      // exclusive prefix of E popcounts
-    uint32_t* red;       // small reduction scratch (one per wave + extras)
+    int jmin, J, bc, wt;
+    Layout lay;
+    int* wb;          // word base per level, wb[J + 1] = wt (LDS)
+    uint32_t* red;    // small scratch: [0] leaf count, [1..16] wave partials
+    // tree arrays, rotated at the end of each step
+    uint64_t* split;  // Lambda^n split bits
+    uint64_t* nsplit; // Lambda^{n+1} split bits
+    uint64_t* keep;   // T_eps bits; then R bits of Lambda^{n+1}
+    uint64_t* ruleb;  // rule (b) bits; then leaf bits of Lambda^{n+1}
+    uint64_t* ro;     // R bits of Lambda^n
+    uint32_t* rpo;    // slot prefix of Lambda^n
+    uint32_t* rpn;    // slot prefix of Lambda^{n+1}
+    WordList swl, nswl, lwl;  // split words of Lambda^n, of Lambda^{n+1}; leaf words of Lambda^{n+1}
+    uint64_t* E;      // finest-level leaf left edges
+    uint32_t* scanE;  // exclusive prefix of popcount(E)
+    LT* ldsA;         // on-chip value arrays (capacity lay.cap slots each)
+    LT* ldsB;
+    LT* ldsP;         // on-chip interface pairs
+    uint32_t* ldsL;   // on-chip leaf list
     T cc[3];
 
-    DEV Block(const Desc& dd, int* wb_, uint64_t* lds, uint32_t* red_) : d(dd), wb(wb_), red(red_) {
+    DEV Block(const Desc& dd, const Layout& L, uint8_t* lds, int* wb_, uint32_t* red_, int* cnts)
+        : d(dd), lay(L), wb(wb_), red(red_) {
         tid = threadIdx.x;
         NT = blockDim.x;
         lane = tid & 63;
@@ -39,33 +103,123 @@ struct Block {
         jmin = d.jmin;
         J = d.jmax;
         bc = d.bc;
-        const int wt = wbase(jmin, J + 1);
-        split = lds;
-        nsplit = split + wt;
-        keep = nsplit + wt;
-        ruleb = keep + wt;
-        E = ruleb + wt;
-        const int nwJ = nwords(J);
-        scan = reinterpret_cast<uint32_t*>(E + nwJ);
+        wt = L.wt;
+        uint64_t* bits = reinterpret_cast<uint64_t*>(lds + L.bits);
+        split = bits;
+        nsplit = bits + wt;
+        keep = bits + 2 * wt;
+        ruleb = bits + 3 * wt;
+        ro = bits + 4 * wt;
+        E = reinterpret_cast<uint64_t*>(lds + L.E);
+        uint32_t* rp = reinterpret_cast<uint32_t*>(lds + L.rp);
+        rpo = rp;
+        rpn = rp + wt + 1;
+        scanE = reinterpret_cast<uint32_t*>(lds + L.scanE);
+        uint16_t* wl = reinterpret_cast<uint16_t*>(lds + L.wl);
+        swl = {wl, cnts};
+        nswl = {wl + wt, cnts + 32};
+        lwl = {wl + 2 * wt, cnts + 64};
+        ldsA = (LT*)(T*)(lds + L.VA);
+        ldsB = (LT*)(T*)(lds + L.VB);
+        ldsP = (LT*)(T*)(lds + L.PP);
+        ldsL = reinterpret_cast<uint32_t*>(lds + L.LL);
         for (int a = 0; a < 3; ++a) cc[a] = (T)d.c[a];
     }
 
-    DEV int wtot() const { return wbase(jmin, J + 1); }
+    // ----------------------------------------------------------- block scan
+    // Exclusive prefix of per-thread values; returns this thread's base, total in *tot.
+    DEV uint32_t block_scan(uint32_t s, uint32_t* tot) {
+        uint32_t x = s;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) red[1 + wave] = x;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t run = 0;
+            for (int wv = 0; wv < nwaves; ++wv) {
+                const uint32_t v = red[1 + wv];
+                red[1 + wv] = run;
+                run += v;
+            }
+            red[20] = run;
+        }
+        __syncthreads();
+        *tot = red[20];
+        return red[1 + wave] + x - s;
+    }
+
+    // ----------------------------------------------------------- tree structures
+    // From split bits sp: R bits (R), slot prefix (RP, RP[wt] = #R), the list of nonzero
+    // split words (sl) and, when LW is given, leaf bits LW = R & ~split, their word list and
+    // the leaf count in red[0]. Ends with a barrier.
+    DEV void build_tree(const uint64_t* sp, uint64_t* R, uint32_t* RP, WordList sl, uint64_t* LW, WordList ll) {
+        if (tid < 32) {
+            sl.c[tid] = 0;
+            if (LW) ll.c[tid] = 0;
+        }
+        if (tid == 0 && LW) red[0] = 0;
+        __syncthreads();
+        const int per = (wt + NT - 1) / NT;
+        const int w0 = tid * per;
+        uint32_t s = 0;
+        uint32_t nleaf = 0;
+        int l = jmin;
+        for (int i = 0; i < per; ++i) {
+            const int w = w0 + i;
+            if (w >= wt) break;
+            while (w >= wb[l + 1]) ++l;
+            const int lw = w - wb[l];
+            const uint64_t r = r_word(sp, wb, jmin, l, lw);
+            R[w] = r;
+            s += (uint32_t)__popcll(r);
+            const uint64_t spw = (l < J) ? sp[w] : 0ull;
+            if (spw) {
+                const int pos = atomicAdd(&sl.c[l], 1);
+                sl.w[wb[l] + pos] = (uint16_t)lw;
+            }
+            if (LW) {
+                const uint64_t lf = r & ~spw;
+                LW[w] = lf;
+                if (lf) {
+                    nleaf += (uint32_t)__popcll(lf);
+                    const int pos = atomicAdd(&ll.c[l], 1);
+                    ll.w[wb[l] + pos] = (uint16_t)lw;
+                }
+            }
+        }
+        if (LW && nleaf) atomicAdd(&red[0], nleaf);
+        uint32_t tot;
+        uint32_t base = block_scan(s, &tot);
+        for (int i = 0; i < per; ++i) {
+            const int w = w0 + i;
+            if (w >= wt) break;
+            RP[w] = base;
+            base += (uint32_t)__popcll(R[w]);
+        }
+        if (tid == 0) RP[wt] = tot;
+        __syncthreads();
+    }
 
     // ----------------------------------------------------------- A1 / B2: projection
-    // Every split cell takes half the sum of its two children, finest level first
-    // (Sec. 3.1, Definition Projection operator).
-    DEV void project_up(const Vals<T>& V) {
+    // Every split cell takes half the sum of its two children (adjacent slots), finest
+    // level first (Sec. 3.1, Definition Projection operator).
+    template <class V>
+    DEV void project_up(const V& Vx, const uint64_t* sp, const uint64_t* R, const uint32_t* RP, WordList sl) {
         for (int l = J - 1; l >= jmin; --l) {
-            const int nw = nwords(l);
-            for (int w = wave; w < nw; w += nwaves) {
-                const uint64_t bits = split[wb[l] + w];
-                if (!bits) continue;
-                if ((bits >> lane) & 1ull) {
+            const int n = sl.c[l];
+            if (n == 0) continue;
+            for (int t = wave; t < n; t += nwaves) {
+                const int w = sl.w[wb[l] + t];
+                const uint64_t b = sp[wb[l] + w];
+                if ((b >> lane) & 1ull) {
                     const int p = (w << 6) + lane;
+                    const int sc = rank_of(R, RP, wb, l + 1, 2 * p);
+                    const int sp_ = rank_of(R, RP, wb, l, p);
 #pragma unroll
-                    for (int h = 0; h < Q; ++h)
-                        V.at(l, h, p) = (T)0.5 * (V.at(l + 1, h, 2 * p) + V.at(l + 1, h, 2 * p + 1));
+                    for (int h = 0; h < Q; ++h) Vx.st(h, sp_, (T)0.5 * (Vx.ld(h, sc) + Vx.ld(h, sc + 1)));
                 }
             }
             __syncthreads();
@@ -75,62 +229,68 @@ struct Block {
     // ----------------------------------------------------------- A2-A4(b): details
     // For every split cell (l, p): d^h = f_{l+1,2p} - (f_{l,p} + sum_a c_a (f_{l,p+a} - f_{l,p-a}))
     // in double (Sec. 3.1-3.2), D = max_h |d^h|; keep iff D >= eps_{l+1} (Sec. 3.4, T_eps);
-    // rule (b) iff kept, l+1 < J and D >= 2^(mu+1) eps_{l+1} (Sec. 4.2). One wave per word;
-    // the 64 lane decisions become the keep / ruleb words through __ballot.
-    DEV void details(const Vals<T>& V, int* nanflag) {
+    // rule (b) iff kept, l+1 < J and D >= 2^(mu+1) eps_{l+1} (Sec. 4.2). One wave per split
+    // word; __ballot turns the 64 lane decisions into the keep / ruleb words. keep and ruleb
+    // must be zero beforehand (only words with split cells are written).
+    template <class V>
+    DEV void details(const V& Vx, int* nanflag) {
         int t = wave;
         for (int l = jmin; l < J; ++l) {
-            const int nw = nwords(l);
+            const int n = swl.c[l];
             const int N = 1 << l;
             const double thr = ldexp(d.eps, l + 1 - J);
             const double thrb = ldexp(d.eps, d.mu_bar + 1 + l + 1 - J);
             const bool rb_level = (l + 1 < J);
-            for (; t < nw; t += nwaves) {
-                const uint64_t bits = split[wb[l] + t];
-                uint64_t kw = 0, rw = 0;
-                if (bits) {
-                    bool kb = false, rbb = false;
-                    if ((bits >> lane) & 1ull) {
-                        const int p = (t << 6) + lane;
-                        double D = 0.0;
-                        bool bad = false;
+            for (; t < n; t += nwaves) {
+                const int w = swl.w[wb[l] + t];
+                const uint64_t b = split[wb[l] + w];
+                bool kb = false, rbb = false;
+                if ((b >> lane) & 1ull) {
+                    const int p = (w << 6) + lane;
+                    const int sc = rank_of(ro, rpo, wb, l + 1, 2 * p);
+                    const int s0 = rank_of(ro, rpo, wb, l, p);
+                    int sp_[G], sm_[G];
 #pragma unroll
-                        for (int h = 0; h < Q; ++h) {
-                            const double f0 = (double)V.at(l, h, p);
-                            double acc = 0.0;
-#pragma unroll
-                            for (int a = 1; a <= G; ++a) {
-                                const double fp = (double)V.at(l, h, bcx(p + a, N, bc));
-                                const double fm = (double)V.at(l, h, bcx(p - a, N, bc));
-                                const double tt = d.c[a - 1] * (fp - fm);
-                                acc = (a == 1) ? tt : acc + tt;
-                            }
-                            const double pred = f0 + acc;
-                            const double dd = (double)V.at(l + 1, h, 2 * p) - pred;
-                            const double ad = fabs(dd);
-                            bad = bad || (ad != ad);
-                            D = ad > D ? ad : D;
-                        }
-                        if (bad) *nanflag = 1;
-                        kb = bad || (D >= thr);
-                        rbb = kb && rb_level && (bad || D >= thrb);
+                    for (int a = 1; a <= G; ++a) {
+                        sp_[a - 1] = rank_of(ro, rpo, wb, l, bcx(p + a, N, bc));
+                        sm_[a - 1] = rank_of(ro, rpo, wb, l, bcx(p - a, N, bc));
                     }
-                    kw = __ballot(kb);
-                    rw = __ballot(rbb);
+                    double D = 0.0;
+                    bool bad = false;
+#pragma unroll
+                    for (int h = 0; h < Q; ++h) {
+                        const double f0 = (double)Vx.ld(h, s0);
+                        double acc = 0.0;
+#pragma unroll
+                        for (int a = 1; a <= G; ++a) {
+                            const double tt = d.c[a - 1] * ((double)Vx.ld(h, sp_[a - 1]) - (double)Vx.ld(h, sm_[a - 1]));
+                            acc = (a == 1) ? tt : acc + tt;
+                        }
+                        const double pred = f0 + acc;
+                        const double dd = (double)Vx.ld(h, sc) - pred;
+                        const double ad = fabs(dd);
+                        bad = bad || (ad != ad);
+                        D = ad > D ? ad : D;
+                    }
+                    if (bad) *nanflag = 1;
+                    kb = bad || (D >= thr);
+                    rbb = kb && rb_level && (bad || D >= thrb);
                 }
+                const uint64_t kw = __ballot(kb);
+                const uint64_t rw = __ballot(rbb);
                 if (lane == 0) {
-                    keep[wb[l] + t] = kw;
-                    ruleb[wb[l] + t] = rw;
+                    keep[wb[l] + w] = kw;
+                    ruleb[wb[l] + w] = rw;
                 }
             }
-            t -= nw;
+            t -= n;
         }
     }
 
     // ----------------------------------------------------------- A4: enlargement
     // Rule (a): every cell of R(T_eps) at level l+1 puts its neighbours within sigma into R,
     // i.e. their parents split: a dilation of keep[l] by ceil(sigma/2) at level l. Rule (b):
-    // both children of a flagged cell are split. Levels below J only.
+    // both children of a flagged cell are split. Writes every word of nsplit.
     DEV void enlarge() {
         const int ra = 1;  // ceil(sigma / 2) for sigma = 1 (every built-in scheme)
         int t = tid;
@@ -171,82 +331,52 @@ struct Block {
         }
     }
 
-    // ----------------------------------------------------------- A7: data transfer
-    // Cells of R(Lambda^{n+1}) not in R(Lambda^n) are predicted from their parent level,
-    // coarse to fine; all other cells keep their values (Sec. 4.1.1). Then the new tree
-    // replaces the old one.
-    DEV void transfer(const Vals<T>& V) {
-        for (int l = jmin + 1; l <= J; ++l) {
-            const int nw = nwords(l);
-            const int Np = 1 << (l - 1);
-            for (int w = wave; w < nw; w += nwaves) {
-                const uint64_t nb = r_word(nsplit, wb, jmin, l, w) & ~r_word(split, wb, jmin, l, w);
-                if (!nb) continue;
-                if ((nb >> lane) & 1ull) {
-                    const int c = (w << 6) + lane;
-                    const int p = c >> 1;
-                    const bool odd = c & 1;
-#pragma unroll
-                    for (int h = 0; h < Q; ++h) {
-                        const T f0 = V.at(l - 1, h, p);
-                        T acc = (T)0;
-#pragma unroll
-                        for (int a = 1; a <= G; ++a) {
-                            const T tt = cc[a - 1] * (V.at(l - 1, h, bcx(p + a, Np, bc)) - V.at(l - 1, h, bcx(p - a, Np, bc)));
-                            acc = (a == 1) ? tt : acc + tt;
-                        }
-                        V.at(l, h, c) = odd ? f0 - acc : f0 + acc;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-        uint64_t* tmp = split;
-        split = nsplit;
-        nsplit = tmp;
-    }
-
-    // ----------------------------------------------------------- A6 + B1
-    // Complete leaves = R(Lambda) minus split cells. Each leaf marks its left edge on the
-    // finest lattice (so that ranks give spatial order) and, when collide is set, is
-    // collided in place (Sec. 4.5). Returns nothing; the count is reduced through red[].
-    DEV void leaves_mark(const Vals<T>& V, bool do_collide, int* nanflag) {
+    // ----------------------------------------------------------- A7 (+ B1): data transfer
+    // Every complete leaf of Lambda^{n+1} gets its value at t^n: the stored value when the
+    // cell is in R(Lambda^n) (a leaf, or the projection of a coarsened subtree), otherwise the
+    // reconstruction from Lambda^n, i.e. level-by-level prediction (Sec. 4.1.1). With collide
+    // set the leaf is collided right away (Sec. 4.5) and its left edge is marked in E.
+    template <class VO_, class VN_>
+    DEV void transfer(const VO_& VO, const VN_& VN, bool collide_mark, int* nanflag) {
         int t = wave;
-        int cnt = 0;
         for (int l = jmin; l <= J; ++l) {
-            const int nw = nwords(l);
-            for (; t < nw; t += nwaves) {
-                const uint64_t lb = r_word(split, wb, jmin, l, t) & (l < J ? ~split[wb[l] + t] : ~0ull);
-                if (!lb) continue;
-                cnt += __popcll(lb);
-                if ((lb >> lane) & 1ull) {
-                    const int k = (t << 6) + lane;
-                    const int e = k << (J - l);
-                    atomicOr((unsigned long long*)&E[e >> 6], 1ull << (e & 63));
-                    if (do_collide) {
-                        T f[Q];
+            const int n = lwl.c[l];
+            for (; t < n; t += nwaves) {
+                const int w = lwl.w[wb[l] + t];
+                const uint64_t b = ruleb[wb[l] + w];
+                if ((b >> lane) & 1ull) {
+                    const int k = (w << 6) + lane;
+                    T f[Q];
+                    if (rbit(ro, wb, l, k)) {
+                        const int so = rank_of(ro, rpo, wb, l, k);
 #pragma unroll
-                        for (int h = 0; h < Q; ++h) f[h] = V.at(l, h, k);
+                        for (int h = 0; h < Q; ++h) f[h] = VO.ld(h, so);
+                    } else {
+                        T g[Q];
+                        chain<T, G, Q, AllPops<S>>(VO, ro, rpo, wb, jmin, l, bc, cc, k, k, f, g);
+                    }
+                    if (collide_mark) {
                         collide<T, S>(d.cf, f);
                         bool bad = false;
 #pragma unroll
-                        for (int h = 0; h < Q; ++h) {
-                            bad = bad || (f[h] != f[h]);
-                            V.at(l, h, k) = f[h];
-                        }
+                        for (int h = 0; h < Q; ++h) bad = bad || (f[h] != f[h]);
                         if (bad) *nanflag = 1;
+                        const int e = k << (J - l);
+                        atomicOr((unsigned long long*)&E[e >> 6], 1ull << (e & 63));
                     }
+                    const int sn = rank_of(keep, rpn, wb, l, k);
+#pragma unroll
+                    for (int h = 0; h < Q; ++h) VN.st(h, sn, f[h]);
                 }
             }
-            t -= nw;
+            t -= n;
         }
-        if (lane == 0) atomicAdd(&red[0], (uint32_t)cnt);
         __syncthreads();
     }
 
-    // Exclusive prefix of popcount(E[w]) over the finest words, block-wide.
+    // ----------------------------------------------------------- A6: leaf list
     DEV void scan_edges() {
-        const int nwJ = nwords(J);
+        const int nwJ = lay.nwJ;
         const int per = (nwJ + NT - 1) / NT;
         const int w0 = tid * per;
         uint32_t s = 0;
@@ -254,72 +384,61 @@ struct Block {
             const int w = w0 + i;
             if (w < nwJ) s += (uint32_t)__popcll(E[w]);
         }
-        // inclusive scan within the wave
-        uint32_t x = s;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) red[1 + wave] = x;
-        __syncthreads();
-        if (tid == 0) {
-            uint32_t run = 0;
-            for (int wv = 0; wv < nwaves; ++wv) {
-                const uint32_t v = red[1 + wv];
-                red[1 + wv] = run;
-                run += v;
-            }
-        }
-        __syncthreads();
-        uint32_t base = red[1 + wave] + x - s;
+        uint32_t tot;
+        uint32_t base = block_scan(s, &tot);
         for (int i = 0; i < per; ++i) {
             const int w = w0 + i;
             if (w < nwJ) {
-                scan[w] = base;
+                scanE[w] = base;
                 base += (uint32_t)__popcll(E[w]);
             }
         }
         __syncthreads();
     }
 
-    // Leaf list in spatial order: rank of a leaf = number of leaf edges left of its own.
-    DEV void write_list() {
+    // Spatial rank of a leaf = number of leaf left edges before its own.
+    template <class LP>
+    DEV void write_list(LP* list) {
         int t = wave;
         for (int l = jmin; l <= J; ++l) {
-            const int nw = nwords(l);
-            for (; t < nw; t += nwaves) {
-                const uint64_t lb = r_word(split, wb, jmin, l, t) & (l < J ? ~split[wb[l] + t] : ~0ull);
-                if (!lb) continue;
-                if ((lb >> lane) & 1ull) {
-                    const int k = (t << 6) + lane;
+            const int n = lwl.c[l];
+            for (; t < n; t += nwaves) {
+                const int w = lwl.w[wb[l] + t];
+                const uint64_t b = ruleb[wb[l] + w];
+                if ((b >> lane) & 1ull) {
+                    const int k = (w << 6) + lane;
                     const int e = k << (J - l);
                     const uint64_t below = E[e >> 6] & ((1ull << (e & 63)) - 1ull);
-                    const uint32_t rank = scan[e >> 6] + (uint32_t)__popcll(below);
-                    d.list[rank] = ((uint32_t)l << 27) | (uint32_t)k;
+                    const uint32_t rank = scanE[e >> 6] + (uint32_t)__popcll(below);
+                    list[rank] = ((uint32_t)l << 27) | (uint32_t)k;
                 }
             }
-            t -= nw;
+            t -= n;
         }
         __syncthreads();
     }
 
     // ----------------------------------------------------------- B3: stream
-    // Interface i is the left edge of leaf i (i = n: the right end of the domain). Its two
+    // Interface i is the left edge of leaf i (i = n: the right end of the domain); its two
     // reconstructed finest values (cells e-1 and e) serve both neighbouring leaves.
-    DEV void pairs(const Vals<T>& V, int n) {
+    template <class V, class LP, class PP>
+    DEV void pairs(const V& Vx, const LP* list, PP* P, int n) {
         const int NJ = 1 << J;
-        T* P = reinterpret_cast<T*>(d.pairs);
-        const int stride = NJ + 1;
+        const int stride = n + 1;
         for (int i = tid; i <= n; i += NT) {
             int e = NJ;
             if (i < n) {
-                const uint32_t key = d.list[i];
+                const uint32_t key = list[i];
                 const int l = key >> 27, k = key & ((1u << 27) - 1u);
                 e = k << (J - l);
             }
+            int tA = e - 1, tB = e;
+            if (bc == CLAMP) {
+                tA = tA < 0 ? 0 : (tA > NJ - 1 ? NJ - 1 : tA);
+                tB = tB > NJ - 1 ? NJ - 1 : tB;
+            }
             T a[NM], b[NM];
-            pair_chain<T, G, NM, MovingPops<S>>(V, split, wb, jmin, J, bc, cc, e, a, b);
+            chain<T, G, NM, MovingPops<S>>(Vx, keep, rpn, wb, jmin, J, bc, cc, tA, tB, a, b);
 #pragma unroll
             for (int m = 0; m < NM; ++m) {
                 P[(2 * m) * stride + i] = a[m];
@@ -329,134 +448,208 @@ struct Block {
         __syncthreads();
     }
 
-    // f^{n+1} of every leaf from its collided value and the interface pairs
+    // f^{n+1} of every leaf from its collided value and the interface pairs, in place
     // (eq. AdaptiveStreamPhase; leaves at level J take the reconstructed neighbour).
-    DEV void combine(const Vals<T>& V, const Vals<T>& Vn, int n) {
-        const int NJ = 1 << J;
-        const T* P = reinterpret_cast<const T*>(d.pairs);
-        const int stride = NJ + 1;
+    template <class V, class LP, class PP>
+    DEV void combine(const V& Vx, const LP* list, const PP* P, int n) {
+        const int stride = n + 1;
         for (int i = tid; i < n; i += NT) {
-            const uint32_t key = d.list[i];
+            const uint32_t key = list[i];
             const int l = key >> 27, k = key & ((1u << 27) - 1u);
+            const int s = rank_of(keep, rpn, wb, l, k);
 #pragma unroll
             for (int h = 0; h < Q; ++h) {
                 const int wh = Sch<S>::w(h);
-                const T fs = V.at(l, h, k);
-                T out = fs;
-                if (wh != 0) {
-                    int m = 0;
+                if (wh == 0) continue;
+                int m = 0;
 #pragma unroll
-                    for (int mm = 0; mm < NM; ++mm)
-                        if (Sch<S>::mv(mm) == h) m = mm;
-                    if (l == J) {
-                        out = wh > 0 ? P[(2 * m) * stride + i] : P[(2 * m + 1) * stride + i + 1];
-                    } else {
-                        const int side = wh > 0 ? 0 : 1;  // eta = -1 (cell e-1) or 0 (cell e)
-                        const T a = P[(2 * m + side) * stride + i];
-                        const T b = P[(2 * m + side) * stride + i + 1];
-                        const T acc = a - b;
-                        out = fs + (T)ldexp(wh > 0 ? acc : -acc, -(J - l));
-                    }
+                for (int mm = 0; mm < NM; ++mm)
+                    if (Sch<S>::mv(mm) == h) m = mm;
+                T out;
+                if (l == J) {
+                    out = wh > 0 ? (T)P[(2 * m) * stride + i] : (T)P[(2 * m + 1) * stride + i + 1];
+                } else {
+                    const int side = wh > 0 ? 0 : 1;  // eta = -1 (cell e-1) or 0 (cell e)
+                    const T a = (T)P[(2 * m + side) * stride + i];
+                    const T b = (T)P[(2 * m + side) * stride + i + 1];
+                    const T acc = a - b;
+                    out = Vx.ld(h, s) + (T)ldexp(wh > 0 ? acc : -acc, -(J - l));
                 }
-                Vn.at(l, h, k) = out;
+                Vx.st(h, s, out);
             }
         }
-        // E is free again (its last reader was write_list, two barriers ago).
-        for (int w = tid; w < nwords(J); w += NT) E[w] = 0ull;
+        for (int w = tid; w < lay.nwJ; w += NT) E[w] = 0ull;
         __syncthreads();
+    }
+
+    // ----------------------------------------------------------- rotation
+    DEV void rotate() {
+        uint64_t* t = split;
+        split = nsplit;
+        nsplit = t;
+        t = ro;
+        ro = keep;
+        keep = t;
+        uint32_t* r = rpo;
+        rpo = rpn;
+        rpn = r;
+        WordList w = swl;
+        swl = nswl;
+        nswl = w;
     }
 };
 
+// Where the values of the current tree live during a launch.
+enum : int { IN_LDS_A = 0, IN_LDS_B = 1, IN_HBM_0 = 2, IN_HBM_1 = 3 };
+
 template <typename T>
-DEV Vals<T> vals_of(const Desc& d, int which) {
-    Vals<T> v;
-    v.base = reinterpret_cast<T*>(which ? d.vb : d.va);
-    v.jmin = d.jmin;
-    v.q = d.q;
-    return v;
-}
+DEV T* hbm_vals(const Desc& d, int which) { return reinterpret_cast<T*>(which ? d.vb : d.va); }
 
-// Block prologue shared by the kernels: level word bases, tree bits into LDS, E cleared.
-template <typename T, int S, int G>
-DEV void load_tree(Block<T, S, G>& B, int* s_wb) {
-    if (B.tid <= 24) s_wb[B.tid] = (B.tid >= B.jmin) ? wbase(B.jmin, B.tid) : 0;
-    if (B.tid < 8) B.red[B.tid] = 0;
-    const int wt = wbase(B.jmin, B.J + 1);
-    const int wsplit = wbase(B.jmin, B.J);
-    for (int w = B.tid; w < wt; w += B.NT) {
-        B.split[w] = w < wsplit ? B.d.split[w] : 0ull;
-        B.nsplit[w] = 0ull;
-    }
-    for (int w = B.tid; w < nwords(B.J); w += B.NT) B.E[w] = 0ull;
-    __syncthreads();
-}
-
-template <typename T, int S, int G>
-DEV void store_tree(Block<T, S, G>& B) {
-    const int wsplit = wbase(B.jmin, B.J);
-    for (int w = B.tid; w < wsplit; w += B.NT) B.d.split[w] = B.split[w];
-}
-
-// nsteps time steps (or adaptations only) of run blockIdx.x.
+// nsteps time steps (or adaptations only) of run blockIdx.x. cap / capS: on-chip capacity in
+// R(Lambda) cells and in leaves (0 = always use the HBM arrays).
 template <typename T, int S, int G>
 __global__ __launch_bounds__(512) void k_steps(const Desc* __restrict__ descs, State* __restrict__ states,
-                                                int nsteps, int mode) {
-    extern __shared__ uint64_t lds[];
+                                               int nsteps, int mode, int cap, int capS) {
+    extern __shared__ __align__(16) uint8_t lds[];
     __shared__ int s_wb[32];
-    __shared__ uint32_t s_red[40];
+    __shared__ uint32_t s_red[24];
+    __shared__ int s_cnt[96];
     __shared__ int s_nan;
+    typedef Block<T, S, G> B_t;
+    typedef typename B_t::LT LT;
+    constexpr int Q = B_t::Q;
     const Desc& d = descs[blockIdx.x];
-    Block<T, S, G> B(d, s_wb, lds, s_red);
+    const Layout lay = make_layout(d.jmin, d.jmax, cap, capS, d.q, d.nm, (int)sizeof(T));
+    B_t B(d, lay, lds, s_wb, s_red, s_cnt);
+    const int Cg = (1 << (d.jmax + 1)) - (1 << d.jmin);  // slots of an HBM array
+    if (threadIdx.x <= 24) s_wb[threadIdx.x] = (threadIdx.x >= d.jmin) ? wbase(d.jmin, threadIdx.x) : 0;
     if (threadIdx.x == 0) s_nan = 0;
-    load_tree(B, s_wb);
-    int cur = states[blockIdx.x].cur;
-    long long upd = 0;
-    int last = -1;
-    for (int st = 0; st < nsteps; ++st) {
-        const Vals<T> V = vals_of<T>(d, cur);
-        if (mode & MODE_ADAPT) {
-            B.project_up(V);
-            B.details(V, &s_nan);
+    if (threadIdx.x < 24) s_red[threadIdx.x] = 0;
+    const int wsplit = wbase(d.jmin, d.jmax);
+    for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) B.split[w] = w < wsplit ? d.split[w] : 0ull;
+    for (int w = threadIdx.x; w < lay.nwJ; w += blockDim.x) B.E[w] = 0ull;
+    __syncthreads();
+    B.build_tree(B.split, B.ro, B.rpo, B.swl, nullptr, B.lwl);
+    State& st = states[blockIdx.x];
+    int where = st.cur ? IN_HBM_1 : IN_HBM_0;
+    {
+        const int nR = (int)B.rpo[lay.wt];
+        if (nR <= cap) {
+            const T* src = hbm_vals<T>(d, st.cur);
+            for (int i = threadIdx.x; i < Q * nR; i += blockDim.x) {
+                const int h = i / nR, s = i - h * nR;
+                B.ldsA[h * cap + s] = src[(size_t)h * Cg + s];
+            }
+            where = IN_LDS_A;
             __syncthreads();
-            B.enlarge();
-            B.grade();
-            B.transfer(V);
-        }
-        if (mode & MODE_SCHEME) {
-            B.leaves_mark(V, true, &s_nan);
-            const int n = (int)B.red[0];
-            B.scan_edges();
-            B.write_list();
-            B.project_up(V);
-            B.pairs(V, n);
-            const Vals<T> Vn = vals_of<T>(d, cur ^ 1);
-            B.combine(V, Vn, n);
-            if (threadIdx.x == 0) B.red[0] = 0;
-            __syncthreads();
-            cur ^= 1;
-            upd += n;
-            last = n;
         }
     }
-    store_tree(B);
-    if (threadIdx.x == 0) {
-        State& s = states[blockIdx.x];
-        s.cur = cur;
-        if (mode & MODE_SCHEME) {
-            s.steps += nsteps;
-            s.leaf_updates += upd;
-            if (last >= 0) s.n_leaves = last;
+    long long upd = 0;
+    int last = -1;
+    bool last_fast = false;
+    for (int stp = 0; stp < nsteps; ++stp) {
+        // ---- adaptation on the old tree
+        for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) {
+            B.keep[w] = 0ull;
+            B.ruleb[w] = 0ull;
         }
-        if (s_nan) s.flags |= 1;
+        __syncthreads();
+        if (where <= IN_LDS_B) {
+            VP<T, LT> VO{where == IN_LDS_A ? B.ldsA : B.ldsB, cap};
+            B.project_up(VO, B.split, B.ro, B.rpo, B.swl);
+            B.details(VO, &s_nan);
+        } else {
+            VP<T, T> VO{hbm_vals<T>(d, where - IN_HBM_0), Cg};
+            B.project_up(VO, B.split, B.ro, B.rpo, B.swl);
+            B.details(VO, &s_nan);
+        }
+        __syncthreads();
+        B.enlarge();
+        B.grade();
+        B.build_tree(B.nsplit, B.keep, B.rpn, B.nswl, B.ruleb, B.lwl);
+        const int nR = (int)B.rpn[lay.wt];
+        const int n = (int)B.red[0];
+        const bool scheme = (mode & MODE_SCHEME) != 0;
+        // ---- new values: on chip when the new tree fits
+        int nwhere;
+        if (where <= IN_LDS_B) nwhere = (nR <= cap) ? (IN_LDS_B - where) : IN_HBM_0;
+        else nwhere = (nR <= cap) ? IN_LDS_A : (where == IN_HBM_0 ? IN_HBM_1 : IN_HBM_0);
+        const bool fast = (where <= IN_LDS_B) && (nwhere <= IN_LDS_B) && (n <= capS);
+        if (fast) {
+            VP<T, LT> VO{where == IN_LDS_A ? B.ldsA : B.ldsB, cap};
+            VP<T, LT> VN{nwhere == IN_LDS_A ? B.ldsA : B.ldsB, cap};
+            B.transfer(VO, VN, scheme, &s_nan);
+            if (scheme) {
+                B.scan_edges();
+                B.write_list(B.ldsL);
+                B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
+                B.pairs(VN, B.ldsL, B.ldsP, n);
+                B.combine(VN, B.ldsL, B.ldsP, n);
+            }
+        } else {
+            T* po = where <= IN_LDS_B ? (T*)(where == IN_LDS_A ? B.ldsA : B.ldsB) : hbm_vals<T>(d, where - IN_HBM_0);
+            const int so = where <= IN_LDS_B ? cap : Cg;
+            T* pn = nwhere <= IN_LDS_B ? (T*)(nwhere == IN_LDS_A ? B.ldsA : B.ldsB) : hbm_vals<T>(d, nwhere - IN_HBM_0);
+            const int sn = nwhere <= IN_LDS_B ? cap : Cg;
+            VP<T, T> VO{po, so};
+            VP<T, T> VN{pn, sn};
+            B.transfer(VO, VN, scheme, &s_nan);
+            if (scheme) {
+                B.scan_edges();
+                B.write_list(d.list);
+                B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
+                T* P = reinterpret_cast<T*>(d.pairs);
+                B.pairs(VN, d.list, P, n);
+                B.combine(VN, d.list, P, n);
+            }
+        }
+        B.rotate();
+        where = nwhere;
+        if (scheme) {
+            upd += n;
+            last = n;
+            last_fast = fast;
+        }
+        if (threadIdx.x == 0) B.red[0] = 0;
+        __syncthreads();
+    }
+    // ---- epilogue: home copy, tree, leaf list of the last step, statistics
+    const int nR = (int)B.rpo[lay.wt];
+    int home;
+    if (where <= IN_LDS_B) {
+        home = st.cur;  // the array the launch started from is free to overwrite
+        T* dst = hbm_vals<T>(d, home);
+        const LT* src = where == IN_LDS_A ? B.ldsA : B.ldsB;
+        for (int i = threadIdx.x; i < Q * nR; i += blockDim.x) {
+            const int h = i / nR, s = i - h * nR;
+            dst[(size_t)h * Cg + s] = src[h * cap + s];
+        }
+        if (last >= 0 && last_fast)
+            for (int i = threadIdx.x; i < last; i += blockDim.x) d.list[i] = B.ldsL[i];
+    } else {
+        home = where - IN_HBM_0;
+    }
+    for (int w = threadIdx.x; w < wsplit; w += blockDim.x) d.split[w] = B.split[w];
+    if (threadIdx.x == 0) {
+        st.cur = home;
+        if (mode & MODE_SCHEME) {
+            st.steps += nsteps;
+            st.leaf_updates += upd;
+            if (last >= 0) st.n_leaves = last;
+        }
+        st.n_r = nR;
+        if (s_nan) st.flags |= 1;
     }
 }
 
-// Initial state: populations at equilibrium on the finest level, full tree.
+// Initial state: populations at equilibrium on the finest level of the full tree.
 template <typename T, int S>
 __global__ void k_init(const Desc* __restrict__ descs, State* __restrict__ states, const double* __restrict__ mc,
                        long long mc_stride) {
     const Desc& d = descs[blockIdx.y];
     const int NJ = 1 << d.jmax;
+    const int Cg = (1 << (d.jmax + 1)) - (1 << d.jmin);
+    const int base = (1 << d.jmax) - (1 << d.jmin);  // slot of (J, 0) in the full tree
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const double* m = mc + blockIdx.y * mc_stride;
     if (k < NJ) {
@@ -464,12 +657,11 @@ __global__ void k_init(const Desc* __restrict__ descs, State* __restrict__ state
         for (int i = 0; i < d.qc; ++i) c[i] = m[(size_t)i * NJ + k];
         T f[Sch<S>::Q];
         equilibrium<T, S>(d.cf, c, f);
-        Vals<T> V = vals_of<T>(d, 0);
-        for (int h = 0; h < Sch<S>::Q; ++h) V.at(d.jmax, h, k) = f[h];
+        T* v = reinterpret_cast<T*>(d.va);
+        for (int h = 0; h < Sch<S>::Q; ++h) v[(size_t)h * Cg + base + k] = f[h];
     }
     const int wsplit = wbase(d.jmin, d.jmax);
     for (int w = k; w < wsplit; w += gridDim.x * blockDim.x) {
-        // full tree: every cell below J split; partial words keep only their valid bits
         int l = d.jmin;
         while (w >= wbase(d.jmin, l + 1)) ++l;
         d.split[w] = lowmask(1 << l);
@@ -479,37 +671,67 @@ __global__ void k_init(const Desc* __restrict__ descs, State* __restrict__ state
         s.steps = 0;
         s.leaf_updates = 0;
         s.n_leaves = NJ;
+        s.n_r = Cg;
         s.cur = 0;
         s.flags = 0;
     }
 }
 
-// Queries: leaf list of the current tree, then per leaf (where = 0) its conserved moments
-// (what = 0) or populations (what = 1), or (where = 1) the reconstruction on every finest
-// cell followed by its conserved moments. Output in d.out, [component][position].
+// Queries on the home copy: leaf list of the current tree, then per leaf (where = 0) its
+// conserved moments (what = 0) or populations (what = 1), or (where = 1) the reconstruction on
+// every finest cell followed by its conserved moments or populations. Output [component][position].
 template <typename T, int S, int G>
 __global__ __launch_bounds__(512) void k_query(const Desc* __restrict__ descs, State* __restrict__ states,
-                                                int where, int what, double* __restrict__ out) {
-    extern __shared__ uint64_t lds[];
+                                               int where, int what, double* __restrict__ out) {
+    extern __shared__ __align__(16) uint8_t lds[];
     __shared__ int s_wb[32];
-    __shared__ uint32_t s_red[40];
-    __shared__ int s_nan;
+    __shared__ uint32_t s_red[24];
+    __shared__ int s_cnt[96];
+    typedef Block<T, S, G> B_t;
+    constexpr int Q = B_t::Q;
     const Desc& d = descs[blockIdx.x];
-    Block<T, S, G> B(d, s_wb, lds, s_red);
-    load_tree(B, s_wb);
-    const int cur = states[blockIdx.x].cur;
-    const Vals<T> V = vals_of<T>(d, cur);
-    B.leaves_mark(V, false, &s_nan);
+    const Layout lay = make_layout(d.jmin, d.jmax, 0, 0, d.q, d.nm, (int)sizeof(T));
+    B_t B(d, lay, lds, s_wb, s_red, s_cnt);
+    const int Cg = (1 << (d.jmax + 1)) - (1 << d.jmin);
+    if (threadIdx.x <= 24) s_wb[threadIdx.x] = (threadIdx.x >= d.jmin) ? wbase(d.jmin, threadIdx.x) : 0;
+    if (threadIdx.x < 24) s_red[threadIdx.x] = 0;
+    const int wsplit = wbase(d.jmin, d.jmax);
+    for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) B.split[w] = w < wsplit ? d.split[w] : 0ull;
+    for (int w = threadIdx.x; w < lay.nwJ; w += blockDim.x) B.E[w] = 0ull;
+    __syncthreads();
+    // The current tree plays the role of the "new" tree of a step (keep = R bits, ruleb = leaf bits).
+    for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) B.nsplit[w] = B.split[w];
+    __syncthreads();
+    B.build_tree(B.nsplit, B.keep, B.rpn, B.nswl, B.ruleb, B.lwl);
     const int n = (int)B.red[0];
+    VP<T, T> V{hbm_vals<T>(d, states[blockIdx.x].cur), Cg};
+    // mark edges, rank, list
+    {
+        int t = B.wave;
+        for (int l = B.jmin; l <= B.J; ++l) {
+            const int nn = B.lwl.c[l];
+            for (; t < nn; t += B.nwaves) {
+                const int w = B.lwl.w[s_wb[l] + t];
+                const uint64_t b = B.ruleb[s_wb[l] + w];
+                if ((b >> B.lane) & 1ull) {
+                    const int k = (w << 6) + B.lane;
+                    const int e = k << (B.J - l);
+                    atomicOr((unsigned long long*)&B.E[e >> 6], 1ull << (e & 63));
+                }
+            }
+            t -= nn;
+        }
+        __syncthreads();
+    }
     B.scan_edges();
-    B.write_list();
-    constexpr int Q = Sch<S>::Q;
+    B.write_list(d.list);
     if (where == 0) {
-        for (int i = B.tid; i < n; i += B.NT) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
             const uint32_t key = d.list[i];
             const int l = key >> 27, k = key & ((1u << 27) - 1u);
+            const int s = rank_of(B.keep, B.rpn, s_wb, l, k);
             T f[Q];
-            for (int h = 0; h < Q; ++h) f[h] = V.at(l, h, k);
+            for (int h = 0; h < Q; ++h) f[h] = V.ld(h, s);
             if (what == 0) {
                 double mc[MAXQ];
                 conserved<T, S>(d.cf, f, mc);
@@ -519,11 +741,11 @@ __global__ __launch_bounds__(512) void k_query(const Desc* __restrict__ descs, S
             }
         }
     } else {
-        B.project_up(V);
+        B.project_up(V, B.nsplit, B.keep, B.rpn, B.nswl);
         const int NJ = 1 << d.jmax;
-        for (int m = B.tid; m < NJ; m += B.NT) {
+        for (int m = threadIdx.x; m < NJ; m += blockDim.x) {
             T a[Q], b[Q];
-            pair_chain<T, G, Q, AllPops<S>>(V, B.split, s_wb, B.jmin, B.J, B.bc, B.cc, m + 1, a, b);
+            chain<T, G, Q, AllPops<S>>(V, B.keep, B.rpn, s_wb, B.jmin, B.J, B.bc, B.cc, m, m, a, b);
             if (what == 0) {
                 double mc[MAXQ];
                 conserved<T, S>(d.cf, a, mc);
@@ -533,7 +755,10 @@ __global__ __launch_bounds__(512) void k_query(const Desc* __restrict__ descs, S
             }
         }
     }
-    if (threadIdx.x == 0) states[blockIdx.x].n_leaves = n;
+    if (threadIdx.x == 0) {
+        states[blockIdx.x].n_leaves = n;
+        states[blockIdx.x].n_r = (int)B.rpn[lay.wt];
+    }
 }
 
 }  // namespace mrl

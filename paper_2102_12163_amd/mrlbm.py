@@ -39,7 +39,8 @@ class Params(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("steps", c_int64), ("leaves", c_int64), ("leaf_updates", c_int64),
-                ("numeric_error", c_int32), ("q", c_int32), ("q_cons", c_int32), ("j_max", c_int32)]
+                ("numeric_error", c_int32), ("q", c_int32), ("q_cons", c_int32), ("j_max", c_int32),
+                ("tree_cells", c_int64)]
 
 
 class MRLBMError(RuntimeError):
@@ -71,6 +72,8 @@ SIGNATURES = {
     "mrlbm_batch_total_updates": (c_int32, [c_void_p, _P(c_int64)]),
     "mrlbm_batch_set_block": (c_int32, [c_void_p, c_int32]),
     "mrlbm_batch_get_block": (c_int32, [c_void_p, _P(c_int32)]),
+    "mrlbm_batch_set_capacity": (c_int32, [c_void_p, c_int32]),
+    "mrlbm_batch_get_capacity": (c_int32, [c_void_p, _P(c_int32)]),
     "mrlbm_batch_destroy": (None, [c_void_p]),
     "mrlbm_batch_last_error": (ctypes.c_char_p, [c_void_p]),
 }
@@ -274,6 +277,14 @@ class Batch:
 
     def set_block(self, threads):
         _check(lib().mrlbm_batch_set_block(self.h, int(threads)), self._err)
+
+    def set_capacity(self, cells):
+        _check(lib().mrlbm_batch_set_capacity(self.h, int(cells)), self._err)
+
+    def get_capacity(self):
+        t = c_int32()
+        _check(lib().mrlbm_batch_get_capacity(self.h, ctypes.byref(t)), self._err)
+        return t.value
 
     def get_block(self):
         t = c_int32()

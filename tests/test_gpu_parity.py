@@ -215,3 +215,28 @@ def test_full_size_shallow_water_j16():
 def test_full_size_euler_j14():
     p, mc = W.euler(0, jmax=14)
     run_pair(p, mc, 60, 30, "euler J14")
+
+
+@pytest.mark.parametrize("cap", [0, 120, 400])
+def test_onchip_capacity_does_not_change_results(cap):
+    """Runs whose trees live in HBM (capacity 0) or switch between LDS and HBM from step to
+    step (small capacities) give the same bits as the on-chip runs and the oracle."""
+    cases = [W.small_case(k, seed=7, jmax=10, eps=1e-4) for k in ("advection", "burgers_d1q2")]
+    announce("capacity", cap)
+    for p, mc in cases:
+        b = mrlbm.Batch([p], [mc])
+        b.set_capacity(cap)
+        assert b.get_capacity() == cap
+        ref = mrlbm.Batch([p], [mc])
+        ora = make_oracle(p, mc)
+        for _ in range(4):
+            b.step(15)
+            ref.step(15)
+            ora.step(15)
+            assert np.array_equal(b.moments(0), ref.moments(0))
+            lv, ix = b.leaves(0)
+            olv, oix = ora.leaf_list()
+            assert np.array_equal(lv, olv) and np.array_equal(ix, oix)
+            assert rel_err(b.moments(0), ora.leaf_conserved()) <= 1e-12
+        b.close()
+        ref.close()
