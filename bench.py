@@ -4,10 +4,11 @@
 Workload (the D1Q3 Burgers family at full size): D1Q3 scheme with m2^eq = 0.9 lambda^2 u,
 lambda = 1, periodic [-1, 1], J_min = 2, J = 14 (16384 finest cells), gamma = 1,
 mu_bar = 0; the sweep s in {1.5, 1.9} x eps in {1e-2, 1e-3, 1e-4}, with ``--seeds``
-seeded initial data per pair (Riemann data + sine, see workloads.burgers). All runs
-advance together in the batched engine (one workgroup per run, one launch per call); a
-"step" is one time step of every run. T = 0.4 is 3277 steps: warmup + timed steps add up
-to that by default.
+seeded initial data per pair (Riemann data + sine, see workloads.burgers); the default
+85 seeds give 510 runs, about two per compute unit. All runs advance together in the
+batched engine (one workgroup per run, one launch per call; the built-in tuner picks the
+launch shape on a snapshot first); a "step" is one time step of every run. T = 0.4 is
+3277 steps: warmup + timed steps add up to that by default.
 
 Reported next to the throughput:
 * roofline of the step kernel: algorithmic bytes (2 q s_b + 8 per leaf-cell update: read
@@ -130,7 +131,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3227)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--seeds", type=int, default=8, help="seeded runs per (s, eps) pair")
+    ap.add_argument("--seeds", type=int, default=85, help="seeded runs per (s, eps) pair")
+    ap.add_argument("--no-tune", action="store_true", help="skip the built-in launch-shape tuner")
+    ap.add_argument("--tune-steps", type=int, default=20)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: tuner)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -153,8 +156,14 @@ def main():
     cases = instances(args.seeds, prec)
     print(f"[bench] {len(cases)} runs, warmup {args.warmup}, timed {args.steps}", file=sys.stderr, flush=True)
     batch = mrlbm.Batch([c[0] for c in cases], [c[1] for c in cases])
+    tuned = None
     if args.block:
         batch.set_block(args.block)
+    elif not args.no_tune:
+        tuned = batch.tune(args.tune_steps)
+        print(f"[bench] tuner: {tuned[0]} threads per workgroup, on-chip capacity {tuned[1]} cells",
+              file=sys.stderr, flush=True)
+    cap_cells = batch.get_capacity()
     if args.warmup:
         batch.step(args.warmup)
     u0 = batch.total_updates()
@@ -186,7 +195,8 @@ def main():
             "workload": "D1Q3 Burgers, J_min=2 J=14 (16384 cells), gamma=1, periodic [-1,1], "
                         "s in {1.5,1.9} x eps in {1e-2,1e-3,1e-4}, batched runs",
             "runs": len(cases), "seeds_per_pair": args.seeds, "finest_cells": 16384,
-            "threads_per_workgroup": block, "form": "batched engine, one launch for all timed steps",
+            "threads_per_workgroup": block, "onchip_capacity_cells": cap_cells,
+            "tuned": tuned is not None, "form": "batched engine, one launch for all timed steps",
             "mean_leaves_per_run": float(np.mean(leaves_now)),
         },
         "roofline": {

@@ -169,6 +169,12 @@ int mrlbm_batch_get_block(mrlbm_batch_t b, int32_t* threads);
  * cells = -1: the largest capacity the device's LDS allows (default); 0: always HBM.
  * get_capacity returns the capacity in use. */
 int mrlbm_batch_set_capacity(mrlbm_batch_t b, int32_t cells);
+/* Built-in tuner: times trial_steps steps of the batch for every candidate launch shape
+ * (threads per workgroup 128/256/512 x LDS capacity for 1, 2 or 3 runs per compute unit),
+ * restoring the runs' state after each trial, and keeps the fastest (leaf-cell updates/s).
+ * The runs end in the state they had before the call. Allocates a temporary snapshot of
+ * the handle's device memory. Chosen values are returned when the pointers are non-NULL. */
+int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int32_t* cells);
 int mrlbm_batch_get_capacity(mrlbm_batch_t b, int32_t* cells);
 void mrlbm_batch_destroy(mrlbm_batch_t b);
 const char* mrlbm_batch_last_error(mrlbm_batch_t b);

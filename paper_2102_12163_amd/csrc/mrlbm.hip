@@ -20,6 +20,27 @@
 #include "mrlbm.h"
 #include "mrlbm_kernels.h"
 
+// The kernels are instantiated in instances.hip (one object per storage type and scheme).
+namespace mrl {
+#define MRL_EXTERN(T, S)                                                                        \
+    extern template __global__ void k_init<T, S>(const Desc*, State*, const double*, long long); \
+    extern template __global__ void k_steps<T, S, 1>(const Desc*, State*, int, int, int, int);   \
+    extern template __global__ void k_steps<T, S, 2>(const Desc*, State*, int, int, int, int);   \
+    extern template __global__ void k_steps<T, S, 3>(const Desc*, State*, int, int, int, int);   \
+    extern template __global__ void k_query<T, S, 1>(const Desc*, State*, int, int, double*);    \
+    extern template __global__ void k_query<T, S, 2>(const Desc*, State*, int, int, double*);    \
+    extern template __global__ void k_query<T, S, 3>(const Desc*, State*, int, int, double*);
+MRL_EXTERN(double, 0)
+MRL_EXTERN(double, 1)
+MRL_EXTERN(double, 2)
+MRL_EXTERN(double, 3)
+MRL_EXTERN(float, 0)
+MRL_EXTERN(float, 1)
+MRL_EXTERN(float, 2)
+MRL_EXTERN(float, 3)
+#undef MRL_EXTERN
+}  // namespace mrl
+
 using namespace mrl;
 
 namespace {
@@ -712,6 +733,80 @@ int mrlbm_batch_get_capacity(mrlbm_batch_t b, int32_t* cells) {
     if (!b || !cells) return MRLBM_EINVAL;
     *cells = b->e->cap;
     return MRLBM_OK;
+}
+
+int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int32_t* cells) {
+    if (!b || trial_steps <= 0) return MRLBM_EINVAL;
+    Engine* e = b->e;
+    if (e->numeric) return MRLBM_ENUMERIC;
+    // snapshot of every run (values, trees, lists, statistics), restored after each trial
+    char* snap = nullptr;
+    State* ssnap = nullptr;
+    hipError_t st = hipMalloc(&snap, e->pool_bytes);
+    if (st != hipSuccess) return hip_fail(e, st, "hipMalloc(tune snapshot)");
+    st = hipMalloc(&ssnap, sizeof(State) * e->n);
+    if (st != hipSuccess) {
+        (void)hipFree(snap);
+        return hip_fail(e, st, "hipMalloc(tune snapshot)");
+    }
+    auto copy_all = [&](bool save) {
+        hipError_t s1 = save ? hipMemcpyAsync(snap, e->pool, e->pool_bytes, hipMemcpyDeviceToDevice, e->stream)
+                             : hipMemcpyAsync(e->pool, snap, e->pool_bytes, hipMemcpyDeviceToDevice, e->stream);
+        hipError_t s2 = save ? hipMemcpyAsync(ssnap, e->ds, sizeof(State) * e->n, hipMemcpyDeviceToDevice, e->stream)
+                             : hipMemcpyAsync(e->ds, ssnap, sizeof(State) * e->n, hipMemcpyDeviceToDevice, e->stream);
+        return s1 != hipSuccess ? s1 : s2;
+    };
+    const int saved_nt = e->nt_user;
+    const size_t full_budget = e->lds_budget;
+    int best_nt = 0;
+    size_t best_budget = full_budget;
+    double best_rate = -1.0;
+    int rc = MRLBM_OK;
+    if ((st = copy_all(true)) != hipSuccess) rc = hip_fail(e, st, "tune snapshot");
+    const int nts[3] = {128, 256, 512};
+    for (int ti = 0; ti < 3 && rc == MRLBM_OK; ++ti) {
+        for (int per_cu = 1; per_cu <= 3 && rc == MRLBM_OK; ++per_cu) {
+            e->nt_user = nts[ti];
+            e->lds_budget = (full_budget + 1024) / per_cu - 1024;
+            choose_capacity(e);
+            if (e->lds > e->lds_budget) continue;  // the tree words alone do not fit
+            std::vector<State> h0, h1;
+            if ((rc = read_states(e, h0)) != MRLBM_OK) break;
+            double ms = 0.0;
+            if ((st = hipEventRecord(e->ev0, e->stream)) != hipSuccess) { rc = hip_fail(e, st, "tune"); break; }
+            if ((rc = launch_steps(e, trial_steps, MODE_ADAPT | MODE_SCHEME, false)) != MRLBM_OK) break;
+            if ((st = hipEventRecord(e->ev1, e->stream)) != hipSuccess) { rc = hip_fail(e, st, "tune"); break; }
+            if ((st = hipEventSynchronize(e->ev1)) != hipSuccess) { rc = hip_fail(e, st, "tune"); break; }
+            float f = 0.f;
+            (void)hipEventElapsedTime(&f, e->ev0, e->ev1);
+            ms = f;
+            if ((rc = read_states(e, h1)) != MRLBM_OK) break;
+            long long upd = 0;
+            for (int i = 0; i < e->n; ++i) upd += h1[i].leaf_updates - h0[i].leaf_updates;
+            const double rate = ms > 0 ? upd / ms : 0.0;
+            if (rate > best_rate) {
+                best_rate = rate;
+                best_nt = nts[ti];
+                best_budget = e->lds_budget;
+            }
+            if ((st = copy_all(false)) != hipSuccess) rc = hip_fail(e, st, "tune restore");
+        }
+    }
+    if ((st = hipStreamSynchronize(e->stream)) != hipSuccess && rc == MRLBM_OK) rc = hip_fail(e, st, "tune");
+    (void)hipFree(snap);
+    (void)hipFree(ssnap);
+    if (rc != MRLBM_OK || best_rate < 0) {
+        e->nt_user = saved_nt;
+        e->lds_budget = full_budget;
+        choose_capacity(e);
+        return rc != MRLBM_OK ? rc : MRLBM_OK;
+    }
+    e->nt_user = best_nt;
+    e->lds_budget = best_budget;
+    choose_capacity(e);
+    if (threads) *threads = best_nt;
+    if (cells) *cells = e->cap;
+    return check_numeric(e);
 }
 
 int mrlbm_batch_get_block(mrlbm_batch_t b, int32_t* threads) {

@@ -55,9 +55,13 @@ struct State {
 #define DEV __device__ __forceinline__
 
 __host__ __device__ inline int nwords(int l) { return l >= 6 ? (1 << (l - 6)) : 1; }
+// Number of words of the levels jmin..l-1: one word per level below 6, 2^(m-6) at level m >= 6.
 __host__ __device__ inline int wbase(int jmin, int l) {
     int s = 0;
-    for (int m = jmin; m < l; ++m) s += nwords(m);
+    const int e1 = l < 6 ? l : 6;
+    if (e1 > jmin) s += e1 - jmin;
+    const int b2 = jmin > 6 ? jmin : 6;
+    if (l > b2) s += (1 << (l - 6)) - (1 << (b2 - 6));
     return s;
 }
 
@@ -92,15 +96,10 @@ DEV uint64_t compress64(uint64_t x) {
 
 DEV bool getbit(const uint64_t* A, int wbl, int k) { return (A[wbl + (k >> 6)] >> (k & 63)) & 1ull; }
 
-// (l, k) in R(Lambda): every cell of level Jmin, else the parent is split.
-DEV bool in_r(const uint64_t* split, const int* wb, int jmin, int l, int k) {
-    return l == jmin ? true : getbit(split, wb[l - 1], k >> 1);
-}
-
-// Word w of R(Lambda) at level l.
-DEV uint64_t r_word(const uint64_t* split, const int* wb, int jmin, int l, int w) {
+// Word w of R(Lambda) at level l: all of level Jmin, else the children of split cells.
+DEV uint64_t r_word(const uint64_t* split, int jmin, int l, int w) {
     if (l == jmin) return lowmask(1 << l);
-    uint64_t x = split[wb[l - 1] + (w >> 1)] >> ((w & 1) * 32);
+    uint64_t x = split[wbase(jmin, l - 1) + (w >> 1)] >> ((w & 1) * 32);
     return spread32(x);
 }
 
@@ -296,11 +295,11 @@ DEV void conserved(const Coef& c, const T* f, double* mc) {
 // p[h * stride + s]. R holds the R(Lambda) bits per 64-bit word and RP the number of
 // R(Lambda) cells in all words before a word, so slot(l, k) = RP[w] + popcount of the R
 // bits below k in its word w.
-DEV int rank_of(const uint64_t* R, const uint32_t* RP, const int* wb, int l, int k) {
-    const int w = wb[l] + (k >> 6);
+DEV int rank_of(const uint64_t* R, const uint32_t* RP, int jmin, int l, int k) {
+    const int w = wbase(jmin, l) + (k >> 6);
     return (int)RP[w] + __popcll(R[w] & ((1ull << (k & 63)) - 1ull));
 }
-DEV bool rbit(const uint64_t* R, const int* wb, int l, int k) { return (R[wb[l] + (k >> 6)] >> (k & 63)) & 1ull; }
+DEV bool rbit(const uint64_t* R, int jmin, int l, int k) { return (R[wbase(jmin, l) + (k >> 6)] >> (k & 63)) & 1ull; }
 
 template <typename T, typename P>
 struct VP {
@@ -321,17 +320,25 @@ struct VP {
 // the whole window stays in registers. Out-of-range cells under clamp copy the edge cell.
 // Under clamp the targets must already be in range.
 template <typename T, int G, int NP, class PM, class V>
-DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, const int* wb, int jmin, int L, int bc,
-               const T* cc, int tA, int tB, T* outA, T* outB) {
+DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, int jmin, int L, int bc, const T* cc, int tA,
+               int tB, T* outA, T* outB) {
     constexpr int WM = 4 * G + 1;
+    // descent: the finest level whose whole window lies in R(Lambda)
     int l0 = L;
     while (l0 > jmin) {
         const int sh = L - l0;
         const int lo = ((tA + 2 * G) >> sh) - 2 * G;
         const int hi = ((tB - 2 * G) >> sh) + 2 * G;
         const int N = 1 << l0;
+        const int wbl = wbase(jmin, l0);
         bool all = true;
-        for (int x = lo; x <= hi && all; ++x) all = rbit(R, wb, l0, bcx(x, N, bc));
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            if (i <= hi - lo) {
+                const int xx = bcx(lo + i, N, bc);
+                all = all && ((R[wbl + (xx >> 6)] >> (xx & 63)) & 1ull);
+            }
+        }
         if (all) break;
         --l0;
     }
@@ -341,15 +348,21 @@ DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, const int* wb
         const int lo = ((tA + 2 * G) >> sh) - 2 * G;
         const int hi = ((tB - 2 * G) >> sh) + 2 * G;
         const int N = 1 << l0;
+        const int wbl = wbase(jmin, l0);
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
             const int xx = bcx(lo + i, N, bc);
-            const bool ok = (i <= hi - lo) && rbit(R, wb, l0, xx);
-            const int s = ok ? rank_of(R, RP, wb, l0, xx) : 0;
+            const int w = wbl + (xx >> 6);
+            const uint64_t rw = R[w];
+            const bool ok = (i <= hi - lo) && ((rw >> (xx & 63)) & 1ull);
+            const int s = ok ? (int)RP[w] + __popcll(rw & ((1ull << (xx & 63)) - 1ull)) : 0;
 #pragma unroll
             for (int m = 0; m < NP; ++m) win[m][i] = ok ? Vx.ld(PM::h(m), s) : (T)0;
         }
     }
+    // ascent; once a window level holds no cell of R(Lambda), no finer window level does
+    // (their parents lie inside it), and the rest is prediction only
+    bool anyr = true;
     for (int l = l0 + 1; l <= L; ++l) {
         const int sh = L - l;
         const int u = (tA + 2 * G) >> sh;
@@ -357,15 +370,24 @@ DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, const int* wb
         const int hi = ((tB - 2 * G) >> sh) + 2 * G;
         const int N = 1 << l;
         const bool par = (u & 1) != 0;
+        const int wbl = wbase(jmin, l);
         T nw[NP][WM];
+        bool any = false;
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
             const int x = lo + i;
             const int xx = bcx(x, N, bc);
             const bool odd = ((i + (par ? 1 : 0)) & 1) != 0;
-            const bool inr = (i <= hi - lo) && rbit(R, wb, l, xx);
+            bool inr = false;
+            int s = 0;
+            if (anyr && i <= hi - lo) {
+                const int w = wbl + (xx >> 6);
+                const uint64_t rw = R[w];
+                inr = (rw >> (xx & 63)) & 1ull;
+                if (inr) s = (int)RP[w] + __popcll(rw & ((1ull << (xx & 63)) - 1ull));
+            }
+            any = any || inr;
             if (inr) {
-                const int s = rank_of(R, RP, wb, l, xx);
 #pragma unroll
                 for (int m = 0; m < NP; ++m) nw[m][i] = Vx.ld(PM::h(m), s);
             } else {
@@ -385,6 +407,7 @@ DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, const int* wb
                 }
             }
         }
+        anyr = any;
         if (bc == CLAMP && (lo < 0 || hi >= N)) {
             const int e0 = -lo, e1 = N - 1 - lo;
 #pragma unroll

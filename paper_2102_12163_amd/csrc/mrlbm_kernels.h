@@ -58,7 +58,7 @@ __host__ __device__ inline Layout make_layout(int jmin, int J, int cap, int capS
 }
 
 // Per-level word lists: the words of level l that carry set bits are
-// list[wb[l] .. wb[l] + count[l]) (any order inside a level).
+// list[WB(l) .. WB(l) + count[l]) (any order inside a level).
 struct WordList {
     uint16_t* w;
     int* c;
@@ -74,7 +74,6 @@ struct Block {
     int tid, NT, lane, wave, nwaves;
     int jmin, J, bc, wt;
     Layout lay;
-    int* wb;          // word base per level, wb[J + 1] = wt (LDS)
     uint32_t* red;    // small scratch: [0] leaf count, [1..16] wave partials
     // tree arrays, rotated at the end of each step
     uint64_t* split;  // Lambda^n split bits
@@ -93,8 +92,8 @@ struct Block {
     uint32_t* ldsL;   // on-chip leaf list
     T cc[3];
 
-    DEV Block(const Desc& dd, const Layout& L, uint8_t* lds, int* wb_, uint32_t* red_, int* cnts)
-        : d(dd), lay(L), wb(wb_), red(red_) {
+    DEV Block(const Desc& dd, const Layout& L, uint8_t* lds, uint32_t* red_, int* cnts)
+        : d(dd), lay(L), red(red_) {
         tid = threadIdx.x;
         NT = blockDim.x;
         lane = tid & 63;
@@ -125,6 +124,8 @@ struct Block {
         ldsL = reinterpret_cast<uint32_t*>(lds + L.LL);
         for (int a = 0; a < 3; ++a) cc[a] = (T)d.c[a];
     }
+
+    DEV int WB(int l) const { return wbase(jmin, l); }
 
     // ----------------------------------------------------------- block scan
     // Exclusive prefix of per-thread values; returns this thread's base, total in *tot.
@@ -170,15 +171,15 @@ struct Block {
         for (int i = 0; i < per; ++i) {
             const int w = w0 + i;
             if (w >= wt) break;
-            while (w >= wb[l + 1]) ++l;
-            const int lw = w - wb[l];
-            const uint64_t r = r_word(sp, wb, jmin, l, lw);
+            while (w >= WB(l + 1)) ++l;
+            const int lw = w - WB(l);
+            const uint64_t r = r_word(sp, jmin, l, lw);
             R[w] = r;
             s += (uint32_t)__popcll(r);
             const uint64_t spw = (l < J) ? sp[w] : 0ull;
             if (spw) {
                 const int pos = atomicAdd(&sl.c[l], 1);
-                sl.w[wb[l] + pos] = (uint16_t)lw;
+                sl.w[WB(l) + pos] = (uint16_t)lw;
             }
             if (LW) {
                 const uint64_t lf = r & ~spw;
@@ -186,7 +187,7 @@ struct Block {
                 if (lf) {
                     nleaf += (uint32_t)__popcll(lf);
                     const int pos = atomicAdd(&ll.c[l], 1);
-                    ll.w[wb[l] + pos] = (uint16_t)lw;
+                    ll.w[WB(l) + pos] = (uint16_t)lw;
                 }
             }
         }
@@ -212,12 +213,12 @@ struct Block {
             const int n = sl.c[l];
             if (n == 0) continue;
             for (int t = wave; t < n; t += nwaves) {
-                const int w = sl.w[wb[l] + t];
-                const uint64_t b = sp[wb[l] + w];
+                const int w = sl.w[WB(l) + t];
+                const uint64_t b = sp[WB(l) + w];
                 if ((b >> lane) & 1ull) {
                     const int p = (w << 6) + lane;
-                    const int sc = rank_of(R, RP, wb, l + 1, 2 * p);
-                    const int sp_ = rank_of(R, RP, wb, l, p);
+                    const int sc = rank_of(R, RP, jmin, l + 1, 2 * p);
+                    const int sp_ = rank_of(R, RP, jmin, l, p);
 #pragma unroll
                     for (int h = 0; h < Q; ++h) Vx.st(h, sp_, (T)0.5 * (Vx.ld(h, sc) + Vx.ld(h, sc + 1)));
                 }
@@ -242,18 +243,18 @@ struct Block {
             const double thrb = ldexp(d.eps, d.mu_bar + 1 + l + 1 - J);
             const bool rb_level = (l + 1 < J);
             for (; t < n; t += nwaves) {
-                const int w = swl.w[wb[l] + t];
-                const uint64_t b = split[wb[l] + w];
+                const int w = swl.w[WB(l) + t];
+                const uint64_t b = split[WB(l) + w];
                 bool kb = false, rbb = false;
                 if ((b >> lane) & 1ull) {
                     const int p = (w << 6) + lane;
-                    const int sc = rank_of(ro, rpo, wb, l + 1, 2 * p);
-                    const int s0 = rank_of(ro, rpo, wb, l, p);
+                    const int sc = rank_of(ro, rpo, jmin, l + 1, 2 * p);
+                    const int s0 = rank_of(ro, rpo, jmin, l, p);
                     int sp_[G], sm_[G];
 #pragma unroll
                     for (int a = 1; a <= G; ++a) {
-                        sp_[a - 1] = rank_of(ro, rpo, wb, l, bcx(p + a, N, bc));
-                        sm_[a - 1] = rank_of(ro, rpo, wb, l, bcx(p - a, N, bc));
+                        sp_[a - 1] = rank_of(ro, rpo, jmin, l, bcx(p + a, N, bc));
+                        sm_[a - 1] = rank_of(ro, rpo, jmin, l, bcx(p - a, N, bc));
                     }
                     double D = 0.0;
                     bool bad = false;
@@ -279,8 +280,8 @@ struct Block {
                 const uint64_t kw = __ballot(kb);
                 const uint64_t rw = __ballot(rbb);
                 if (lane == 0) {
-                    keep[wb[l] + w] = kw;
-                    ruleb[wb[l] + w] = rw;
+                    keep[WB(l) + w] = kw;
+                    ruleb[WB(l) + w] = rw;
                 }
             }
             t -= n;
@@ -299,13 +300,13 @@ struct Block {
             for (; t < nw; t += NT) {
                 uint64_t v = 0;
                 if (l < J) {
-                    v = dilate_word(keep, wb[l], l, t, ra, bc);
+                    v = dilate_word(keep, WB(l), l, t, ra, bc);
                     if (l > jmin) {
-                        const uint64_t pb = ruleb[wb[l - 1] + (t >> 1)] >> ((t & 1) * 32);
+                        const uint64_t pb = ruleb[WB(l - 1) + (t >> 1)] >> ((t & 1) * 32);
                         v |= spread32(pb);
                     }
                 }
-                nsplit[wb[l] + t] = v;
+                nsplit[WB(l) + t] = v;
             }
             t -= nw;
         }
@@ -317,17 +318,31 @@ struct Block {
     // |delta| <= gamma, in R, so the parents of those cells are split. One sweep from the
     // finest level; delta = 0 also restores the tree property.
     DEV void grade() {
-        for (int a = J - 1; a > jmin; --a) {
-            const int pnw = nwords(a - 1);
-            const int cnw = nwords(a);
-            for (int pw = tid; pw < pnw; pw += NT) {
-                const int c0 = 2 * pw, c1 = 2 * pw + 1;
-                uint64_t v = 0;
-                if (c0 < cnw) v |= compress64(dilate_word(nsplit, wb[a], a, c0, G, bc));
-                if (c1 < cnw) v |= compress64(dilate_word(nsplit, wb[a], a, c1, G, bc)) << 32;
-                nsplit[wb[a - 1] + pw] |= v;
-            }
+        // one parent word per thread and a barrier per level while a level is wider than a
+        // wave; the remaining coarse levels in wave 0 alone (LDS order within a wave)
+        int a = J - 1;
+        for (; a > jmin && nwords(a - 1) > 64; --a) {
+            grade_level(a, tid, NT);
             __syncthreads();
+        }
+        if (wave == 0) {
+            for (; a > jmin; --a) {
+                grade_level(a, lane, 64);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            }
+        }
+        __syncthreads();
+    }
+
+    DEV void grade_level(int a, int t0, int stride) {
+        const int pnw = nwords(a - 1);
+        const int cnw = nwords(a);
+        for (int pw = t0; pw < pnw; pw += stride) {
+            const int c0 = 2 * pw, c1 = 2 * pw + 1;
+            uint64_t v = 0;
+            if (c0 < cnw) v |= compress64(dilate_word(nsplit, WB(a), a, c0, G, bc));
+            if (c1 < cnw) v |= compress64(dilate_word(nsplit, WB(a), a, c1, G, bc)) << 32;
+            nsplit[WB(a - 1) + pw] |= v;
         }
     }
 
@@ -342,18 +357,18 @@ struct Block {
         for (int l = jmin; l <= J; ++l) {
             const int n = lwl.c[l];
             for (; t < n; t += nwaves) {
-                const int w = lwl.w[wb[l] + t];
-                const uint64_t b = ruleb[wb[l] + w];
+                const int w = lwl.w[WB(l) + t];
+                const uint64_t b = ruleb[WB(l) + w];
                 if ((b >> lane) & 1ull) {
                     const int k = (w << 6) + lane;
                     T f[Q];
-                    if (rbit(ro, wb, l, k)) {
-                        const int so = rank_of(ro, rpo, wb, l, k);
+                    if (rbit(ro, jmin, l, k)) {
+                        const int so = rank_of(ro, rpo, jmin, l, k);
 #pragma unroll
                         for (int h = 0; h < Q; ++h) f[h] = VO.ld(h, so);
                     } else {
                         T g[Q];
-                        chain<T, G, Q, AllPops<S>>(VO, ro, rpo, wb, jmin, l, bc, cc, k, k, f, g);
+                        chain<T, G, Q, AllPops<S>>(VO, ro, rpo, jmin, l, bc, cc, k, k, f, g);
                     }
                     if (collide_mark) {
                         collide<T, S>(d.cf, f);
@@ -364,7 +379,7 @@ struct Block {
                         const int e = k << (J - l);
                         atomicOr((unsigned long long*)&E[e >> 6], 1ull << (e & 63));
                     }
-                    const int sn = rank_of(keep, rpn, wb, l, k);
+                    const int sn = rank_of(keep, rpn, jmin, l, k);
 #pragma unroll
                     for (int h = 0; h < Q; ++h) VN.st(h, sn, f[h]);
                 }
@@ -403,8 +418,8 @@ struct Block {
         for (int l = jmin; l <= J; ++l) {
             const int n = lwl.c[l];
             for (; t < n; t += nwaves) {
-                const int w = lwl.w[wb[l] + t];
-                const uint64_t b = ruleb[wb[l] + w];
+                const int w = lwl.w[WB(l) + t];
+                const uint64_t b = ruleb[WB(l) + w];
                 if ((b >> lane) & 1ull) {
                     const int k = (w << 6) + lane;
                     const int e = k << (J - l);
@@ -438,7 +453,7 @@ struct Block {
                 tB = tB > NJ - 1 ? NJ - 1 : tB;
             }
             T a[NM], b[NM];
-            chain<T, G, NM, MovingPops<S>>(Vx, keep, rpn, wb, jmin, J, bc, cc, tA, tB, a, b);
+            chain<T, G, NM, MovingPops<S>>(Vx, keep, rpn, jmin, J, bc, cc, tA, tB, a, b);
 #pragma unroll
             for (int m = 0; m < NM; ++m) {
                 P[(2 * m) * stride + i] = a[m];
@@ -456,7 +471,7 @@ struct Block {
         for (int i = tid; i < n; i += NT) {
             const uint32_t key = list[i];
             const int l = key >> 27, k = key & ((1u << 27) - 1u);
-            const int s = rank_of(keep, rpn, wb, l, k);
+            const int s = rank_of(keep, rpn, jmin, l, k);
 #pragma unroll
             for (int h = 0; h < Q; ++h) {
                 const int wh = Sch<S>::w(h);
@@ -511,7 +526,6 @@ template <typename T, int S, int G>
 __global__ __launch_bounds__(512) void k_steps(const Desc* __restrict__ descs, State* __restrict__ states,
                                                int nsteps, int mode, int cap, int capS) {
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ int s_wb[32];
     __shared__ uint32_t s_red[24];
     __shared__ int s_cnt[96];
     __shared__ int s_nan;
@@ -520,9 +534,8 @@ __global__ __launch_bounds__(512) void k_steps(const Desc* __restrict__ descs, S
     constexpr int Q = B_t::Q;
     const Desc& d = descs[blockIdx.x];
     const Layout lay = make_layout(d.jmin, d.jmax, cap, capS, d.q, d.nm, (int)sizeof(T));
-    B_t B(d, lay, lds, s_wb, s_red, s_cnt);
+    B_t B(d, lay, lds, s_red, s_cnt);
     const int Cg = (1 << (d.jmax + 1)) - (1 << d.jmin);  // slots of an HBM array
-    if (threadIdx.x <= 24) s_wb[threadIdx.x] = (threadIdx.x >= d.jmin) ? wbase(d.jmin, threadIdx.x) : 0;
     if (threadIdx.x == 0) s_nan = 0;
     if (threadIdx.x < 24) s_red[threadIdx.x] = 0;
     const int wsplit = wbase(d.jmin, d.jmax);
@@ -684,16 +697,14 @@ template <typename T, int S, int G>
 __global__ __launch_bounds__(512) void k_query(const Desc* __restrict__ descs, State* __restrict__ states,
                                                int where, int what, double* __restrict__ out) {
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ int s_wb[32];
     __shared__ uint32_t s_red[24];
     __shared__ int s_cnt[96];
     typedef Block<T, S, G> B_t;
     constexpr int Q = B_t::Q;
     const Desc& d = descs[blockIdx.x];
     const Layout lay = make_layout(d.jmin, d.jmax, 0, 0, d.q, d.nm, (int)sizeof(T));
-    B_t B(d, lay, lds, s_wb, s_red, s_cnt);
+    B_t B(d, lay, lds, s_red, s_cnt);
     const int Cg = (1 << (d.jmax + 1)) - (1 << d.jmin);
-    if (threadIdx.x <= 24) s_wb[threadIdx.x] = (threadIdx.x >= d.jmin) ? wbase(d.jmin, threadIdx.x) : 0;
     if (threadIdx.x < 24) s_red[threadIdx.x] = 0;
     const int wsplit = wbase(d.jmin, d.jmax);
     for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) B.split[w] = w < wsplit ? d.split[w] : 0ull;
@@ -711,8 +722,8 @@ __global__ __launch_bounds__(512) void k_query(const Desc* __restrict__ descs, S
         for (int l = B.jmin; l <= B.J; ++l) {
             const int nn = B.lwl.c[l];
             for (; t < nn; t += B.nwaves) {
-                const int w = B.lwl.w[s_wb[l] + t];
-                const uint64_t b = B.ruleb[s_wb[l] + w];
+                const int w = B.lwl.w[B.WB(l) + t];
+                const uint64_t b = B.ruleb[B.WB(l) + w];
                 if ((b >> B.lane) & 1ull) {
                     const int k = (w << 6) + B.lane;
                     const int e = k << (B.J - l);
@@ -729,7 +740,7 @@ __global__ __launch_bounds__(512) void k_query(const Desc* __restrict__ descs, S
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             const uint32_t key = d.list[i];
             const int l = key >> 27, k = key & ((1u << 27) - 1u);
-            const int s = rank_of(B.keep, B.rpn, s_wb, l, k);
+            const int s = rank_of(B.keep, B.rpn, B.jmin, l, k);
             T f[Q];
             for (int h = 0; h < Q; ++h) f[h] = V.ld(h, s);
             if (what == 0) {
@@ -745,7 +756,7 @@ __global__ __launch_bounds__(512) void k_query(const Desc* __restrict__ descs, S
         const int NJ = 1 << d.jmax;
         for (int m = threadIdx.x; m < NJ; m += blockDim.x) {
             T a[Q], b[Q];
-            chain<T, G, Q, AllPops<S>>(V, B.keep, B.rpn, s_wb, B.jmin, B.J, B.bc, B.cc, m, m, a, b);
+            chain<T, G, Q, AllPops<S>>(V, B.keep, B.rpn, B.jmin, B.J, B.bc, B.cc, m, m, a, b);
             if (what == 0) {
                 double mc[MAXQ];
                 conserved<T, S>(d.cf, a, mc);

@@ -74,6 +74,7 @@ SIGNATURES = {
     "mrlbm_batch_get_block": (c_int32, [c_void_p, _P(c_int32)]),
     "mrlbm_batch_set_capacity": (c_int32, [c_void_p, c_int32]),
     "mrlbm_batch_get_capacity": (c_int32, [c_void_p, _P(c_int32)]),
+    "mrlbm_batch_tune": (c_int32, [c_void_p, c_int32, _P(c_int32), _P(c_int32)]),
     "mrlbm_batch_destroy": (None, [c_void_p]),
     "mrlbm_batch_last_error": (ctypes.c_char_p, [c_void_p]),
 }
@@ -280,6 +281,11 @@ class Batch:
 
     def set_capacity(self, cells):
         _check(lib().mrlbm_batch_set_capacity(self.h, int(cells)), self._err)
+
+    def tune(self, trial_steps=20):
+        t, c = c_int32(), c_int32()
+        _check(lib().mrlbm_batch_tune(self.h, int(trial_steps), ctypes.byref(t), ctypes.byref(c)), self._err)
+        return t.value, c.value
 
     def get_capacity(self):
         t = c_int32()

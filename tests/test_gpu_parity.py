@@ -240,3 +240,23 @@ def test_onchip_capacity_does_not_change_results(cap):
             assert rel_err(b.moments(0), ora.leaf_conserved()) <= 1e-12
         b.close()
         ref.close()
+
+
+def test_tuner_keeps_state_and_results():
+    """The launch-shape tuner restores every run after its trials: a tuned batch continues
+    bit for bit like an untuned one."""
+    cases = [W.batch_instance(s, steps=0) for s in range(10)]
+    announce("tuner")
+    a = mrlbm.Batch([c[0] for c in cases], [c[1] for c in cases])
+    b = mrlbm.Batch([c[0] for c in cases], [c[1] for c in cases])
+    a.step(10)
+    b.step(10)
+    threads, cells = a.tune(5)
+    assert threads in (128, 256, 512) and cells >= 0
+    assert all(a.stats(i)["steps"] == 10 for i in range(len(cases)))
+    a.step(25)
+    b.step(25)
+    for i in range(len(cases)):
+        assert np.array_equal(a.moments(i), b.moments(i))
+    a.close()
+    b.close()
