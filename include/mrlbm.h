@@ -93,6 +93,8 @@ typedef struct {
     int32_t q_cons;       /* conserved moments per cell                                   */
     int32_t j_max;
     int64_t tree_cells;   /* #R(Lambda): cells of the complete tree (leaves + split cells) */
+    int64_t misses;       /* refinement predictor: declined pairs the judge found wrong     */
+    int64_t redos;        /* refinement predictor: steps redone after a miss                */
 } mrlbm_stats_t;
 
 typedef struct mrlbm_s* mrlbm_t;
@@ -178,6 +180,55 @@ int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int
 int mrlbm_batch_get_capacity(mrlbm_batch_t b, int32_t* cells);
 void mrlbm_batch_destroy(mrlbm_batch_t b);
 const char* mrlbm_batch_last_error(mrlbm_batch_t b);
+
+/* ---------------------------------------------------------------- refinement predictor
+ * Not part of the paper's method: a small network (32 inputs, two hidden layers of 64 ReLU
+ * units, one logit; bfloat16 parameters, float32 sums) stands in for enlargement rule (b)
+ * (Sec. 4.2, eq. HartenLossOfRegularity) on the pairs that rule would refine with
+ * D < gate * 2^(mu_bar+1) eps_l; rule (a) is unchanged. The paper's heuristic judges every
+ * step: a declined pair whose detail after the step still reaches the rule-(b) threshold is a
+ * miss (eq. DetailRatio); the step is then redone from t^n with the missed pairs refined, so
+ * the enlarged mesh never falls below what the judge demands. Runs with FP64 storage and
+ * gamma = 1. Parameter vector order: W1[64][32], b1[64], W2[64][64], b2[64], w3[64], b3.
+ * Features of a pair (split cell p of level l): d / (|d| + eps_{l+1}) of the details of the
+ * split cells p-2..p+2 for every population ([delta][population]; 0 where not split), then
+ * (l+1)/J, zero-padded to 32. */
+#define MRLBM_MLP_INPUTS 32
+#define MRLBM_MLP_PARAMS 6337
+enum mrlbm_predictor_mode { MRLBM_PRED_OFF = 0, MRLBM_PRED_LEARNED = 1, MRLBM_PRED_RECORD = 2 };
+
+/* Attach the predictor to every run of a handle. bf16_params: MRLBM_MLP_PARAMS bfloat16
+ * values (host, copied; required for MRLBM_PRED_LEARNED). MRLBM_PRED_RECORD: plain rule (b),
+ * and every rule-(b) pair of every step becomes a training sample (features at t^n, label 1
+ * when the pair's detail after the step still reaches the rule-(b) threshold, i.e. when
+ * declining it would have been a miss), up to
+ * sample_capacity samples (the buffer restarts empty at each call). MRLBM_PRED_OFF restores
+ * the plain method. */
+int mrlbm_set_predictor(mrlbm_t h, const uint16_t* bf16_params, int32_t mode, double gate, int64_t sample_capacity);
+int mrlbm_batch_set_predictor(mrlbm_batch_t b, const uint16_t* bf16_params, int32_t mode, double gate,
+                              int64_t sample_capacity);
+/* Recorded samples: X[n][MRLBM_MLP_INPUTS] and y[n] (host arrays of cap rows). */
+int mrlbm_samples(mrlbm_t h, float* X, float* y, int64_t cap, int64_t* n);
+int mrlbm_batch_samples(mrlbm_batch_t b, float* X, float* y, int64_t cap, int64_t* n);
+
+/* Training of the network on the GPU (weighted binary cross-entropy on the logit, Adam on
+ * float32 master parameters; forward and backward products on the matrix cores with
+ * bfloat16 operands). theta0: initial float32 parameters (host). */
+typedef struct mrlbm_mlp_s* mrlbm_mlp_t;
+int mrlbm_mlp_create(const float* theta0, mrlbm_mlp_t* out);
+/* Mean loss and its gradient (float32, MRLBM_MLP_PARAMS) on n host samples. */
+int mrlbm_mlp_loss_grad(mrlbm_mlp_t m, const float* X, const float* y, int64_t n, float pos_weight, float* loss,
+                        float* grad);
+/* epochs over n host samples in minibatches of `batch` (a multiple of 64), reshuffled from
+ * seed every epoch; *last_loss = mean minibatch loss of the last epoch. */
+int mrlbm_mlp_train(mrlbm_mlp_t m, const float* X, const float* y, int64_t n, int32_t epochs, int32_t batch, float lr,
+                    float pos_weight, uint64_t seed, float* last_loss);
+/* Current parameters: float32 master copy and/or the bfloat16 copy the steps use. */
+int mrlbm_mlp_params(mrlbm_mlp_t m, float* theta, uint16_t* bf16);
+/* Logits of n host feature rows with the bfloat16 parameters, as the steps compute them. */
+int mrlbm_mlp_logits(mrlbm_mlp_t m, const float* X, int64_t n, float* logits);
+void mrlbm_mlp_destroy(mrlbm_mlp_t m);
+const char* mrlbm_mlp_last_error(mrlbm_mlp_t m);
 
 #ifdef __cplusplus
 }

@@ -113,8 +113,22 @@ class AdaptiveMRLBM:
             keep[l] = self.split[l] & (D[l] >= thr)
         return keep
 
-    def enlarge(self, keep, D):
-        """H_eps applied to T_eps(Lambda^n), rules (a) and (b) united."""
+    def rule_b(self, keep, D):
+        """Pairs flagged by enlargement rule (b): kept detail (l+1, 2p) with J_min < l+1 < J and
+        D >= 2^(mu+1) eps_{l+1}, per parent level l (Sec. 4.2, eq. HartenLossOfRegularity)."""
+        J = self.jmax
+        out = {}
+        for l in range(self.jmin, J):
+            if l + 1 < J:
+                thr_b = float(np.ldexp(self.eps, self.mu_bar + 1 + (l + 1) - J))
+                out[l] = keep[l] & (D[l] >= thr_b)
+            else:
+                out[l] = np.zeros_like(keep[l])
+        return out
+
+    def enlarge(self, keep, D, rule_b=None):
+        """H_eps applied to T_eps(Lambda^n), rules (a) and (b) united. ``rule_b`` overrides the
+        cells where rule (b) refines (default: the paper's rule, or ``refine_rule``)."""
         J, jmin = self.jmax, self.jmin
         new = {l: keep[l].copy() for l in range(jmin, J)}
         sig = self.sch.sigma
@@ -129,10 +143,11 @@ class AdaptiveMRLBM:
                 new[l][idx // 2] = True
         # Rule (b): kept detail (l+1, 2p) with J_min < l+1 < J and D >= 2^(mu+1) eps_{l+1}
         # puts (l+2, 4p + delta), delta = 0..3, into R: both children of (l, p) split.
+        if rule_b is None and self.refine_rule is None:
+            rule_b = self.rule_b(keep, D)
         for l in range(jmin, J - 1):
-            if self.refine_rule is None:
-                thr_b = float(np.ldexp(self.eps, self.mu_bar + 1 + (l + 1) - J))
-                hit = keep[l] & (D[l] >= thr_b)
+            if rule_b is not None:
+                hit = rule_b[l]
             else:
                 hit = keep[l] & self.refine_rule(self, l, keep[l], D[l])
             p = np.nonzero(hit)[0]

@@ -33,7 +33,10 @@ def build_library(verbose=False, jobs=None):
     units = [("host", os.path.join(CSRC, "mrlbm.hip"), [])]
     for t in ("double", "float"):
         for s in range(4):
-            units.append((f"k_{t}_{s}", os.path.join(CSRC, "instances.hip"), [f"-DMRL_T={t}", f"-DMRL_S={s}"]))
+            lrn = "1" if t == "double" else "0"
+            units.append((f"k_{t}_{s}", os.path.join(CSRC, "instances.hip"),
+                          [f"-DMRL_T={t}", f"-DMRL_S={s}", f"-DMRL_LRN={lrn}"]))
+    units.append(("mlp", os.path.join(CSRC, "mlp.hip"), []))
     jobs = jobs or min(len(units), os.cpu_count() or 4)
     procs, objs, failed = [], [], []
     pending = list(units)

@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
 #include <string>
 #include <vector>
@@ -29,16 +30,26 @@ namespace mrl {
     extern template __global__ void k_steps<T, S, 3>(const Desc*, State*, int, int, int, int);   \
     extern template __global__ void k_query<T, S, 1>(const Desc*, State*, int, int, double*);    \
     extern template __global__ void k_query<T, S, 2>(const Desc*, State*, int, int, double*);    \
-    extern template __global__ void k_query<T, S, 3>(const Desc*, State*, int, int, double*);
+    extern template __global__ void k_query<T, S, 3>(const Desc*, State*, int, int, double*);          \
+    extern template __global__ void k_steps<T, S, 1, true>(const Desc*, State*, int, int, int, int);
 MRL_EXTERN(double, 0)
 MRL_EXTERN(double, 1)
 MRL_EXTERN(double, 2)
 MRL_EXTERN(double, 3)
-MRL_EXTERN(float, 0)
-MRL_EXTERN(float, 1)
-MRL_EXTERN(float, 2)
-MRL_EXTERN(float, 3)
 #undef MRL_EXTERN
+#define MRL_EXTERN32(T, S)                                                                      \
+    extern template __global__ void k_init<T, S>(const Desc*, State*, const double*, long long); \
+    extern template __global__ void k_steps<T, S, 1>(const Desc*, State*, int, int, int, int);   \
+    extern template __global__ void k_steps<T, S, 2>(const Desc*, State*, int, int, int, int);   \
+    extern template __global__ void k_steps<T, S, 3>(const Desc*, State*, int, int, int, int);   \
+    extern template __global__ void k_query<T, S, 1>(const Desc*, State*, int, int, double*);    \
+    extern template __global__ void k_query<T, S, 2>(const Desc*, State*, int, int, double*);    \
+    extern template __global__ void k_query<T, S, 3>(const Desc*, State*, int, int, double*);
+MRL_EXTERN32(float, 0)
+MRL_EXTERN32(float, 1)
+MRL_EXTERN32(float, 2)
+MRL_EXTERN32(float, 3)
+#undef MRL_EXTERN32
 }  // namespace mrl
 
 using namespace mrl;
@@ -72,6 +83,13 @@ struct Engine {
     hipGraphExec_t gexec = nullptr;
     int gsteps = -1, gnt = -1, gcap = -1;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // refinement predictor
+    bool lrn = false;             // launch the predictor-capable kernels
+    uint16_t* d_mlp = nullptr;
+    float* d_samples = nullptr;
+    unsigned int* d_nsamples = nullptr;
+    long long sample_cap = 0;    // samples the current record may hold
+    long long sample_alloc = 0;  // rows of d_samples
 };
 
 thread_local std::string g_create_error;
@@ -190,7 +208,7 @@ void choose_capacity(Engine* e) {
         size_t t = 0;
         for (auto& d : e->hd) {
             const int capS = cap > 0 ? cap / 2 + (1 << d.jmin) : 0;
-            t = std::max(t, (size_t)make_layout(d.jmin, d.jmax, cap, capS, d.q, d.nm, tsz).total);
+            t = std::max(t, (size_t)make_layout(d.jmin, d.jmax, cap, capS, d.q, d.nm, tsz, e->lrn).total);
         }
         return t;
     };
@@ -220,6 +238,15 @@ template <typename T, int S, int G>
 void pick(StepK* s, QueryK* q) {
     *s = k_steps<T, S, G>;
     *q = k_query<T, S, G>;
+}
+
+StepK lrn_kernel(int scheme) {
+    switch (scheme) {
+        case 0: return k_steps<double, 0, 1, true>;
+        case 1: return k_steps<double, 1, 1, true>;
+        case 2: return k_steps<double, 2, 1, true>;
+        default: return k_steps<double, 3, 1, true>;
+    }
 }
 
 bool kernels_for(int prec, int scheme, int gamma, StepK* s, QueryK* q, InitK* in) {
@@ -260,6 +287,9 @@ void engine_free(Engine* e) {
     if (e->ev0) (void)hipEventDestroy(e->ev0);
     if (e->ev1) (void)hipEventDestroy(e->ev1);
     if (e->stage) (void)hipFree(e->stage);
+    if (e->d_mlp) (void)hipFree(e->d_mlp);
+    if (e->d_samples) (void)hipFree(e->d_samples);
+    if (e->d_nsamples) (void)hipFree(e->d_nsamples);
     if (e->pool) (void)hipFree(e->pool);
     if (e->dd) (void)hipFree(e->dd);
     if (e->ds) (void)hipFree(e->ds);
@@ -436,6 +466,7 @@ int launch_steps(Engine* e, int nsteps, int mode, bool use_graph) {
     QueryK qk;
     InitK ik;
     kernels_for(e->prec, e->scheme, e->gamma, &sk, &qk, &ik);
+    if (e->lrn) sk = lrn_kernel(e->scheme);
     const int nt = e->nt_user ? e->nt_user : e->nt;
     hipError_t st;
     if (use_graph && mode == (MODE_ADAPT | MODE_SCHEME)) {
@@ -556,6 +587,8 @@ int engine_stats(Engine* e, int inst, mrlbm_stats_t* st) {
     st->q_cons = e->hd[inst].qc;
     st->j_max = e->hd[inst].jmax;
     st->tree_cells = s.n_r;
+    st->misses = s.misses;
+    st->redos = s.redos;
     return MRLBM_OK;
 }
 
@@ -807,6 +840,107 @@ int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int
     if (threads) *threads = best_nt;
     if (cells) *cells = e->cap;
     return check_numeric(e);
+}
+
+static int set_predictor(Engine* e, const uint16_t* params, int32_t mode, double gate, int64_t sample_capacity) {
+    if (mode < MRLBM_PRED_OFF || mode > MRLBM_PRED_RECORD || (mode == MRLBM_PRED_LEARNED && !params) ||
+        !(gate > 0.0) || !std::isfinite(gate) || sample_capacity < 0 || sample_capacity > (1ll << 28)) {
+        e->err = "bad predictor arguments";
+        return MRLBM_EINVAL;
+    }
+    if (mode != MRLBM_PRED_OFF && (e->prec != MRLBM_FP64 || e->gamma != 1)) {
+        e->err = "the refinement predictor runs with FP64 storage and gamma = 1";
+        return MRLBM_EINVAL;
+    }
+    // steps still in flight on the handle's stream read the weights and samples replaced here
+    hipError_t st = hipStreamSynchronize(e->stream);
+    if (st != hipSuccess) return hip_fail(e, st, "set_predictor");
+    if (params) {
+        if (!e->d_mlp && (st = hipMalloc(&e->d_mlp, sizeof(uint16_t) * MLP_NPARAM)) != hipSuccess)
+            return hip_fail(e, st, "hipMalloc(predictor)");
+        if ((st = hipMemcpy(e->d_mlp, params, sizeof(uint16_t) * MLP_NPARAM, hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, st, "hipMemcpy(predictor)");
+    }
+    if (mode == MRLBM_PRED_RECORD && sample_capacity > e->sample_alloc) {
+        // the old buffer stays valid (and in use by the descriptors) until the new one exists
+        float* nb = nullptr;
+        if ((st = hipMalloc(&nb, sizeof(float) * (MLP_IN + 1) * sample_capacity)) != hipSuccess)
+            return hip_fail(e, st, "hipMalloc(samples)");
+        if (e->d_samples) (void)hipFree(e->d_samples);
+        e->d_samples = nb;
+        e->sample_alloc = sample_capacity;
+    }
+    e->sample_cap = mode == MRLBM_PRED_RECORD ? sample_capacity : 0;
+    if (mode == MRLBM_PRED_RECORD && !e->d_nsamples) {
+        if ((st = hipMalloc(&e->d_nsamples, sizeof(unsigned int))) != hipSuccess) return hip_fail(e, st, "hipMalloc");
+    }
+    if (e->d_nsamples) (void)hipMemsetAsync(e->d_nsamples, 0, sizeof(unsigned int), e->stream);
+    for (auto& d : e->hd) {
+        d.mlp = e->d_mlp;
+        d.pmode = mode;
+        d.gate = gate;
+        d.samples = e->d_samples;
+        d.nsamples = e->d_nsamples;
+        d.sample_cap = (int)e->sample_cap;
+    }
+    if ((st = hipMemcpyAsync(e->dd, e->hd.data(), sizeof(Desc) * e->n, hipMemcpyHostToDevice, e->stream)) != hipSuccess)
+        return hip_fail(e, st, "hipMemcpy(desc)");
+    if ((st = hipStreamSynchronize(e->stream)) != hipSuccess) return hip_fail(e, st, "set_predictor");
+    e->lrn = mode != MRLBM_PRED_OFF;
+    choose_capacity(e);
+    if (e->lrn)
+        (void)hipFuncSetAttribute((const void*)lrn_kernel(e->scheme), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)e->lds);
+    e->gsteps = -1;  // the captured graph is stale
+    return MRLBM_OK;
+}
+
+static int get_samples(Engine* e, float* X, float* y, int64_t cap, int64_t* n) {
+    if (!n) return MRLBM_EINVAL;
+    unsigned int cnt = 0;
+    if (e->d_nsamples) {
+        // the steps run on the handle's own stream (non-blocking): read behind them
+        hipError_t st = hipMemcpyAsync(&cnt, e->d_nsamples, sizeof(unsigned int), hipMemcpyDeviceToHost, e->stream);
+        if (st == hipSuccess) st = hipStreamSynchronize(e->stream);
+        if (st != hipSuccess) return hip_fail(e, st, "samples");
+    }
+    const int64_t have = std::min<int64_t>(cnt, e->sample_cap);
+    *n = have;
+    if (!X || !y || cap < have) {
+        e->err = "output capacity too small";
+        return MRLBM_ECAPACITY;
+    }
+    if (have == 0) return MRLBM_OK;
+    std::vector<float> buf((size_t)have * (MLP_IN + 1));
+    hipError_t st = hipMemcpyAsync(buf.data(), e->d_samples, sizeof(float) * buf.size(), hipMemcpyDeviceToHost, e->stream);
+    if (st == hipSuccess) st = hipStreamSynchronize(e->stream);
+    if (st != hipSuccess) return hip_fail(e, st, "samples");
+    for (int64_t i = 0; i < have; ++i) {
+        for (int k = 0; k < MLP_IN; ++k) X[i * MLP_IN + k] = buf[i * (MLP_IN + 1) + k];
+        y[i] = buf[i * (MLP_IN + 1) + MLP_IN];
+    }
+    return MRLBM_OK;
+}
+
+int mrlbm_batch_set_predictor(mrlbm_batch_t b, const uint16_t* bf16_params, int32_t mode, double gate,
+                              int64_t sample_capacity) {
+    if (!b) return MRLBM_EINVAL;
+    return set_predictor(b->e, bf16_params, mode, gate, sample_capacity);
+}
+
+int mrlbm_batch_samples(mrlbm_batch_t b, float* X, float* y, int64_t cap, int64_t* n) {
+    if (!b) return MRLBM_EINVAL;
+    return get_samples(b->e, X, y, cap, n);
+}
+
+int mrlbm_set_predictor(mrlbm_t h, const uint16_t* bf16_params, int32_t mode, double gate, int64_t sample_capacity) {
+    if (!h) return MRLBM_EINVAL;
+    return set_predictor(h->e, bf16_params, mode, gate, sample_capacity);
+}
+
+int mrlbm_samples(mrlbm_t h, float* X, float* y, int64_t cap, int64_t* n) {
+    if (!h) return MRLBM_EINVAL;
+    return get_samples(h->e, X, y, cap, n);
 }
 
 int mrlbm_batch_get_block(mrlbm_batch_t b, int32_t* threads) {

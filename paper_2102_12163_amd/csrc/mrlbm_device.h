@@ -42,6 +42,13 @@ struct Desc {
     uint64_t* split;
     uint32_t* list;
     void* pairs;
+    // refinement predictor (shared by the runs of a handle)
+    const uint16_t* mlp;    // bfloat16 parameters, or null
+    int pmode;              // 0 off, 1 learned rule (b) with judge, 2 record training samples
+    int sample_cap;
+    double gate;            // the network decides only pairs with D < gate * rule-(b) threshold
+    float* samples;         // [sample_cap][33]: 32 features and the label
+    unsigned int* nsamples;
 };
 
 struct State {
@@ -50,6 +57,7 @@ struct State {
     int flags;  // bit 0: NaN met
     int n_r;    // #R(Lambda) of the current tree
     int pad;
+    long long misses, redos;  // predictor: judged misses and redone steps
 };
 
 #define DEV __device__ __forceinline__

@@ -12,6 +12,7 @@
 // The home copy in HBM is read at launch start and written at launch end.
 #pragma once
 
+#include "mlp.h"
 #include "mrlbm_device.h"
 
 namespace mrl {
@@ -28,7 +29,8 @@ struct Layout {
     unsigned bits, E, VA, VB, PP, rp, scanE, LL, wl, total;
 };
 __host__ __device__ inline unsigned al16(unsigned x) { return (x + 15u) & ~15u; }
-__host__ __device__ inline Layout make_layout(int jmin, int J, int cap, int capS, int q, int nm, int tsz) {
+__host__ __device__ inline Layout make_layout(int jmin, int J, int cap, int capS, int q, int nm, int tsz,
+                                              bool learned = false) {
     Layout L;
     L.wt = wbase(jmin, J + 1);
     L.nwJ = nwords(J);
@@ -36,7 +38,7 @@ __host__ __device__ inline Layout make_layout(int jmin, int J, int cap, int capS
     L.capS = capS;
     unsigned o = 0;
     L.bits = o;
-    o = al16(o + 5u * (unsigned)L.wt * 8u);
+    o = al16(o + (learned ? 7u : 5u) * (unsigned)L.wt * 8u);
     L.E = o;
     o = al16(o + (unsigned)L.nwJ * 8u);
     L.VA = o;
@@ -64,7 +66,7 @@ struct WordList {
     int* c;
 };
 
-template <typename T, int S, int G>
+template <typename T, int S, int G, bool LRN = false>
 struct Block {
     static constexpr int Q = Sch<S>::Q;
     static constexpr int NM = Sch<S>::NM;
@@ -81,6 +83,8 @@ struct Block {
     uint64_t* keep;   // T_eps bits; then R bits of Lambda^{n+1}
     uint64_t* ruleb;  // rule (b) bits; then leaf bits of Lambda^{n+1}
     uint64_t* ro;     // R bits of Lambda^n
+    uint64_t* forced;   // predictor: rule (b) pairs the judge forces (this step)
+    uint64_t* declined; // predictor: pairs the network declined / recorded candidates
     uint32_t* rpo;    // slot prefix of Lambda^n
     uint32_t* rpn;    // slot prefix of Lambda^{n+1}
     WordList swl, nswl, lwl;  // split words of Lambda^n, of Lambda^{n+1}; leaf words of Lambda^{n+1}
@@ -109,6 +113,8 @@ struct Block {
         keep = bits + 2 * wt;
         ruleb = bits + 3 * wt;
         ro = bits + 4 * wt;
+        forced = LRN ? bits + 5 * wt : nullptr;
+        declined = LRN ? bits + 6 * wt : nullptr;
         E = reinterpret_cast<uint64_t*>(lds + L.E);
         uint32_t* rp = reinterpret_cast<uint32_t*>(lds + L.rp);
         rpo = rp;
@@ -233,6 +239,72 @@ struct Block {
     // rule (b) iff kept, l+1 < J and D >= 2^(mu+1) eps_{l+1} (Sec. 4.2). One wave per split
     // word; __ballot turns the 64 lane decisions into the keep / ruleb words. keep and ruleb
     // must be zero beforehand (only words with split cells are written).
+    // Features of a candidate pair (l, p) from the values of Lambda^n: for the split cells
+    // p-2..p+2 and every population, d / (|d| + eps_{l+1}) (0 for cells that are not split),
+    // then (l + 1) / J. Same detail arithmetic as details().
+    template <class V>
+    DEV void features(const V& Vx, int l, int p, float* x) {
+        const int N = 1 << l;
+        const double el = ldexp(d.eps, l + 1 - J);
+#pragma unroll
+        for (int i = 0; i < MLP_IN; ++i) x[i] = 0.f;
+#pragma unroll
+        for (int di = 0; di < 5; ++di) {
+            const int c = bcx(p + di - 2, N, bc);
+            if (getbit(split, WB(l), c)) {
+                const int sc = rank_of(ro, rpo, jmin, l + 1, 2 * c);
+                const int s0 = rank_of(ro, rpo, jmin, l, c);
+                int sp_[G], sm_[G];
+#pragma unroll
+                for (int a = 1; a <= G; ++a) {
+                    sp_[a - 1] = rank_of(ro, rpo, jmin, l, bcx(c + a, N, bc));
+                    sm_[a - 1] = rank_of(ro, rpo, jmin, l, bcx(c - a, N, bc));
+                }
+#pragma unroll
+                for (int h = 0; h < Q; ++h) {
+                    const double f0 = (double)Vx.ld(h, s0);
+                    double acc = 0.0;
+#pragma unroll
+                    for (int a = 1; a <= G; ++a) {
+                        const double tt = d.c[a - 1] * ((double)Vx.ld(h, sp_[a - 1]) - (double)Vx.ld(h, sm_[a - 1]));
+                        acc = (a == 1) ? tt : acc + tt;
+                    }
+                    const double dd = (double)Vx.ld(h, sc) - (f0 + acc);
+                    x[di * Q + h] = (float)(dd / (fabs(dd) + el));
+                }
+            }
+        }
+        x[5 * Q] = (float)((double)(l + 1) / (double)J);
+    }
+
+    // Max over populations of |d| for the split cell (l, p) of a tree (R bits, slot prefix).
+    template <class V>
+    DEV double max_detail(const V& Vx, const uint64_t* R, const uint32_t* RP, int l, int p) {
+        const int N = 1 << l;
+        const int sc = rank_of(R, RP, jmin, l + 1, 2 * p);
+        const int s0 = rank_of(R, RP, jmin, l, p);
+        int sp_[G], sm_[G];
+#pragma unroll
+        for (int a = 1; a <= G; ++a) {
+            sp_[a - 1] = rank_of(R, RP, jmin, l, bcx(p + a, N, bc));
+            sm_[a - 1] = rank_of(R, RP, jmin, l, bcx(p - a, N, bc));
+        }
+        double D = 0.0;
+#pragma unroll
+        for (int h = 0; h < Q; ++h) {
+            const double f0 = (double)Vx.ld(h, s0);
+            double acc = 0.0;
+#pragma unroll
+            for (int a = 1; a <= G; ++a) {
+                const double tt = d.c[a - 1] * ((double)Vx.ld(h, sp_[a - 1]) - (double)Vx.ld(h, sm_[a - 1]));
+                acc = (a == 1) ? tt : acc + tt;
+            }
+            const double ad = fabs((double)Vx.ld(h, sc) - (f0 + acc));
+            D = ad > D ? ad : D;
+        }
+        return D;
+    }
+
     template <class V>
     DEV void details(const V& Vx, int* nanflag) {
         int t = wave;
@@ -245,7 +317,7 @@ struct Block {
             for (; t < n; t += nwaves) {
                 const int w = swl.w[WB(l) + t];
                 const uint64_t b = split[WB(l) + w];
-                bool kb = false, rbb = false;
+                bool kb = false, rbb = false, rbu = false;
                 if ((b >> lane) & 1ull) {
                     const int p = (w << 6) + lane;
                     const int sc = rank_of(ro, rpo, jmin, l + 1, 2 * p);
@@ -276,13 +348,24 @@ struct Block {
                     if (bad) *nanflag = 1;
                     kb = bad || (D >= thr);
                     rbb = kb && rb_level && (bad || D >= thrb);
+                    rbu = rbb;
+                    if constexpr (LRN) {
+                        if (d.pmode == 1 && d.mlp && rbb && !getbit(forced, WB(l), p) && D < d.gate * thrb) {
+                            float x[MLP_IN];
+                            features(Vx, l, p, x);
+                            rbu = mlp_logit_seq(d.mlp, x) >= 0.f;
+                        }
+                    }
                 }
                 const uint64_t kw = __ballot(kb);
                 const uint64_t rw = __ballot(rbb);
+                const uint64_t uw = __ballot(rbu);
                 if (lane == 0) {
                     keep[WB(l) + w] = kw;
-                    ruleb[WB(l) + w] = rw;
+                    ruleb[WB(l) + w] = uw;
+                    if constexpr (LRN) declined[WB(l) + w] = d.pmode == 1 ? (rw & ~uw) : (d.pmode == 2 ? rw : 0ull);
                 }
+                (void)rw;
             }
             t -= n;
         }
@@ -497,6 +580,51 @@ struct Block {
         __syncthreads();
     }
 
+    // ----------------------------------------------------------- predictor: judge / record
+    // After the step (VN holds f^{n+1} on Lambda^{n+1}, its split cells projected). Learned
+    // mode: a declined pair whose new detail still reaches the rule-(b) threshold is a miss;
+    // it is forced for the redo; returns the number of misses. Record mode: every rule-(b)
+    // pair becomes a sample, features from t^n, label 1 when declining it would have been
+    // a miss.
+    template <class VO_, class VN_>
+    DEV void judge_or_record(const VO_& VO, const VN_& VN, int* s_miss) {
+        int t = wave;
+        for (int l = jmin; l < J; ++l) {
+            const int n = nswl.c[l];
+            const double thrb = ldexp(d.eps, d.mu_bar + 1 + l + 1 - J);
+            for (; t < n; t += nwaves) {
+                const int w = nswl.w[WB(l) + t];
+                const uint64_t dec = declined[WB(l) + w];
+                if (!dec) continue;
+                bool miss = false;
+                if ((dec >> lane) & 1ull) {
+                    const int p = (w << 6) + lane;
+                    const bool over = max_detail(VN, keep, rpn, l, p) >= thrb;
+                    if (d.pmode == 1) {
+                        miss = over;
+                    } else {
+                        const unsigned slot = atomicAdd(d.nsamples, 1u);
+                        if (slot < (unsigned)d.sample_cap) {
+                            float x[MLP_IN];
+                            features(VO, l, p, x);
+                            float* o = d.samples + (size_t)slot * (MLP_IN + 1);
+#pragma unroll
+                            for (int i = 0; i < MLP_IN; ++i) o[i] = x[i];
+                            o[MLP_IN] = over ? 1.f : 0.f;
+                        }
+                    }
+                }
+                const uint64_t mw = __ballot(miss);
+                if (lane == 0 && mw) {
+                    forced[WB(l) + w] |= mw;
+                    atomicAdd(s_miss, __popcll(mw));
+                }
+            }
+            t -= n;
+        }
+        __syncthreads();
+    }
+
     // ----------------------------------------------------------- rotation
     DEV void rotate() {
         uint64_t* t = split;
@@ -521,22 +649,27 @@ template <typename T>
 DEV T* hbm_vals(const Desc& d, int which) { return reinterpret_cast<T*>(which ? d.vb : d.va); }
 
 // nsteps time steps (or adaptations only) of run blockIdx.x. cap / capS: on-chip capacity in
-// R(Lambda) cells and in leaves (0 = always use the HBM arrays).
-template <typename T, int S, int G>
+// R(Lambda) cells and in leaves (0 = always use the HBM arrays). LRN: the variant that can run
+// the refinement predictor (d.pmode != 0).
+template <typename T, int S, int G, bool LRN = false>
 __global__ __launch_bounds__(512) void k_steps(const Desc* __restrict__ descs, State* __restrict__ states,
                                                int nsteps, int mode, int cap, int capS) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t s_red[24];
     __shared__ int s_cnt[96];
     __shared__ int s_nan;
-    typedef Block<T, S, G> B_t;
+    __shared__ int s_miss;
+    typedef Block<T, S, G, LRN> B_t;
     typedef typename B_t::LT LT;
     constexpr int Q = B_t::Q;
     const Desc& d = descs[blockIdx.x];
-    const Layout lay = make_layout(d.jmin, d.jmax, cap, capS, d.q, d.nm, (int)sizeof(T));
+    const Layout lay = make_layout(d.jmin, d.jmax, cap, capS, d.q, d.nm, (int)sizeof(T), LRN);
     B_t B(d, lay, lds, s_red, s_cnt);
     const int Cg = (1 << (d.jmax + 1)) - (1 << d.jmin);  // slots of an HBM array
-    if (threadIdx.x == 0) s_nan = 0;
+    if (threadIdx.x == 0) {
+        s_nan = 0;
+        s_miss = 0;
+    }
     if (threadIdx.x < 24) s_red[threadIdx.x] = 0;
     const int wsplit = wbase(d.jmin, d.jmax);
     for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) B.split[w] = w < wsplit ? d.split[w] : 0ull;
@@ -557,63 +690,102 @@ __global__ __launch_bounds__(512) void k_steps(const Desc* __restrict__ descs, S
             __syncthreads();
         }
     }
-    long long upd = 0;
+    const bool scheme = (mode & MODE_SCHEME) != 0;
+    const bool judge = LRN && scheme && (d.pmode == 2 || (d.pmode == 1 && d.mlp != nullptr));
+    long long upd = 0, misses = 0, redos = 0;
     int last = -1;
     bool last_fast = false;
     for (int stp = 0; stp < nsteps; ++stp) {
-        // ---- adaptation on the old tree
-        for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) {
-            B.keep[w] = 0ull;
-            B.ruleb[w] = 0ull;
-        }
-        __syncthreads();
+        // ---- projection of f^n up the old tree (once per step, kept through redos)
+        if constexpr (LRN)
+            for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) B.forced[w] = 0ull;
         if (where <= IN_LDS_B) {
             VP<T, LT> VO{where == IN_LDS_A ? B.ldsA : B.ldsB, cap};
             B.project_up(VO, B.split, B.ro, B.rpo, B.swl);
-            B.details(VO, &s_nan);
         } else {
             VP<T, T> VO{hbm_vals<T>(d, where - IN_HBM_0), Cg};
             B.project_up(VO, B.split, B.ro, B.rpo, B.swl);
-            B.details(VO, &s_nan);
         }
-        __syncthreads();
-        B.enlarge();
-        B.grade();
-        B.build_tree(B.nsplit, B.keep, B.rpn, B.nswl, B.ruleb, B.lwl);
-        const int nR = (int)B.rpn[lay.wt];
-        const int n = (int)B.red[0];
-        const bool scheme = (mode & MODE_SCHEME) != 0;
-        // ---- new values: on chip when the new tree fits
-        int nwhere;
-        if (where <= IN_LDS_B) nwhere = (nR <= cap) ? (IN_LDS_B - where) : IN_HBM_0;
-        else nwhere = (nR <= cap) ? IN_LDS_A : (where == IN_HBM_0 ? IN_HBM_1 : IN_HBM_0);
-        const bool fast = (where <= IN_LDS_B) && (nwhere <= IN_LDS_B) && (n <= capS);
-        if (fast) {
-            VP<T, LT> VO{where == IN_LDS_A ? B.ldsA : B.ldsB, cap};
-            VP<T, LT> VN{nwhere == IN_LDS_A ? B.ldsA : B.ldsB, cap};
-            B.transfer(VO, VN, scheme, &s_nan);
-            if (scheme) {
-                B.scan_edges();
-                B.write_list(B.ldsL);
-                B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
-                B.pairs(VN, B.ldsL, B.ldsP, n);
-                B.combine(VN, B.ldsL, B.ldsP, n);
+        int nwhere = where, n = 0;
+        bool fast = false;
+        int attempt = 0;
+        for (;;) {
+            // ---- adaptation on the old tree
+            for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) {
+                B.keep[w] = 0ull;
+                B.ruleb[w] = 0ull;
+                if constexpr (LRN) B.declined[w] = 0ull;
             }
-        } else {
-            T* po = where <= IN_LDS_B ? (T*)(where == IN_LDS_A ? B.ldsA : B.ldsB) : hbm_vals<T>(d, where - IN_HBM_0);
-            const int so = where <= IN_LDS_B ? cap : Cg;
-            T* pn = nwhere <= IN_LDS_B ? (T*)(nwhere == IN_LDS_A ? B.ldsA : B.ldsB) : hbm_vals<T>(d, nwhere - IN_HBM_0);
-            const int sn = nwhere <= IN_LDS_B ? cap : Cg;
-            VP<T, T> VO{po, so};
-            VP<T, T> VN{pn, sn};
-            B.transfer(VO, VN, scheme, &s_nan);
-            if (scheme) {
-                B.scan_edges();
-                B.write_list(d.list);
-                B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
-                T* P = reinterpret_cast<T*>(d.pairs);
-                B.pairs(VN, d.list, P, n);
-                B.combine(VN, d.list, P, n);
+            __syncthreads();
+            if (where <= IN_LDS_B) {
+                VP<T, LT> VO{where == IN_LDS_A ? B.ldsA : B.ldsB, cap};
+                B.details(VO, &s_nan);
+            } else {
+                VP<T, T> VO{hbm_vals<T>(d, where - IN_HBM_0), Cg};
+                B.details(VO, &s_nan);
+            }
+            __syncthreads();
+            B.enlarge();
+            B.grade();
+            B.build_tree(B.nsplit, B.keep, B.rpn, B.nswl, B.ruleb, B.lwl);
+            const int nR = (int)B.rpn[lay.wt];
+            n = (int)B.red[0];
+            // ---- new values: on chip when the new tree fits
+            if (where <= IN_LDS_B) nwhere = (nR <= cap) ? (IN_LDS_B - where) : IN_HBM_0;
+            else nwhere = (nR <= cap) ? IN_LDS_A : (where == IN_HBM_0 ? IN_HBM_1 : IN_HBM_0);
+            fast = (where <= IN_LDS_B) && (nwhere <= IN_LDS_B) && (n <= capS);
+            if (threadIdx.x == 0) s_miss = 0;
+            if (fast) {
+                VP<T, LT> VO{where == IN_LDS_A ? B.ldsA : B.ldsB, cap};
+                VP<T, LT> VN{nwhere == IN_LDS_A ? B.ldsA : B.ldsB, cap};
+                B.transfer(VO, VN, scheme, &s_nan);
+                if (scheme) {
+                    B.scan_edges();
+                    B.write_list(B.ldsL);
+                    B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
+                    B.pairs(VN, B.ldsL, B.ldsP, n);
+                    B.combine(VN, B.ldsL, B.ldsP, n);
+                }
+                if constexpr (LRN) {
+                    if (judge) {
+                        B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
+                        B.judge_or_record(VO, VN, &s_miss);
+                    }
+                }
+            } else {
+                T* po = where <= IN_LDS_B ? (T*)(where == IN_LDS_A ? B.ldsA : B.ldsB) : hbm_vals<T>(d, where - IN_HBM_0);
+                const int so = where <= IN_LDS_B ? cap : Cg;
+                T* pn = nwhere <= IN_LDS_B ? (T*)(nwhere == IN_LDS_A ? B.ldsA : B.ldsB) : hbm_vals<T>(d, nwhere - IN_HBM_0);
+                const int sn = nwhere <= IN_LDS_B ? cap : Cg;
+                VP<T, T> VO{po, so};
+                VP<T, T> VN{pn, sn};
+                B.transfer(VO, VN, scheme, &s_nan);
+                if (scheme) {
+                    B.scan_edges();
+                    B.write_list(d.list);
+                    B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
+                    T* P = reinterpret_cast<T*>(d.pairs);
+                    B.pairs(VN, d.list, P, n);
+                    B.combine(VN, d.list, P, n);
+                }
+                if constexpr (LRN) {
+                    if (judge) {
+                        B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
+                        B.judge_or_record(VO, VN, &s_miss);
+                    }
+                }
+            }
+            if (!judge || d.pmode != 1) break;
+            const int nm = s_miss;  // written before the barrier that ends judge_or_record
+            if (nm == 0) break;
+            misses += nm;
+            ++redos;
+            ++attempt;
+            __syncthreads();
+            if constexpr (LRN) {
+                // after a few redos every rule-(b) pair is forced: the plain rule, no misses
+                if (attempt >= 8)
+                    for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) B.forced[w] = ~0ull;
             }
         }
         B.rotate();
@@ -651,6 +823,8 @@ __global__ __launch_bounds__(512) void k_steps(const Desc* __restrict__ descs, S
             if (last >= 0) st.n_leaves = last;
         }
         st.n_r = nR;
+        st.misses += misses;
+        st.redos += redos;
         if (s_nan) st.flags |= 1;
     }
 }
@@ -687,6 +861,8 @@ __global__ void k_init(const Desc* __restrict__ descs, State* __restrict__ state
         s.n_r = Cg;
         s.cur = 0;
         s.flags = 0;
+        s.misses = 0;
+        s.redos = 0;
     }
 }
 

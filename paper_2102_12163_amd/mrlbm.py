@@ -21,6 +21,8 @@ PERIODIC, CLAMP = 0, 1
 FP64, FP32_STORAGE = 0, 1
 LEAVES, FINEST = 0, 1
 MAX_J = 16
+PRED_OFF, PRED_LEARNED, PRED_RECORD = 0, 1, 2
+MLP_INPUTS, MLP_PARAMS = 32, 6337
 
 _STATUS = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENUMERIC: "ENUMERIC",
            ECAPACITY: "ECAPACITY", ESTATE: "ESTATE"}
@@ -40,7 +42,7 @@ class Params(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("steps", c_int64), ("leaves", c_int64), ("leaf_updates", c_int64),
                 ("numeric_error", c_int32), ("q", c_int32), ("q_cons", c_int32), ("j_max", c_int32),
-                ("tree_cells", c_int64)]
+                ("tree_cells", c_int64), ("misses", c_int64), ("redos", c_int64)]
 
 
 class MRLBMError(RuntimeError):
@@ -75,6 +77,19 @@ SIGNATURES = {
     "mrlbm_batch_set_capacity": (c_int32, [c_void_p, c_int32]),
     "mrlbm_batch_get_capacity": (c_int32, [c_void_p, _P(c_int32)]),
     "mrlbm_batch_tune": (c_int32, [c_void_p, c_int32, _P(c_int32), _P(c_int32)]),
+    "mrlbm_set_predictor": (c_int32, [c_void_p, _P(ctypes.c_uint16), c_int32, c_double, c_int64]),
+    "mrlbm_batch_set_predictor": (c_int32, [c_void_p, _P(ctypes.c_uint16), c_int32, c_double, c_int64]),
+    "mrlbm_samples": (c_int32, [c_void_p, _P(ctypes.c_float), _P(ctypes.c_float), c_int64, _P(c_int64)]),
+    "mrlbm_batch_samples": (c_int32, [c_void_p, _P(ctypes.c_float), _P(ctypes.c_float), c_int64, _P(c_int64)]),
+    "mrlbm_mlp_create": (c_int32, [_P(ctypes.c_float), _PP]),
+    "mrlbm_mlp_loss_grad": (c_int32, [c_void_p, _P(ctypes.c_float), _P(ctypes.c_float), c_int64, ctypes.c_float,
+                                      _P(ctypes.c_float), _P(ctypes.c_float)]),
+    "mrlbm_mlp_train": (c_int32, [c_void_p, _P(ctypes.c_float), _P(ctypes.c_float), c_int64, c_int32, c_int32,
+                                  ctypes.c_float, ctypes.c_float, ctypes.c_uint64, _P(ctypes.c_float)]),
+    "mrlbm_mlp_params": (c_int32, [c_void_p, _P(ctypes.c_float), _P(ctypes.c_uint16)]),
+    "mrlbm_mlp_logits": (c_int32, [c_void_p, _P(ctypes.c_float), c_int64, _P(ctypes.c_float)]),
+    "mrlbm_mlp_destroy": (None, [c_void_p]),
+    "mrlbm_mlp_last_error": (ctypes.c_char_p, [c_void_p]),
     "mrlbm_batch_destroy": (None, [c_void_p]),
     "mrlbm_batch_last_error": (ctypes.c_char_p, [c_void_p]),
 }
@@ -139,6 +154,80 @@ def _check(rc, msgfn):
         raise MRLBMError(rc, msgfn())
 
 
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _u16ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16))
+
+
+def _samples(fn, h, err):
+    n = c_int64()
+    rc = fn(h, None, None, 0, ctypes.byref(n))
+    if rc not in (OK, ECAPACITY):
+        _check(rc, err)
+    X = np.zeros((max(n.value, 1), MLP_INPUTS), dtype=np.float32)
+    y = np.zeros(max(n.value, 1), dtype=np.float32)
+    _check(fn(h, _fptr(X), _fptr(y), X.shape[0], ctypes.byref(n)), err)
+    return X[: n.value], y[: n.value]
+
+
+class MLP:
+    """The refinement predictor's network on the GPU (training and deployment logits)."""
+
+    def __init__(self, theta0):
+        t = np.ascontiguousarray(theta0, dtype=np.float32)
+        if t.size != MLP_PARAMS:
+            raise ValueError("need MLP_PARAMS parameters")
+        h = ctypes.c_void_p()
+        _check(lib().mrlbm_mlp_create(_fptr(t), ctypes.byref(h)), lambda: lib().mrlbm_mlp_last_error(None).decode())
+        self.h = h
+
+    def _err(self):
+        return lib().mrlbm_mlp_last_error(self.h).decode()
+
+    def loss_grad(self, X, y, pos_weight=1.0):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        loss = ctypes.c_float()
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(lib().mrlbm_mlp_loss_grad(self.h, _fptr(X), _fptr(y), X.shape[0], float(pos_weight), ctypes.byref(loss),
+                                         _fptr(g)), self._err)
+        return loss.value, g
+
+    def train(self, X, y, epochs=20, batch=512, lr=1e-3, pos_weight=1.0, seed=0):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(lib().mrlbm_mlp_train(self.h, _fptr(X), _fptr(y), X.shape[0], int(epochs), int(batch), float(lr),
+                                     float(pos_weight), int(seed), ctypes.byref(loss)), self._err)
+        return loss.value
+
+    def params(self):
+        t = np.zeros(MLP_PARAMS, dtype=np.float32)
+        b = np.zeros(MLP_PARAMS, dtype=np.uint16)
+        _check(lib().mrlbm_mlp_params(self.h, _fptr(t), _u16ptr(b)), self._err)
+        return t, b
+
+    def logits(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        out = np.zeros(X.shape[0], dtype=np.float32)
+        _check(lib().mrlbm_mlp_logits(self.h, _fptr(X), X.shape[0], _fptr(out)), self._err)
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mrlbm_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class MRLBM:
     """One adaptive run on the GPU."""
 
@@ -200,6 +289,16 @@ class MRLBM:
         s = Stats()
         _check(lib().mrlbm_stats(self.h, ctypes.byref(s)), self._err)
         return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def set_predictor(self, bf16_params=None, mode=PRED_LEARNED, gate=8.0, sample_capacity=0):
+        ptr = None
+        if bf16_params is not None:
+            self._pw = np.ascontiguousarray(bf16_params, dtype=np.uint16)
+            ptr = _u16ptr(self._pw)
+        _check(lib().mrlbm_set_predictor(self.h, ptr, int(mode), float(gate), int(sample_capacity)), self._err)
+
+    def samples(self):
+        return _samples(lib().mrlbm_samples, self.h, self._err)
 
     def close(self):
         if getattr(self, "h", None):
@@ -270,6 +369,16 @@ class Batch:
         s = Stats()
         _check(lib().mrlbm_batch_stats(self.h, inst, ctypes.byref(s)), self._err)
         return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def set_predictor(self, bf16_params=None, mode=PRED_LEARNED, gate=8.0, sample_capacity=0):
+        ptr = None
+        if bf16_params is not None:
+            self._pw = np.ascontiguousarray(bf16_params, dtype=np.uint16)
+            ptr = _u16ptr(self._pw)
+        _check(lib().mrlbm_batch_set_predictor(self.h, ptr, int(mode), float(gate), int(sample_capacity)), self._err)
+
+    def samples(self):
+        return _samples(lib().mrlbm_batch_samples, self.h, self._err)
 
     def total_updates(self):
         t = c_int64()

@@ -36,7 +36,7 @@ def test_struct_layout():
     assert ctypes.sizeof(mrlbm.Params) == 176
     assert mrlbm.Params.lam.offset == 24
     assert mrlbm.Params.eps.offset == 160
-    assert ctypes.sizeof(mrlbm.Stats) == 48
+    assert ctypes.sizeof(mrlbm.Stats) == 64
 
 
 def good():

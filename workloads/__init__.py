@@ -206,3 +206,16 @@ def small_case(kind="advection", seed=0, jmax=7, **kw):
     if kind == "euler":
         return euler(seed, jmax=jmax, **kw)
     raise ValueError(kind)
+
+
+def mlp_init(seed, nin=32, hidden=64):
+    """Seeded initial parameters of the refinement predictor's network (He-uniform weights,
+    zero biases), flat float32 in the order W1[64][32], b1, W2[64][64], b2, w3, b3."""
+    rng = np.random.default_rng([5, seed])
+    a1 = math.sqrt(6.0 / nin)
+    a2 = math.sqrt(6.0 / hidden)
+    W1 = rng.uniform(-a1, a1, size=(hidden, nin))
+    W1[:, nin - 1] = 0.0
+    W2 = rng.uniform(-a2, a2, size=(hidden, hidden))
+    w3 = rng.uniform(-a2, a2, size=hidden)
+    return np.concatenate([W1.ravel(), np.zeros(hidden), W2.ravel(), np.zeros(hidden), w3, np.zeros(1)]).astype(np.float32)
