@@ -18,6 +18,9 @@ Reported next to the throughput:
   and run, for comparison;
 * the error check: delta = ||M_ref - m_hathat||_1 on the conserved moment against an
   eps = 0 run of the same library (the uniform finest-grid scheme, bit for bit), as delta/eps;
+* the learned-refinement form: on D1Q2^3 Euler Riemann problems (J = 14, eps = 1e-4) the
+  network is trained on the rule-(b) pairs the method records, then unseen runs advance with
+  and without it: leaf-cell updates/s, delta/eps, misses and redos of the judge;
 * the CPU baseline: the FP64 oracle (plain numpy, one thread) on a bounded sample.
 """
 
@@ -113,17 +116,117 @@ def cpu_baseline(sample_steps):
             "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
 
 
+def euler_runs(seeds, jmax, eps, steps):
+    ps, ms = [], []
+    for s in seeds:
+        p, mc = W.euler(s, jmax=jmax, eps=eps, steps=steps)
+        ps.append(p)
+        ms.append(mc)
+    return ps, ms
+
+
+def learned_form(mrlbm, n_train, n_test, steps, jmax=14, eps=1e-4, pos_weight=16.0, gate=8.0):
+    """The learned-refinement form on the D1Q2^3 Euler Riemann problems (J = 14, eps = 1e-4):
+    record the rule-(b) pairs of n_train runs, train the network on the GPU, then advance
+    n_test unseen runs in the batched engine with and without it (same launch shape)."""
+    ps, ms = euler_runs(range(1000, 1000 + n_train), jmax, eps, steps)
+    rec = mrlbm.Batch(ps, ms)
+    rec.set_predictor(None, mrlbm.PRED_RECORD, sample_capacity=2_000_000)
+    rec.step(steps)
+    X, y = rec.samples()
+    rec.close()
+    t0 = time.perf_counter()
+    net = mrlbm.MLP(W.mlp_init(0))
+    loss = net.train(X, y, epochs=20, batch=512, lr=2e-3, pos_weight=pos_weight, seed=3)
+    _, bits = net.params()
+    net.close()
+    t_train = time.perf_counter() - t0
+    ps, ms = euler_runs(range(2000, 2000 + n_test), jmax, eps, steps)
+    ref = mrlbm.Batch([dict(p, eps=0.0) for p in ps], ms)
+    ref.step(steps)
+    fin_ref = [ref.moments(i, mrlbm.FINEST) for i in range(n_test)]
+    ref.close()
+    out = {"workload": f"D1Q2^3 Euler Riemann problems, J_min=2 J={jmax}, eps={eps}, s=1.9, lambda=3, clamp",
+           "train_runs": n_train, "test_runs": n_test, "steps": steps, "samples": int(X.shape[0]),
+           "positive_fraction": float(y.mean()), "train_seconds": t_train, "train_loss": loss,
+           "pos_weight": pos_weight, "gate": gate}
+    for name, mode in (("plain", mrlbm.PRED_OFF), ("learned", mrlbm.PRED_LEARNED)):
+        b = mrlbm.Batch(ps, ms)
+        if mode != mrlbm.PRED_OFF:
+            b.set_predictor(bits, mode, gate)
+        ms_run = b.step_timed(steps)
+        sts = [b.stats(i) for i in range(n_test)]
+        upd = sum(st["leaf_updates"] for st in sts)
+        worst = 0.0
+        for i in range(n_test):
+            m = b.moments(i, mrlbm.FINEST)
+            dx = 2.0 / m.shape[1]
+            worst = max(worst, max(float(dx * np.sum(np.abs(m[c] - fin_ref[i][c]))) for c in range(m.shape[0])))
+        b.close()
+        out[name] = {"updates_per_s": upd / (ms_run / 1e3), "leaf_updates": upd, "ms": ms_run,
+                     "max_delta_over_eps": worst / eps, "misses": sum(st["misses"] for st in sts),
+                     "redos": sum(st["redos"] for st in sts)}
+    out["leaf_update_gain"] = 1.0 - out["learned"]["leaf_updates"] / out["plain"]["leaf_updates"]
+    out["speed_vs_plain"] = out["learned"]["updates_per_s"] / out["plain"]["updates_per_s"]
+    return out
+
+
 def copy_probe(nbytes):
-    """Plain device-to-device copy of known size, for scaling rocprofv3 FETCH/WRITE counters."""
-    import torch
-    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    a.fill_(1.0)
-    torch.cuda.synchronize()
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes": nbytes}))
+    """Device-to-device copy of known size through the HIP runtime (its blit kernel), for
+    scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters: 3 copies of nbytes."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    n = ctypes.c_size_t(nbytes)
+    if hip.hipMalloc(ctypes.byref(a), n) or hip.hipMalloc(ctypes.byref(b), n):
+        raise RuntimeError("hipMalloc failed")
+    try:
+        if hip.hipMemset(a, 1, n) or hip.hipDeviceSynchronize():
+            raise RuntimeError("hipMemset failed")
+        for _ in range(3):
+            if hip.hipMemcpy(b, a, n, 3):  # hipMemcpyDeviceToDevice
+                raise RuntimeError("hipMemcpy failed")
+        if hip.hipDeviceSynchronize():
+            raise RuntimeError("copy failed")
+    finally:
+        hip.hipFree(a)
+        hip.hipFree(b)
+    print(json.dumps({"copy_probe_bytes": nbytes, "copies": 3}))
+
+
+def profile_summary(path):
+    """Text summary of rocprofv3 CSV output under ``path`` (kernel stats, per-dispatch trace
+    figures of the step kernel, and counter averages per kernel)."""
+    import csv
+    import glob
+    lines = []
+    for f in sorted(glob.glob(os.path.join(path, "**", "*_kernel_stats.csv"), recursive=True)):
+        lines.append(f"kernel stats ({os.path.basename(f)}):")
+        lines.append(f"  {'calls':>6} {'avg_us':>12} {'total_ms':>10} {'pct':>6}  name")
+        with open(f) as fh:
+            for r in list(csv.DictReader(fh))[:8]:
+                lines.append(f"  {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:12.1f} "
+                             f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f}  {r['Name'][:90]}")
+    for f in sorted(glob.glob(os.path.join(path, "**", "*_kernel_trace.csv"), recursive=True)):
+        with open(f) as fh:
+            rows = [r for r in csv.DictReader(fh) if "k_steps" in r["Kernel_Name"]]
+        for r in rows[:4]:
+            dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            lines.append(f"step kernel dispatch: {dur:.1f} us, grid {r['Grid_Size_X']}, workgroup "
+                         f"{r['Workgroup_Size_X']}, LDS {r['LDS_Block_Size']} B, VGPR {r['VGPR_Count']}, "
+                         f"AGPR {r['Accum_VGPR_Count']}, SGPR {r['SGPR_Count']}, scratch {r['Scratch_Size']} B")
+    for f in sorted(glob.glob(os.path.join(path, "**", "*_counter_collection.csv"), recursive=True)):
+        acc = {}
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                k = (r["Kernel_Name"][:70], r["Counter_Name"])
+                d = acc.setdefault(k, {})
+                d[r["Dispatch_Id"]] = d.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+        lines.append(f"counters ({os.path.basename(f)}), average per dispatch:")
+        for (kn, cn), d in sorted(acc.items()):
+            v = list(d.values())
+            lines.append(f"  {cn:>12} {sum(v) / len(v):16.1f} over {len(v):3d} dispatches  {kn}")
+    print("\n".join(lines) if lines else f"no rocprofv3 CSV output under {path}")
 
 
 def main():
@@ -139,15 +242,22 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=2500)
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-step and delta checks")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-refinement form")
+    ap.add_argument("--learned-steps", type=int, default=2400)
+    ap.add_argument("--capacity", type=int, default=-1, help="on-chip capacity in cells (-1: tuner or default)")
+    ap.add_argument("--profile-summary", default="", help="only summarize rocprofv3 CSV output in this folder")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     args = ap.parse_args()
 
+    if args.profile_summary:
+        profile_summary(args.profile_summary)
+        return 0
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return 0
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the batched engine shards runs "
-              f"across GPUs by design but this build measures one MI355X", file=sys.stderr)
+        print(f"bench.py measures a single GPU (asked for {args.gpus}): the batched engine runs on one "
+              f"device; across GPUs the independent runs would be split by instance", file=sys.stderr)
         return 2
 
     from paper_2102_12163_amd import mrlbm
@@ -159,7 +269,9 @@ def main():
     tuned = None
     if args.block:
         batch.set_block(args.block)
-    elif not args.no_tune:
+    if args.capacity >= 0:
+        batch.set_capacity(args.capacity)
+    if not args.block and args.capacity < 0 and not args.no_tune:
         tuned = batch.tune(args.tune_steps)
         print(f"[bench] tuner: {tuned[0]} threads per workgroup, on-chip capacity {tuned[1]} cells",
               file=sys.stderr, flush=True)
@@ -219,6 +331,9 @@ def main():
         worst, rows = delta_check(mrlbm, sample, args.warmup + args.steps)
         result["error_check"] = {"max_delta_over_eps": worst, "runs": rows,
                                  "reference": "eps=0 run of the same library (uniform finest scheme)"}
+    if not args.no_learned and prec == 0:
+        print("[bench] learned-refinement form", file=sys.stderr, flush=True)
+        result["learned_form"] = learned_form(mrlbm, 8, 64, args.learned_steps)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample_steps)
     print(json.dumps(result))

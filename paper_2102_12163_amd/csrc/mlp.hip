@@ -224,14 +224,22 @@ __global__ void k_mlp_zero(float* p, int n) {
     if (i < n) p[i] = 0.f;
 }
 
-// Deployment logits of n feature rows (the in-step decision path, one row per thread).
-__global__ void k_mlp_logits(const uint16_t* __restrict__ wbf, const float* __restrict__ X, int n, float* out) {
+// Deployment logits of n feature rows, through the in-step decision path: each wave loads
+// 64 rows (one per lane) and evaluates them one after the other with the whole wave.
+__global__ __launch_bounds__(256) void k_mlp_logits(const uint16_t* __restrict__ wbf, const float* __restrict__ X, int n,
+                                                    float* out) {
+    const int lane = threadIdx.x & 63;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
     float x[MLP_IN];
 #pragma unroll
-    for (int i = 0; i < MLP_IN; ++i) x[i] = X[(size_t)s * MLP_IN + i];
-    out[s] = mlp_logit_seq(wbf, x);
+    for (int i = 0; i < MLP_IN; ++i) x[i] = s < n ? X[(size_t)s * MLP_IN + i] : 0.f;
+    const int cnt = min(64, n - (s - lane));  // rows of this wave (wave-uniform)
+    float mine = 0.f;
+    for (int c = 0; c < cnt; ++c) {
+        const float o = mlp_logit_wave(wbf, x, c, lane);
+        if (lane == c) mine = o;
+    }
+    if (s < n) out[s] = mine;
 }
 
 }  // namespace
@@ -413,7 +421,7 @@ int mrlbm_mlp_logits(mrlbm_mlp_t h, const float* X, int64_t n, float* logits) {
     if ((st = hipMalloc(&dX.p, sizeof(float) * MLP_IN * n)) != hipSuccess) return mfail(h, st, "hipMalloc");
     if ((st = hipMalloc(&dl.p, sizeof(float) * n)) != hipSuccess) return mfail(h, st, "hipMalloc");
     (void)hipMemcpyAsync(dX.p, X, sizeof(float) * MLP_IN * n, hipMemcpyHostToDevice, h->stream);
-    hipLaunchKernelGGL(k_mlp_logits, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, h->stream, (const uint16_t*)h->wbf,
+    hipLaunchKernelGGL(k_mlp_logits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream, (const uint16_t*)h->wbf,
                        (const float*)dX.p, (int)n, (float*)dl.p);
     (void)hipMemcpyAsync(logits, dl.p, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
     if ((st = hipStreamSynchronize(h->stream)) != hipSuccess) return mfail(h, st, "logits");

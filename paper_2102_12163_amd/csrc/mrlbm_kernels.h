@@ -317,7 +317,7 @@ struct Block {
             for (; t < n; t += nwaves) {
                 const int w = swl.w[WB(l) + t];
                 const uint64_t b = split[WB(l) + w];
-                bool kb = false, rbb = false, rbu = false;
+                bool kb = false, rbb = false, rbu = false, cand = false;
                 if ((b >> lane) & 1ull) {
                     const int p = (w << 6) + lane;
                     const int sc = rank_of(ro, rpo, jmin, l + 1, 2 * p);
@@ -349,12 +349,25 @@ struct Block {
                     kb = bad || (D >= thr);
                     rbb = kb && rb_level && (bad || D >= thrb);
                     rbu = rbb;
-                    if constexpr (LRN) {
-                        if (d.pmode == 1 && d.mlp && rbb && !getbit(forced, WB(l), p) && D < d.gate * thrb) {
-                            float x[MLP_IN];
-                            features(Vx, l, p, x);
-                            rbu = mlp_logit_seq(d.mlp, x) >= 0.f;
+                    if constexpr (LRN)
+                        cand = d.pmode == 1 && d.mlp && rbb && !getbit(forced, WB(l), p) && D < d.gate * thrb;
+                }
+                if constexpr (LRN) {
+                    // the network decides the candidates of this word one at a time, each
+                    // evaluated by the whole wave (lane = hidden unit)
+                    uint64_t cm = __ballot(cand);
+                    if (cm) {
+                        float x[MLP_IN];
+#pragma unroll
+                        for (int i = 0; i < MLP_IN; ++i) x[i] = 0.f;
+                        if (cand) features(Vx, l, (w << 6) + lane, x);
+                        uint64_t accept = 0ull;
+                        while (cm) {
+                            const int c = __builtin_ctzll(cm);
+                            cm &= cm - 1ull;
+                            if (mlp_logit_wave(d.mlp, x, c, lane) >= 0.f) accept |= 1ull << c;
                         }
+                        if (cand) rbu = ((accept >> lane) & 1ull) != 0ull;
                     }
                 }
                 const uint64_t kw = __ballot(kb);
