@@ -65,7 +65,7 @@ def delta_check(mrlbm, cases, nsteps):
     rows = []
     for p, mc in cases:
         a = mrlbm.MRLBM(p, mc)
-        r = mrlbm.MRLBM(dict(p, eps=0.0), mc)
+        r = mrlbm.MRLBM(dict(p, eps=0.0, precision=0), mc)
         a.step(nsteps)
         r.step(nsteps)
         ma = a.moments(mrlbm.FINEST)
@@ -229,6 +229,68 @@ def profile_summary(path):
     print("\n".join(lines) if lines else f"no rocprofv3 CSV output under {path}")
 
 
+KERNEL_SOURCES = ("mrlbm_device.h", "mrlbm_kernels.h", "instances.hip")
+COUNTER_FILE = os.path.join(ROOT, "profiles", "k_steps_burgers_j14_counters.txt")
+
+
+def kernel_source_hash():
+    """sha256 over the sources of the step kernel: counters taken on other sources are stale."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2102_12163_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _counter_avg(path, counter, kernel_substr):
+    import csv
+    import glob
+    per = {}
+    for f in glob.glob(os.path.join(path, "**", "*_counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter and kernel_substr in r["Kernel_Name"]:
+                    per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    if not per:
+        raise SystemExit(f"no {counter} rows for {kernel_substr} under {path}")
+    return sum(per.values()) / len(per), len(per)
+
+
+def traffic_summary(dirs, copy_bytes, updates):
+    """Machine-readable block of HBM traffic per step-kernel launch from four rocprofv3 --pmc
+    folders (step FETCH_SIZE, step WRITE_SIZE, copy FETCH_SIZE, copy WRITE_SIZE); each counter
+    is scaled by what it reads for the copy probe of known size (KiB per dispatch)."""
+    fd, wd, cfd, cwd = dirs.split(",")
+    f, nf = _counter_avg(fd, "FETCH_SIZE", "k_steps")
+    w, nw = _counter_avg(wd, "WRITE_SIZE", "k_steps")
+    cf, _ = _counter_avg(cfd, "FETCH_SIZE", "copyBuffer")
+    cw, _ = _counter_avg(cwd, "WRITE_SIZE", "copyBuffer")
+    kib = copy_bytes / 1024.0
+    sf, sw = kib / cf, kib / cw
+    traffic = (f * sf + w * sw) * 1024.0
+    print(f"kernel_source_sha256: {kernel_source_hash()}")
+    print(f"fetch_kib_per_dispatch: {f:.1f}  (over {nf} dispatches)")
+    print(f"write_kib_per_dispatch: {w:.1f}  (over {nw} dispatches)")
+    print(f"copy_probe_bytes: {copy_bytes}  fetch_kib {cf:.1f} -> scale {sf:.4f}  write_kib {cw:.1f} -> scale {sw:.4f}")
+    print(f"traffic_bytes_per_launch: {traffic:.6e}")
+    print(f"updates_per_launch: {updates}")
+    print(f"traffic_bytes_per_update: {traffic / updates:.3f}")
+
+
+def traffic_for(upd):
+    """HBM bytes of a launch of ``upd`` leaf-cell updates from the committed counter summary,
+    or None when the summary is missing or the kernel sources changed since it was taken."""
+    try:
+        with open(COUNTER_FILE) as fh:
+            kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("kernel_source_sha256", "").strip() != kernel_source_hash():
+        return None
+    return float(kv["traffic_bytes_per_update"].split()[0]) * upd
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,9 +308,15 @@ def main():
     ap.add_argument("--learned-steps", type=int, default=2400)
     ap.add_argument("--capacity", type=int, default=-1, help="on-chip capacity in cells (-1: tuner or default)")
     ap.add_argument("--profile-summary", default="", help="only summarize rocprofv3 CSV output in this folder")
+    ap.add_argument("--traffic-summary", default="", help="only print the traffic block from four --pmc folders "
+                    "(step FETCH, step WRITE, copy FETCH, copy WRITE), comma-separated")
+    ap.add_argument("--traffic-updates", type=int, default=0, help="leaf-cell updates of the profiled launch")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     args = ap.parse_args()
 
+    if args.traffic_summary:
+        traffic_summary(args.traffic_summary, 1073741824, args.traffic_updates)
+        return 0
     if args.profile_summary:
         profile_summary(args.profile_summary)
         return 0
@@ -313,7 +381,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(upd) if prec == 0 else None,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-probe scaled)",
             "kernel": "k_steps<double,1,1>" if prec == 0 else "k_steps<float,1,1>",
             "bytes_per_update": bpu,
         },
@@ -331,6 +400,24 @@ def main():
         worst, rows = delta_check(mrlbm, sample, args.warmup + args.steps)
         result["error_check"] = {"max_delta_over_eps": worst, "runs": rows,
                                  "reference": "eps=0 run of the same library (uniform finest scheme)"}
+    if not args.no_extras and prec == 0:
+        print("[bench] FP32-storage form", file=sys.stderr, flush=True)
+        c32 = instances(args.seeds, 1)
+        b32 = mrlbm.Batch([c[0] for c in c32], [c[1] for c in c32])
+        t32 = b32.tune(args.tune_steps) if not args.no_tune else None
+        if args.warmup:
+            b32.step(args.warmup)
+        v0 = b32.total_updates()
+        ms32 = b32.step_timed(args.steps)
+        u32 = b32.total_updates() - v0
+        b32.close()
+        sample32 = [c for c in c32 if c[0]["s"][0] == 1.9 and c[0]["eps"] in (1e-3, 1e-4)][:: args.seeds]
+        worst32, _ = delta_check(mrlbm, sample32, args.warmup + args.steps)
+        result["fp32_form"] = {"updates_per_s": u32 / (ms32 / 1e3), "ms_per_step": ms32 / args.steps,
+                               "tuned": list(t32) if t32 else None, "bytes_per_update": b_alg(Q, 1),
+                               "speed_vs_fp64": (u32 / (ms32 / 1e3)) / value,
+                               "max_delta_over_eps": worst32,
+                               "reference": "eps=0 FP64 run of the same library"}
     if not args.no_learned and prec == 0:
         print("[bench] learned-refinement form", file=sys.stderr, flush=True)
         result["learned_form"] = learned_form(mrlbm, 8, 64, args.learned_steps)

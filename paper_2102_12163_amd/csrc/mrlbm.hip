@@ -796,8 +796,8 @@ int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int
     double best_rate = -1.0;
     int rc = MRLBM_OK;
     if ((st = copy_all(true)) != hipSuccess) rc = hip_fail(e, st, "tune snapshot");
-    const int nts[3] = {128, 256, 512};
-    for (int ti = 0; ti < 3 && rc == MRLBM_OK; ++ti) {
+    const int nts[4] = {128, 256, 384, 512};
+    for (int ti = 0; ti < 4 && rc == MRLBM_OK; ++ti) {
         for (int per_cu = 1; per_cu <= 3 && rc == MRLBM_OK; ++per_cu) {
             e->nt_user = nts[ti];
             e->lds_budget = (full_budget + 1024) / per_cu - 1024;

@@ -45,8 +45,10 @@ __host__ __device__ inline Layout make_layout(int jmin, int J, int cap, int capS
     o = al16(o + (unsigned)q * (unsigned)cap * (unsigned)tsz);
     L.VB = o;
     o = al16(o + (unsigned)q * (unsigned)cap * (unsigned)tsz);
+    // interface pairs: without the predictor they reuse the old value array, dead once the
+    // transfer has read it; the predictor's judge still reads it after the stream
     L.PP = o;
-    o = al16(o + 2u * (unsigned)nm * (unsigned)(capS > 0 ? capS + 1 : 0) * (unsigned)tsz);
+    if (learned) o = al16(o + 2u * (unsigned)nm * (unsigned)(capS > 0 ? capS + 1 : 0) * (unsigned)tsz);
     L.rp = o;
     o = al16(o + 2u * (unsigned)(L.wt + 1) * 4u);
     L.scanE = o;
@@ -665,7 +667,7 @@ DEV T* hbm_vals(const Desc& d, int which) { return reinterpret_cast<T*>(which ? 
 // R(Lambda) cells and in leaves (0 = always use the HBM arrays). LRN: the variant that can run
 // the refinement predictor (d.pmode != 0).
 template <typename T, int S, int G, bool LRN = false>
-__global__ __launch_bounds__(512) void k_steps(const Desc* __restrict__ descs, State* __restrict__ states,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && !LRN) ? 4 : 1))) void k_steps(const Desc* __restrict__ descs, State* __restrict__ states,
                                                int nsteps, int mode, int cap, int capS) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t s_red[24];
@@ -746,7 +748,8 @@ __global__ __launch_bounds__(512) void k_steps(const Desc* __restrict__ descs, S
             // ---- new values: on chip when the new tree fits
             if (where <= IN_LDS_B) nwhere = (nR <= cap) ? (IN_LDS_B - where) : IN_HBM_0;
             else nwhere = (nR <= cap) ? IN_LDS_A : (where == IN_HBM_0 ? IN_HBM_1 : IN_HBM_0);
-            fast = (where <= IN_LDS_B) && (nwhere <= IN_LDS_B) && (n <= capS);
+            fast = (where <= IN_LDS_B) && (nwhere <= IN_LDS_B) && (n <= capS) &&
+                   (LRN || 2 * B_t::NM * (n + 1) <= Q * cap);
             if (threadIdx.x == 0) s_miss = 0;
             if (fast) {
                 VP<T, LT> VO{where == IN_LDS_A ? B.ldsA : B.ldsB, cap};
@@ -756,8 +759,9 @@ __global__ __launch_bounds__(512) void k_steps(const Desc* __restrict__ descs, S
                     B.scan_edges();
                     B.write_list(B.ldsL);
                     B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
-                    B.pairs(VN, B.ldsL, B.ldsP, n);
-                    B.combine(VN, B.ldsL, B.ldsP, n);
+                    LT* PB = LRN ? B.ldsP : (where == IN_LDS_A ? B.ldsA : B.ldsB);
+                    B.pairs(VN, B.ldsL, PB, n);
+                    B.combine(VN, B.ldsL, PB, n);
                 }
                 if constexpr (LRN) {
                     if (judge) {
