@@ -27,7 +27,7 @@ complete leaves) is, in the paper's order:
      finest level take the reconstructed finest neighbour directly (the same value in
      exact arithmetic, and the uniform scheme's value when eps = 0).
 
-Readings (see DESIGN.md): complete leaves are the cells of R(Lambda) without children;
+Readings: complete leaves are the cells of R(Lambda) without children;
 rule (a) is applied once to every cell of R(T_eps(Lambda^n)); rules (a) and (b) both read
 T_eps(Lambda^n) and their results are united; a tie with a threshold keeps/refines.
 """

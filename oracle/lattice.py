@@ -16,7 +16,7 @@ Paper passages followed
 * Sec. 5.3: vectorial D1Q2^3 for Euler, three juxtaposed D1Q2 blocks coupled
   through the equilibria of the odd moments.
 
-Readings where the paper is silent (listed in the design doc as well)
+Readings where the paper is silent
 ----------------------------------------------------------------
 * D1Q3 for Burgers (one conserved moment): m1^eq = u^2/2, m2^eq = alpha lambda^2 u.
 * Vectorial D1Q2^2 for shallow water: blocks (h, hu) with m1^eq = hu and

@@ -87,6 +87,7 @@ struct Block {
     uint64_t* ro;     // R bits of Lambda^n
     uint64_t* forced;   // predictor: rule (b) pairs the judge forces (this step)
     uint64_t* declined; // predictor: pairs the network declined / recorded candidates
+    int* any_declined;  // predictor: set when a declined word of this attempt is nonzero
     uint32_t* rpo;    // slot prefix of Lambda^n
     uint32_t* rpn;    // slot prefix of Lambda^{n+1}
     WordList swl, nswl, lwl;  // split words of Lambda^n, of Lambda^{n+1}; leaf words of Lambda^{n+1}
@@ -378,7 +379,11 @@ struct Block {
                 if (lane == 0) {
                     keep[WB(l) + w] = kw;
                     ruleb[WB(l) + w] = uw;
-                    if constexpr (LRN) declined[WB(l) + w] = d.pmode == 1 ? (rw & ~uw) : (d.pmode == 2 ? rw : 0ull);
+                    if constexpr (LRN) {
+                        const uint64_t dw = d.pmode == 1 ? (rw & ~uw) : (d.pmode == 2 ? rw : 0ull);
+                        declined[WB(l) + w] = dw;
+                        if (dw) *any_declined = 1;
+                    }
                 }
                 (void)rw;
             }
@@ -674,12 +679,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
     __shared__ int s_cnt[96];
     __shared__ int s_nan;
     __shared__ int s_miss;
+    __shared__ int s_dec;
     typedef Block<T, S, G, LRN> B_t;
     typedef typename B_t::LT LT;
     constexpr int Q = B_t::Q;
     const Desc& d = descs[blockIdx.x];
     const Layout lay = make_layout(d.jmin, d.jmax, cap, capS, d.q, d.nm, (int)sizeof(T), LRN);
     B_t B(d, lay, lds, s_red, s_cnt);
+    B.any_declined = &s_dec;
     const int Cg = (1 << (d.jmax + 1)) - (1 << d.jmin);  // slots of an HBM array
     if (threadIdx.x == 0) {
         s_nan = 0;
@@ -731,6 +738,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                 B.ruleb[w] = 0ull;
                 if constexpr (LRN) B.declined[w] = 0ull;
             }
+            if (threadIdx.x == 0) s_dec = 0;
             __syncthreads();
             if (where <= IN_LDS_B) {
                 VP<T, LT> VO{where == IN_LDS_A ? B.ldsA : B.ldsB, cap};
@@ -764,7 +772,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                     B.combine(VN, B.ldsL, PB, n);
                 }
                 if constexpr (LRN) {
-                    if (judge) {
+                    if (judge && (d.pmode == 2 || s_dec)) {
                         B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
                         B.judge_or_record(VO, VN, &s_miss);
                     }
@@ -786,7 +794,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                     B.combine(VN, d.list, P, n);
                 }
                 if constexpr (LRN) {
-                    if (judge) {
+                    if (judge && (d.pmode == 2 || s_dec)) {
                         B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
                         B.judge_or_record(VO, VN, &s_miss);
                     }
@@ -897,6 +905,7 @@ __global__ __launch_bounds__(512) void k_query(const Desc* __restrict__ descs, S
     const Desc& d = descs[blockIdx.x];
     const Layout lay = make_layout(d.jmin, d.jmax, 0, 0, d.q, d.nm, (int)sizeof(T));
     B_t B(d, lay, lds, s_red, s_cnt);
+    B.any_declined = &s_dec;
     const int Cg = (1 << (d.jmax + 1)) - (1 << d.jmin);
     if (threadIdx.x < 24) s_red[threadIdx.x] = 0;
     const int wsplit = wbase(d.jmin, d.jmax);
