@@ -132,6 +132,7 @@ struct Block {
         ldsP = (LT*)(T*)(lds + L.PP);
         ldsL = reinterpret_cast<uint32_t*>(lds + L.LL);
         for (int a = 0; a < 3; ++a) cc[a] = (T)d.c[a];
+        any_declined = nullptr;
     }
 
     DEV int WB(int l) const { return wbase(jmin, l); }
@@ -905,7 +906,6 @@ __global__ __launch_bounds__(512) void k_query(const Desc* __restrict__ descs, S
     const Desc& d = descs[blockIdx.x];
     const Layout lay = make_layout(d.jmin, d.jmax, 0, 0, d.q, d.nm, (int)sizeof(T));
     B_t B(d, lay, lds, s_red, s_cnt);
-    B.any_declined = &s_dec;
     const int Cg = (1 << (d.jmax + 1)) - (1 << d.jmin);
     if (threadIdx.x < 24) s_red[threadIdx.x] = 0;
     const int wsplit = wbase(d.jmin, d.jmax);
