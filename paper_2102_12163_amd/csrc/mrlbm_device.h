@@ -329,10 +329,11 @@ struct VP {
 // Under clamp the targets must already be in range.
 template <typename T, int G, int NP, class PM, class V>
 DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, int jmin, int L, int bc, const T* cc, int tA,
-               int tB, T* outA, T* outB) {
+               int tB, T* outA, T* outB, int lstart) {
     constexpr int WM = 4 * G + 1;
-    // descent: the finest level whose whole window lies in R(Lambda)
-    int l0 = L;
+    // descent: the finest level whose whole window lies in R(Lambda); no level above lstart
+    // qualifies (the caller knows a window cell there lies below a leaf)
+    int l0 = lstart < L ? lstart : L;
     while (l0 > jmin) {
         const int sh = L - l0;
         const int lo = ((tA + 2 * G) >> sh) - 2 * G;

@@ -472,7 +472,7 @@ struct Block {
                         for (int h = 0; h < Q; ++h) f[h] = VO.ld(h, so);
                     } else {
                         T g[Q];
-                        chain<T, G, Q, AllPops<S>>(VO, ro, rpo, jmin, l, bc, cc, k, k, f, g);
+                        chain<T, G, Q, AllPops<S>>(VO, ro, rpo, jmin, l, bc, cc, k, k, f, g, l);
                     }
                     if (collide_mark) {
                         collide<T, S>(d.cf, f);
@@ -546,10 +546,18 @@ struct Block {
         const int stride = n + 1;
         for (int i = tid; i <= n; i += NT) {
             int e = NJ;
+            // levels of the leaves left (la) and right (lb) of the interface; the finest
+            // cells tA and tB lie in them, so no window above min(la, lb) is inside R
+            int la, lb;
             if (i < n) {
                 const uint32_t key = list[i];
                 const int l = key >> 27, k = key & ((1u << 27) - 1u);
                 e = k << (J - l);
+                lb = l;
+                la = i > 0 ? (int)(list[i - 1] >> 27) : (bc == CLAMP ? l : (int)(list[n - 1] >> 27));
+            } else {
+                la = (int)(list[n - 1] >> 27);
+                lb = bc == CLAMP ? la : (int)(list[0] >> 27);
             }
             int tA = e - 1, tB = e;
             if (bc == CLAMP) {
@@ -557,7 +565,7 @@ struct Block {
                 tB = tB > NJ - 1 ? NJ - 1 : tB;
             }
             T a[NM], b[NM];
-            chain<T, G, NM, MovingPops<S>>(Vx, keep, rpn, jmin, J, bc, cc, tA, tB, a, b);
+            chain<T, G, NM, MovingPops<S>>(Vx, keep, rpn, jmin, J, bc, cc, tA, tB, a, b, la < lb ? la : lb);
 #pragma unroll
             for (int m = 0; m < NM; ++m) {
                 P[(2 * m) * stride + i] = a[m];
@@ -673,7 +681,7 @@ DEV T* hbm_vals(const Desc& d, int which) { return reinterpret_cast<T*>(which ? 
 // R(Lambda) cells and in leaves (0 = always use the HBM arrays). LRN: the variant that can run
 // the refinement predictor (d.pmode != 0).
 template <typename T, int S, int G, bool LRN = false>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && !LRN) ? 4 : 1))) void k_steps(const Desc* __restrict__ descs, State* __restrict__ states,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && !LRN && S <= 1) ? 4 : 1))) void k_steps(const Desc* __restrict__ descs, State* __restrict__ states,
                                                int nsteps, int mode, int cap, int capS) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t s_red[24];
@@ -958,7 +966,7 @@ __global__ __launch_bounds__(512) void k_query(const Desc* __restrict__ descs, S
         const int NJ = 1 << d.jmax;
         for (int m = threadIdx.x; m < NJ; m += blockDim.x) {
             T a[Q], b[Q];
-            chain<T, G, Q, AllPops<S>>(V, B.keep, B.rpn, B.jmin, B.J, B.bc, B.cc, m, m, a, b);
+            chain<T, G, Q, AllPops<S>>(V, B.keep, B.rpn, B.jmin, B.J, B.bc, B.cc, m, m, a, b, B.J);
             if (what == 0) {
                 double mc[MAXQ];
                 conserved<T, S>(d.cf, a, mc);
