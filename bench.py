@@ -307,6 +307,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-refinement form")
     ap.add_argument("--learned-steps", type=int, default=2400)
     ap.add_argument("--capacity", type=int, default=-1, help="on-chip capacity in cells (-1: tuner or default)")
+    ap.add_argument("--schedule", type=int, default=-1, help="workgroup schedule stride (-1: tuner or identity)")
     ap.add_argument("--profile-summary", default="", help="only summarize rocprofv3 CSV output in this folder")
     ap.add_argument("--traffic-summary", default="", help="only print the traffic block from four --pmc folders "
                     "(step FETCH, step WRITE, copy FETCH, copy WRITE), comma-separated")
@@ -339,13 +340,18 @@ def main():
         batch.set_block(args.block)
     if args.capacity >= 0:
         batch.set_capacity(args.capacity)
-    if not args.block and args.capacity < 0 and not args.no_tune:
-        tuned = batch.tune(args.tune_steps)
-        print(f"[bench] tuner: {tuned[0]} threads per workgroup, on-chip capacity {tuned[1]} cells",
-              file=sys.stderr, flush=True)
-    cap_cells = batch.get_capacity()
     if args.warmup:
         batch.step(args.warmup)
+    # tuned after the warmup: the schedule pairs runs by their leaf counts, which the full
+    # initial tree does not tell apart (the tuner restores the runs after its trials)
+    if not args.block and args.capacity < 0 and not args.no_tune:
+        tuned = batch.tune(args.tune_steps)
+        print(f"[bench] tuner: {tuned[0]} threads per workgroup, on-chip capacity {tuned[1]} cells, "
+              f"schedule stride {batch.get_schedule()}", file=sys.stderr, flush=True)
+    if args.schedule >= 0:
+        batch.set_schedule(args.schedule)
+    cap_cells = batch.get_capacity()
+    sched = batch.get_schedule()
     u0 = batch.total_updates()
     ms = batch.step_timed(args.steps)
     u1 = batch.total_updates()
@@ -375,7 +381,7 @@ def main():
             "workload": "D1Q3 Burgers, J_min=2 J=14 (16384 cells), gamma=1, periodic [-1,1], "
                         "s in {1.5,1.9} x eps in {1e-2,1e-3,1e-4}, batched runs",
             "runs": len(cases), "seeds_per_pair": args.seeds, "finest_cells": 16384,
-            "threads_per_workgroup": block, "onchip_capacity_cells": cap_cells,
+            "threads_per_workgroup": block, "onchip_capacity_cells": cap_cells, "schedule_stride": sched,
             "tuned": tuned is not None, "form": "batched engine, one launch for all timed steps",
             "mean_leaves_per_run": float(np.mean(leaves_now)),
         },
@@ -404,9 +410,9 @@ def main():
         print("[bench] FP32-storage form", file=sys.stderr, flush=True)
         c32 = instances(args.seeds, 1)
         b32 = mrlbm.Batch([c[0] for c in c32], [c[1] for c in c32])
-        t32 = b32.tune(args.tune_steps) if not args.no_tune else None
         if args.warmup:
             b32.step(args.warmup)
+        t32 = b32.tune(args.tune_steps) if not args.no_tune else None
         v0 = b32.total_updates()
         ms32 = b32.step_timed(args.steps)
         u32 = b32.total_updates() - v0

@@ -25,13 +25,13 @@
 namespace mrl {
 #define MRL_EXTERN(T, S)                                                                        \
     extern template __global__ void k_init<T, S>(const Desc*, State*, const double*, long long); \
-    extern template __global__ void k_steps<T, S, 1>(const Desc*, State*, int, int, int, int);   \
-    extern template __global__ void k_steps<T, S, 2>(const Desc*, State*, int, int, int, int);   \
-    extern template __global__ void k_steps<T, S, 3>(const Desc*, State*, int, int, int, int);   \
+    extern template __global__ void k_steps<T, S, 1>(const Desc*, State*, const int*, int, int, int, int);   \
+    extern template __global__ void k_steps<T, S, 2>(const Desc*, State*, const int*, int, int, int, int);   \
+    extern template __global__ void k_steps<T, S, 3>(const Desc*, State*, const int*, int, int, int, int);   \
     extern template __global__ void k_query<T, S, 1>(const Desc*, State*, int, int, double*);    \
     extern template __global__ void k_query<T, S, 2>(const Desc*, State*, int, int, double*);    \
     extern template __global__ void k_query<T, S, 3>(const Desc*, State*, int, int, double*);          \
-    extern template __global__ void k_steps<T, S, 1, true>(const Desc*, State*, int, int, int, int);
+    extern template __global__ void k_steps<T, S, 1, true>(const Desc*, State*, const int*, int, int, int, int);
 MRL_EXTERN(double, 0)
 MRL_EXTERN(double, 1)
 MRL_EXTERN(double, 2)
@@ -39,9 +39,9 @@ MRL_EXTERN(double, 3)
 #undef MRL_EXTERN
 #define MRL_EXTERN32(T, S)                                                                      \
     extern template __global__ void k_init<T, S>(const Desc*, State*, const double*, long long); \
-    extern template __global__ void k_steps<T, S, 1>(const Desc*, State*, int, int, int, int);   \
-    extern template __global__ void k_steps<T, S, 2>(const Desc*, State*, int, int, int, int);   \
-    extern template __global__ void k_steps<T, S, 3>(const Desc*, State*, int, int, int, int);   \
+    extern template __global__ void k_steps<T, S, 1>(const Desc*, State*, const int*, int, int, int, int);   \
+    extern template __global__ void k_steps<T, S, 2>(const Desc*, State*, const int*, int, int, int, int);   \
+    extern template __global__ void k_steps<T, S, 3>(const Desc*, State*, const int*, int, int, int, int);   \
     extern template __global__ void k_query<T, S, 1>(const Desc*, State*, int, int, double*);    \
     extern template __global__ void k_query<T, S, 2>(const Desc*, State*, int, int, double*);    \
     extern template __global__ void k_query<T, S, 3>(const Desc*, State*, int, int, double*);
@@ -63,6 +63,8 @@ struct Engine {
     std::vector<size_t> voff;
     Desc* dd = nullptr;
     State* ds = nullptr;
+    int* d_sched = nullptr;       // workgroup -> run (null: identity)
+    int sched_stride = 0;         // 0: identity; else heavy/light pairs (b, b + stride)
     char* pool = nullptr;
     size_t pool_bytes = 0;
     double* stage = nullptr;
@@ -230,7 +232,7 @@ void choose_capacity(Engine* e) {
 }
 
 // ---------------------------------------------------------------- kernel dispatch
-typedef void (*StepK)(const Desc*, State*, int, int, int, int);
+typedef void (*StepK)(const Desc*, State*, const int*, int, int, int, int);
 typedef void (*QueryK)(const Desc*, State*, int, int, double*);
 typedef void (*InitK)(const Desc*, State*, const double*, long long);
 
@@ -293,6 +295,7 @@ void engine_free(Engine* e) {
     if (e->pool) (void)hipFree(e->pool);
     if (e->dd) (void)hipFree(e->dd);
     if (e->ds) (void)hipFree(e->ds);
+    if (e->d_sched) (void)hipFree(e->d_sched);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
     delete e;
 }
@@ -477,7 +480,8 @@ int launch_steps(Engine* e, int nsteps, int mode, bool use_graph) {
             e->graph = nullptr;
             if ((st = hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
                 return hip_fail(e, st, "hipStreamBeginCapture");
-            hipLaunchKernelGGL(sk, dim3(e->n), dim3(nt), e->lds, e->stream, (const Desc*)e->dd, e->ds, nsteps, mode,
+            hipLaunchKernelGGL(sk, dim3(e->n), dim3(nt), e->lds, e->stream, (const Desc*)e->dd, e->ds,
+                               (const int*)e->d_sched, nsteps, mode,
                                e->cap, e->capS);
             st = hipStreamEndCapture(e->stream, &e->graph);
             if (st != hipSuccess) return hip_fail(e, st, "hipStreamEndCapture");
@@ -490,7 +494,8 @@ int launch_steps(Engine* e, int nsteps, int mode, bool use_graph) {
         if ((st = hipGraphLaunch(e->gexec, e->stream)) != hipSuccess) return hip_fail(e, st, "hipGraphLaunch");
         return MRLBM_OK;
     }
-    hipLaunchKernelGGL(sk, dim3(e->n), dim3(nt), e->lds, e->stream, (const Desc*)e->dd, e->ds, nsteps, mode, e->cap,
+    hipLaunchKernelGGL(sk, dim3(e->n), dim3(nt), e->lds, e->stream, (const Desc*)e->dd, e->ds, (const int*)e->d_sched,
+                       nsteps, mode, e->cap,
                        e->capS);
     st = hipGetLastError();
     if (st != hipSuccess) return hip_fail(e, st, "step launch");
@@ -768,6 +773,56 @@ int mrlbm_batch_get_capacity(mrlbm_batch_t b, int32_t* cells) {
     return MRLBM_OK;
 }
 
+// Workgroup -> run schedule. Runs are sorted by cost (leaf count, heaviest first); the
+// positions b with (b / stride) even take the heavy runs in that order and their partners
+// b + stride the light runs from the lightest up, so that two workgroups that share a CU
+// pair a heavy run with a light one. The kernel's wall time is that of its slowest run.
+// stride 0 = identity.
+static void make_schedule(int stride, const std::vector<long long>& cost, std::vector<int>& perm) {
+    const int n = (int)cost.size();
+    perm.resize(n);
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    if (stride <= 0 || stride >= n) return;
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    int hi = 0, lo = n - 1;
+    for (int b = 0; b < n; ++b) {
+        if ((b / stride) % 2) continue;
+        perm[b] = order[hi++];
+        if (b + stride < n) perm[b + stride] = order[lo--];
+    }
+}
+
+static int set_schedule(Engine* e, int stride) {
+    std::vector<State> hs;
+    int rc = read_states(e, hs);
+    if (rc != MRLBM_OK) return rc;
+    std::vector<long long> cost(e->n);
+    for (int i = 0; i < e->n; ++i) cost[i] = hs[i].n_leaves;
+    std::vector<int> perm;
+    make_schedule(stride, cost, perm);
+    std::vector<char> seen(e->n, 0);  // the kernel indexes runs through it: must be a permutation
+    for (int v : perm) {
+        if (v < 0 || v >= e->n || seen[v]) {
+            e->err = "internal: schedule is not a permutation";
+            return MRLBM_EDEVICE;
+        }
+        seen[v] = 1;
+    }
+    hipError_t st;
+    if (!e->d_sched) {
+        if ((st = hipMalloc(&e->d_sched, sizeof(int) * e->n)) != hipSuccess) return hip_fail(e, st, "hipMalloc(schedule)");
+        e->gsteps = -1;  // a captured launch still has the null schedule
+    }
+    if ((st = hipMemcpyAsync(e->d_sched, perm.data(), sizeof(int) * e->n, hipMemcpyHostToDevice, e->stream)) !=
+            hipSuccess ||
+        (st = hipStreamSynchronize(e->stream)) != hipSuccess)
+        return hip_fail(e, st, "schedule upload");
+    e->sched_stride = stride;
+    return MRLBM_OK;
+}
+
 int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int32_t* cells) {
     if (!b || trial_steps <= 0) return MRLBM_EINVAL;
     Engine* e = b->e;
@@ -789,13 +844,33 @@ int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int
                              : hipMemcpyAsync(e->ds, ssnap, sizeof(State) * e->n, hipMemcpyDeviceToDevice, e->stream);
         return s1 != hipSuccess ? s1 : s2;
     };
+    // leaf-cell updates per ms of trial_steps steps from the snapshot, which is restored after
+    auto trial = [&](double* rate) -> int {
+        std::vector<State> h0, h1;
+        int r = read_states(e, h0);
+        if (r != MRLBM_OK) return r;
+        if ((st = hipEventRecord(e->ev0, e->stream)) != hipSuccess) return hip_fail(e, st, "tune");
+        if ((r = launch_steps(e, trial_steps, MODE_ADAPT | MODE_SCHEME, false)) != MRLBM_OK) return r;
+        if ((st = hipEventRecord(e->ev1, e->stream)) != hipSuccess) return hip_fail(e, st, "tune");
+        if ((st = hipEventSynchronize(e->ev1)) != hipSuccess) return hip_fail(e, st, "tune");
+        float f = 0.f;
+        (void)hipEventElapsedTime(&f, e->ev0, e->ev1);
+        if ((r = read_states(e, h1)) != MRLBM_OK) return r;
+        long long upd = 0;
+        for (int i = 0; i < e->n; ++i) upd += h1[i].leaf_updates - h0[i].leaf_updates;
+        *rate = f > 0.f ? upd / (double)f : 0.0;
+        if ((st = copy_all(false)) != hipSuccess) return hip_fail(e, st, "tune restore");
+        return MRLBM_OK;
+    };
     const int saved_nt = e->nt_user;
     const size_t full_budget = e->lds_budget;
+    const int saved_stride = e->sched_stride;
     int best_nt = 0;
     size_t best_budget = full_budget;
     double best_rate = -1.0;
     int rc = MRLBM_OK;
     if ((st = copy_all(true)) != hipSuccess) rc = hip_fail(e, st, "tune snapshot");
+    // launch shape: threads per workgroup x runs per CU (which sets the on-chip capacity)
     const int nts[4] = {128, 256, 384, 512};
     for (int ti = 0; ti < 4 && rc == MRLBM_OK; ++ti) {
         for (int per_cu = 1; per_cu <= 3 && rc == MRLBM_OK; ++per_cu) {
@@ -803,26 +878,36 @@ int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int
             e->lds_budget = (full_budget + 1024) / per_cu - 1024;
             choose_capacity(e);
             if (e->lds > e->lds_budget) continue;  // the tree words alone do not fit
-            std::vector<State> h0, h1;
-            if ((rc = read_states(e, h0)) != MRLBM_OK) break;
-            double ms = 0.0;
-            if ((st = hipEventRecord(e->ev0, e->stream)) != hipSuccess) { rc = hip_fail(e, st, "tune"); break; }
-            if ((rc = launch_steps(e, trial_steps, MODE_ADAPT | MODE_SCHEME, false)) != MRLBM_OK) break;
-            if ((st = hipEventRecord(e->ev1, e->stream)) != hipSuccess) { rc = hip_fail(e, st, "tune"); break; }
-            if ((st = hipEventSynchronize(e->ev1)) != hipSuccess) { rc = hip_fail(e, st, "tune"); break; }
-            float f = 0.f;
-            (void)hipEventElapsedTime(&f, e->ev0, e->ev1);
-            ms = f;
-            if ((rc = read_states(e, h1)) != MRLBM_OK) break;
-            long long upd = 0;
-            for (int i = 0; i < e->n; ++i) upd += h1[i].leaf_updates - h0[i].leaf_updates;
-            const double rate = ms > 0 ? upd / ms : 0.0;
+            double rate = 0.0;
+            if ((rc = trial(&rate)) != MRLBM_OK) break;
             if (rate > best_rate) {
                 best_rate = rate;
                 best_nt = nts[ti];
                 best_budget = e->lds_budget;
             }
-            if ((st = copy_all(false)) != hipSuccess) rc = hip_fail(e, st, "tune restore");
+        }
+    }
+    // schedule: identity, or heavy/light pairs at the stride of one CU slot per CU (the
+    // dispatcher fills every CU once before doubling up) or of one XCD round (8 XCDs)
+    int best_stride = saved_stride;
+    if (rc == MRLBM_OK && best_rate >= 0) {
+        e->nt_user = best_nt;
+        e->lds_budget = best_budget;
+        choose_capacity(e);
+        int dev = 0, ncu = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        const int strides[3] = {0, ncu, 8};
+        double best_s = -1.0;
+        for (int si = 0; si < 3 && rc == MRLBM_OK; ++si) {
+            if (si > 0 && (strides[si] <= 0 || strides[si] >= e->n)) continue;
+            if ((rc = set_schedule(e, strides[si])) != MRLBM_OK) break;
+            double rate = 0.0;
+            if ((rc = trial(&rate)) != MRLBM_OK) break;
+            if (rate > best_s) {
+                best_s = rate;
+                best_stride = strides[si];
+            }
         }
     }
     if ((st = hipStreamSynchronize(e->stream)) != hipSuccess && rc == MRLBM_OK) rc = hip_fail(e, st, "tune");
@@ -832,14 +917,28 @@ int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int
         e->nt_user = saved_nt;
         e->lds_budget = full_budget;
         choose_capacity(e);
-        return rc != MRLBM_OK ? rc : MRLBM_OK;
+        if (e->d_sched) (void)set_schedule(e, saved_stride);
+        return rc;
     }
     e->nt_user = best_nt;
     e->lds_budget = best_budget;
     choose_capacity(e);
+    if ((rc = set_schedule(e, best_stride)) != MRLBM_OK) return rc;
     if (threads) *threads = best_nt;
     if (cells) *cells = e->cap;
     return check_numeric(e);
+}
+
+int mrlbm_batch_get_schedule(mrlbm_batch_t b, int32_t* stride) {
+    if (!b || !stride) return MRLBM_EINVAL;
+    *stride = b->e->sched_stride;
+    return MRLBM_OK;
+}
+
+int mrlbm_batch_set_schedule(mrlbm_batch_t b, int32_t stride) {
+    if (!b || stride < 0) return MRLBM_EINVAL;
+    if (b->e->numeric) return MRLBM_ENUMERIC;
+    return set_schedule(b->e, stride);
 }
 
 static int set_predictor(Engine* e, const uint16_t* params, int32_t mode, double gate, int64_t sample_capacity) {

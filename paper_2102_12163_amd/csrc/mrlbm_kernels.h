@@ -677,12 +677,12 @@ enum : int { IN_LDS_A = 0, IN_LDS_B = 1, IN_HBM_0 = 2, IN_HBM_1 = 3 };
 template <typename T>
 DEV T* hbm_vals(const Desc& d, int which) { return reinterpret_cast<T*>(which ? d.vb : d.va); }
 
-// nsteps time steps (or adaptations only) of run blockIdx.x. cap / capS: on-chip capacity in
+// nsteps time steps (or adaptations only) of run sched[blockIdx.x]. cap / capS: on-chip capacity in
 // R(Lambda) cells and in leaves (0 = always use the HBM arrays). LRN: the variant that can run
 // the refinement predictor (d.pmode != 0).
 template <typename T, int S, int G, bool LRN = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && !LRN && S <= 1) ? 4 : 1))) void k_steps(const Desc* __restrict__ descs, State* __restrict__ states,
-                                               int nsteps, int mode, int cap, int capS) {
+                                               const int* __restrict__ sched, int nsteps, int mode, int cap, int capS) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t s_red[24];
     __shared__ int s_cnt[96];
@@ -692,7 +692,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
     typedef Block<T, S, G, LRN> B_t;
     typedef typename B_t::LT LT;
     constexpr int Q = B_t::Q;
-    const Desc& d = descs[blockIdx.x];
+    // the run of this workgroup: the launch schedule maps workgroups to runs (identity when null)
+    const int run = sched ? sched[blockIdx.x] : (int)blockIdx.x;
+    const Desc& d = descs[run];
     const Layout lay = make_layout(d.jmin, d.jmax, cap, capS, d.q, d.nm, (int)sizeof(T), LRN);
     B_t B(d, lay, lds, s_red, s_cnt);
     B.any_declined = &s_dec;
@@ -707,7 +709,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
     for (int w = threadIdx.x; w < lay.nwJ; w += blockDim.x) B.E[w] = 0ull;
     __syncthreads();
     B.build_tree(B.split, B.ro, B.rpo, B.swl, nullptr, B.lwl);
-    State& st = states[blockIdx.x];
+    State& st = states[run];
     int where = st.cur ? IN_HBM_1 : IN_HBM_0;
     {
         const int nR = (int)B.rpo[lay.wt];

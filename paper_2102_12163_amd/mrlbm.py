@@ -77,6 +77,8 @@ SIGNATURES = {
     "mrlbm_batch_set_capacity": (c_int32, [c_void_p, c_int32]),
     "mrlbm_batch_get_capacity": (c_int32, [c_void_p, _P(c_int32)]),
     "mrlbm_batch_tune": (c_int32, [c_void_p, c_int32, _P(c_int32), _P(c_int32)]),
+    "mrlbm_batch_set_schedule": (c_int32, [c_void_p, c_int32]),
+    "mrlbm_batch_get_schedule": (c_int32, [c_void_p, _P(c_int32)]),
     "mrlbm_set_predictor": (c_int32, [c_void_p, _P(ctypes.c_uint16), c_int32, c_double, c_int64]),
     "mrlbm_batch_set_predictor": (c_int32, [c_void_p, _P(ctypes.c_uint16), c_int32, c_double, c_int64]),
     "mrlbm_samples": (c_int32, [c_void_p, _P(ctypes.c_float), _P(ctypes.c_float), c_int64, _P(c_int64)]),
@@ -395,6 +397,14 @@ class Batch:
         t, c = c_int32(), c_int32()
         _check(lib().mrlbm_batch_tune(self.h, int(trial_steps), ctypes.byref(t), ctypes.byref(c)), self._err)
         return t.value, c.value
+
+    def set_schedule(self, stride):
+        _check(lib().mrlbm_batch_set_schedule(self.h, int(stride)), self._err)
+
+    def get_schedule(self):
+        t = c_int32()
+        _check(lib().mrlbm_batch_get_schedule(self.h, ctypes.byref(t)), self._err)
+        return t.value
 
     def get_capacity(self):
         t = c_int32()

@@ -260,3 +260,32 @@ def test_tuner_keeps_state_and_results():
         assert np.array_equal(a.moments(i), b.moments(i))
     a.close()
     b.close()
+
+
+def test_schedule_does_not_change_results():
+    """The workgroup-to-run schedule only moves runs between workgroups."""
+    cases = [W.batch_instance(s, steps=0) for s in range(24)]
+    announce("schedule", len(cases))
+    ps, ms = [c[0] for c in cases], [c[1] for c in cases]
+    a = mrlbm.Batch(ps, ms)
+    b = mrlbm.Batch(ps, ms)
+    try:
+        a.step(10)
+        b.step(10)
+        assert b.get_schedule() == 0
+        b.set_schedule(5)
+        assert b.get_schedule() == 5
+        a.step(25)
+        b.step(25)
+        b.set_schedule(1)
+        a.step(7)
+        b.step(7)
+        for i in range(len(cases)):
+            la, ia = a.leaves(i)
+            lb, ib = b.leaves(i)
+            assert np.array_equal(la, lb) and np.array_equal(ia, ib), i
+            assert np.array_equal(a.moments(i), b.moments(i)), i
+            assert a.stats(i)["leaf_updates"] == b.stats(i)["leaf_updates"], i
+    finally:
+        a.close()
+        b.close()
