@@ -73,6 +73,20 @@ __host__ __device__ inline int wbase(int jmin, int l) {
     return s;
 }
 
+// Level of word index w of the level-major bit arrays (levels jmin..), and its index inside
+// the level: levels below 6 hold one word each, level l >= 6 holds 2^(l-6) words.
+DEV int level_of_word(int jmin, int w, int* lw) {
+    const int small = jmin < 6 ? 6 - jmin : 0;
+    if (w < small) {
+        *lw = 0;
+        return jmin + w;
+    }
+    const int m = w - small + (jmin > 6 ? (1 << (jmin - 6)) : 1);
+    const int l = 6 + (31 - __clz(m));
+    *lw = m - (1 << (l - 6));
+    return l;
+}
+
 DEV int bcx(int i, int n, int bc) {
     if (bc == PERIODIC) return i & (n - 1);
     return i < 0 ? 0 : (i >= n ? n - 1 : i);

@@ -177,12 +177,11 @@ struct Block {
         const int w0 = tid * per;
         uint32_t s = 0;
         uint32_t nleaf = 0;
-        int l = jmin;
         for (int i = 0; i < per; ++i) {
             const int w = w0 + i;
             if (w >= wt) break;
-            while (w >= WB(l + 1)) ++l;
-            const int lw = w - WB(l);
+            int lw;
+            const int l = level_of_word(jmin, w, &lw);
             const uint64_t r = r_word(sp, jmin, l, lw);
             R[w] = r;
             s += (uint32_t)__popcll(r);
@@ -398,21 +397,18 @@ struct Block {
     // both children of a flagged cell are split. Writes every word of nsplit.
     DEV void enlarge() {
         const int ra = 1;  // ceil(sigma / 2) for sigma = 1 (every built-in scheme)
-        int t = tid;
-        for (int l = jmin; l <= J; ++l) {
-            const int nw = nwords(l);
-            for (; t < nw; t += NT) {
-                uint64_t v = 0;
-                if (l < J) {
-                    v = dilate_word(keep, WB(l), l, t, ra, bc);
-                    if (l > jmin) {
-                        const uint64_t pb = ruleb[WB(l - 1) + (t >> 1)] >> ((t & 1) * 32);
-                        v |= spread32(pb);
-                    }
+        for (int w = tid; w < wt; w += NT) {
+            int t;
+            const int l = level_of_word(jmin, w, &t);
+            uint64_t v = 0;
+            if (l < J) {
+                v = dilate_word(keep, w - t, l, t, ra, bc);
+                if (l > jmin) {
+                    const uint64_t pb = ruleb[WB(l - 1) + (t >> 1)] >> ((t & 1) * 32);
+                    v |= spread32(pb);
                 }
-                nsplit[WB(l) + t] = v;
             }
-            t -= nw;
+            nsplit[w] = v;
         }
         __syncthreads();
     }
