@@ -137,6 +137,29 @@ struct Block {
 
     DEV int WB(int l) const { return wbase(jmin, l); }
 
+    // The words of a per-level word list as one sequence of tasks, levels in order: returns
+    // the number of tasks; lane i keeps the first task of level jmin + i in *first.
+    DEV int list_tasks(WordList wl, int* first) const {
+        const int nlev = J - jmin + 1;
+        const int c = lane < nlev ? wl.c[jmin + lane] : 0;
+        int x = c;
+#pragma unroll
+        for (int o = 1; o < 32; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        *first = x - c;
+        return __shfl(x, nlev - 1, 64);
+    }
+    // Level of task k (wave-uniform) and its position t inside the level's list.
+    DEV int task_level(int k, int first, int* t) const {
+        const int nlev = J - jmin + 1;
+        const uint64_t m = __ballot(lane < nlev && first <= k);
+        const int i = __popcll(m) - 1;
+        *t = k - __shfl(first, i, 64);
+        return jmin + i;
+    }
+
     // ----------------------------------------------------------- block scan
     // Exclusive prefix of per-thread values; returns this thread's base, total in *tot.
     DEV uint32_t block_scan(uint32_t s, uint32_t* tot) {
@@ -310,14 +333,16 @@ struct Block {
 
     template <class V>
     DEV void details(const V& Vx, int* nanflag) {
-        int t = wave;
-        for (int l = jmin; l < J; ++l) {
-            const int n = swl.c[l];
-            const int N = 1 << l;
-            const double thr = ldexp(d.eps, l + 1 - J);
-            const double thrb = ldexp(d.eps, d.mu_bar + 1 + l + 1 - J);
-            const bool rb_level = (l + 1 < J);
-            for (; t < n; t += nwaves) {
+        int first;
+        const int ntask = list_tasks(swl, &first);
+        for (int task = wave; task < ntask; task += nwaves) {
+            {
+                int t;
+                const int l = task_level(task, first, &t);
+                const int N = 1 << l;
+                const double thr = ldexp(d.eps, l + 1 - J);
+                const double thrb = ldexp(d.eps, d.mu_bar + 1 + l + 1 - J);
+                const bool rb_level = (l + 1 < J);
                 const int w = swl.w[WB(l) + t];
                 const uint64_t b = split[WB(l) + w];
                 bool kb = false, rbb = false, rbu = false, cand = false;
@@ -387,7 +412,6 @@ struct Block {
                 }
                 (void)rw;
             }
-            t -= n;
         }
     }
 
@@ -453,10 +477,12 @@ struct Block {
     // set the leaf is collided right away (Sec. 4.5) and its left edge is marked in E.
     template <class VO_, class VN_>
     DEV void transfer(const VO_& VO, const VN_& VN, bool collide_mark, int* nanflag) {
-        int t = wave;
-        for (int l = jmin; l <= J; ++l) {
-            const int n = lwl.c[l];
-            for (; t < n; t += nwaves) {
+        int first;
+        const int ntask = list_tasks(lwl, &first);
+        for (int task = wave; task < ntask; task += nwaves) {
+            {
+                int t;
+                const int l = task_level(task, first, &t);
                 const int w = lwl.w[WB(l) + t];
                 const uint64_t b = ruleb[WB(l) + w];
                 if ((b >> lane) & 1ull) {
@@ -484,7 +510,6 @@ struct Block {
                     for (int h = 0; h < Q; ++h) VN.st(h, sn, f[h]);
                 }
             }
-            t -= n;
         }
         __syncthreads();
     }
@@ -514,10 +539,12 @@ struct Block {
     // Spatial rank of a leaf = number of leaf left edges before its own.
     template <class LP>
     DEV void write_list(LP* list) {
-        int t = wave;
-        for (int l = jmin; l <= J; ++l) {
-            const int n = lwl.c[l];
-            for (; t < n; t += nwaves) {
+        int first;
+        const int ntask = list_tasks(lwl, &first);
+        for (int task = wave; task < ntask; task += nwaves) {
+            {
+                int t;
+                const int l = task_level(task, first, &t);
                 const int w = lwl.w[WB(l) + t];
                 const uint64_t b = ruleb[WB(l) + w];
                 if ((b >> lane) & 1ull) {
@@ -528,7 +555,6 @@ struct Block {
                     list[rank] = ((uint32_t)l << 27) | (uint32_t)k;
                 }
             }
-            t -= n;
         }
         __syncthreads();
     }
