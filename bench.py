@@ -6,9 +6,10 @@ lambda = 1, periodic [-1, 1], J_min = 2, J = 14 (16384 finest cells), gamma = 1,
 mu_bar = 0; the sweep s in {1.5, 1.9} x eps in {1e-2, 1e-3, 1e-4}, with ``--seeds``
 seeded initial data per pair (Riemann data + sine, see workloads.burgers); the default
 85 seeds give 510 runs, about two per compute unit. All runs advance together in the
-batched engine (one workgroup per run, one launch per call; the built-in tuner picks the
-launch shape on a snapshot first); a "step" is one time step of every run. T = 0.4 is
-3277 steps: warmup + timed steps add up to that by default.
+batched engine (one workgroup per run, persistent over launches of 113 steps; after the
+warmup the built-in tuner picks the launch shape and the run-to-workgroup schedule on a
+snapshot); a "step" is one time step of every run. T = 0.4 is 3277 = 29 x 113 steps:
+113 warmup + 3164 timed steps by default.
 
 Reported next to the throughput:
 * roofline of the step kernel: algorithmic bytes (2 q s_b + 8 per leaf-cell update: read
@@ -274,13 +275,14 @@ def traffic_summary(dirs, copy_bytes, updates):
     print(f"write_kib_per_dispatch: {w:.1f}  (over {nw} dispatches)")
     print(f"copy_probe_bytes: {copy_bytes}  fetch_kib {cf:.1f} -> scale {sf:.4f}  write_kib {cw:.1f} -> scale {sw:.4f}")
     print(f"traffic_bytes_per_launch: {traffic:.6e}")
-    print(f"updates_per_launch: {updates}")
+    print(f"updates_per_launch: {updates:.0f}")
     print(f"traffic_bytes_per_update: {traffic / updates:.3f}")
 
 
 def traffic_for(upd):
-    """HBM bytes of a launch of ``upd`` leaf-cell updates from the committed counter summary,
-    or None when the summary is missing or the kernel sources changed since it was taken."""
+    """HBM bytes of a launch of ``upd`` leaf-cell updates from the committed counter summary
+    (bytes per update x updates), or None when the summary is missing or the kernel sources
+    changed since it was taken."""
     try:
         with open(COUNTER_FILE) as fh:
             kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
@@ -294,8 +296,11 @@ def traffic_for(upd):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3227)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=3164)
+    ap.add_argument("--warmup", type=int, default=113)
+    ap.add_argument("--launch-steps", type=int, default=113,
+                    help="steps per kernel launch (the warmup and the timed steps are issued as launches of "
+                         "this many steps; 0: one launch per call)")
     ap.add_argument("--seeds", type=int, default=85, help="seeded runs per (s, eps) pair")
     ap.add_argument("--no-tune", action="store_true", help="skip the built-in launch-shape tuner")
     ap.add_argument("--tune-steps", type=int, default=20)
@@ -311,7 +316,7 @@ def main():
     ap.add_argument("--profile-summary", default="", help="only summarize rocprofv3 CSV output in this folder")
     ap.add_argument("--traffic-summary", default="", help="only print the traffic block from four --pmc folders "
                     "(step FETCH, step WRITE, copy FETCH, copy WRITE), comma-separated")
-    ap.add_argument("--traffic-updates", type=int, default=0, help="leaf-cell updates of the profiled launch")
+    ap.add_argument("--traffic-updates", type=float, default=0, help="leaf-cell updates per profiled launch")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     args = ap.parse_args()
 
@@ -335,6 +340,7 @@ def main():
     cases = instances(args.seeds, prec)
     print(f"[bench] {len(cases)} runs, warmup {args.warmup}, timed {args.steps}", file=sys.stderr, flush=True)
     batch = mrlbm.Batch([c[0] for c in cases], [c[1] for c in cases])
+    batch.set_launch_steps(args.launch_steps)
     tuned = None
     if args.block:
         batch.set_block(args.block)
@@ -363,6 +369,8 @@ def main():
     print(f"[bench] timed region {ms:.1f} ms, {upd} leaf-cell updates", file=sys.stderr, flush=True)
 
     bpu = b_alg(Q, prec)
+    launches = -(-args.steps // args.launch_steps) if args.launch_steps > 0 else 1
+    # algorithmic bytes per launch / average launch duration = total bytes / total time
     achieved = upd * bpu / (ms / 1e3) / 1e9
     result = {
         "metric": "leaf-cell updates/s and % HBM roofline at error<=C*eps vs plain adaptive step",
@@ -382,17 +390,33 @@ def main():
                         "s in {1.5,1.9} x eps in {1e-2,1e-3,1e-4}, batched runs",
             "runs": len(cases), "seeds_per_pair": args.seeds, "finest_cells": 16384,
             "threads_per_workgroup": block, "onchip_capacity_cells": cap_cells, "schedule_stride": sched,
-            "tuned": tuned is not None, "form": "batched engine, one launch for all timed steps",
+            "tuned": tuned is not None, "launch_steps": args.launch_steps,
+            "form": "batched engine, persistent workgroups, launches of launch_steps steps",
             "mean_leaves_per_run": float(np.mean(leaves_now)),
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(upd) if prec == 0 else None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(upd / launches) if prec == 0 else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-probe scaled)",
             "kernel": "k_steps<double,1,1>" if prec == 0 else "k_steps<float,1,1>",
-            "bytes_per_update": bpu,
+            "bytes_per_update": bpu, "launches": launches, "avg_launch_ms": ms / launches,
         },
     }
+    if not args.no_extras and args.launch_steps > 0:
+        # the same timed steps as one persistent launch (no synchronisation between launches)
+        b1 = mrlbm.Batch([c[0] for c in cases], [c[1] for c in cases])
+        b1.set_block(block)
+        b1.set_capacity(cap_cells)
+        if args.warmup:
+            b1.step(args.warmup)
+        b1.set_schedule(sched)
+        v0 = b1.total_updates()
+        ms1 = b1.step_timed(args.steps)
+        u1b = b1.total_updates() - v0
+        b1.close()
+        result["single_launch"] = {"updates_per_s": u1b / (ms1 / 1e3), "ms_per_step": ms1 / args.steps,
+                                   "note": "timed steps as one launch; the launches of the main figure "
+                                           "synchronise all runs every launch_steps steps"}
     if not args.no_extras:
         one = [c for c in cases if c[0]["eps"] == 1e-4][:1] * 1
         rate_plain, _ = plain_step_rate(mrlbm, one, 300)

@@ -187,6 +187,10 @@ int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int
  * get_schedule returns the stride in use. */
 int mrlbm_batch_set_schedule(mrlbm_batch_t b, int32_t stride);
 int mrlbm_batch_get_schedule(mrlbm_batch_t b, int32_t* stride);
+/* Longest launch: a step call of more steps is issued as consecutive launches of at most
+ * `steps` steps each on the handle's stream (same results). 0 (default): one launch per
+ * call. */
+int mrlbm_batch_set_launch_steps(mrlbm_batch_t b, int32_t steps);
 int mrlbm_batch_get_capacity(mrlbm_batch_t b, int32_t* cells);
 void mrlbm_batch_destroy(mrlbm_batch_t b);
 const char* mrlbm_batch_last_error(mrlbm_batch_t b);

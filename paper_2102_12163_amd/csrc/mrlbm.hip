@@ -64,6 +64,7 @@ struct Engine {
     Desc* dd = nullptr;
     State* ds = nullptr;
     int* d_sched = nullptr;       // workgroup -> run (null: identity)
+    int launch_max = 0;           // steps per launch (0: all steps of a call in one launch)
     int sched_stride = 0;         // 0: identity; else heavy/light pairs (b, b + stride)
     char* pool = nullptr;
     size_t pool_bytes = 0;
@@ -463,8 +464,23 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
 
 int check_numeric(Engine* e) { return e->numeric ? MRLBM_ENUMERIC : MRLBM_OK; }
 
+static int launch_once(Engine* e, int nsteps, int mode, bool use_graph);
+
+// nsteps steps as launches of at most e->launch_max steps each (0: one launch).
 int launch_steps(Engine* e, int nsteps, int mode, bool use_graph) {
     if (nsteps <= 0) return MRLBM_OK;
+    const int chunk = e->launch_max > 0 ? e->launch_max : nsteps;
+    for (int done = 0; done < nsteps;) {
+        const int k = std::min(chunk, nsteps - done);
+        // the graph is kept for the full chunk size; a shorter tail is launched directly
+        const int rc = launch_once(e, k, mode, use_graph && (k == chunk || done == 0));
+        if (rc != MRLBM_OK) return rc;
+        done += k;
+    }
+    return MRLBM_OK;
+}
+
+static int launch_once(Engine* e, int nsteps, int mode, bool use_graph) {
     StepK sk;
     QueryK qk;
     InitK ik;
@@ -927,6 +943,12 @@ int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int
     if (threads) *threads = best_nt;
     if (cells) *cells = e->cap;
     return check_numeric(e);
+}
+
+int mrlbm_batch_set_launch_steps(mrlbm_batch_t b, int32_t steps) {
+    if (!b || steps < 0) return MRLBM_EINVAL;
+    b->e->launch_max = steps;
+    return MRLBM_OK;
 }
 
 int mrlbm_batch_get_schedule(mrlbm_batch_t b, int32_t* stride) {

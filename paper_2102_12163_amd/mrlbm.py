@@ -79,6 +79,7 @@ SIGNATURES = {
     "mrlbm_batch_tune": (c_int32, [c_void_p, c_int32, _P(c_int32), _P(c_int32)]),
     "mrlbm_batch_set_schedule": (c_int32, [c_void_p, c_int32]),
     "mrlbm_batch_get_schedule": (c_int32, [c_void_p, _P(c_int32)]),
+    "mrlbm_batch_set_launch_steps": (c_int32, [c_void_p, c_int32]),
     "mrlbm_set_predictor": (c_int32, [c_void_p, _P(ctypes.c_uint16), c_int32, c_double, c_int64]),
     "mrlbm_batch_set_predictor": (c_int32, [c_void_p, _P(ctypes.c_uint16), c_int32, c_double, c_int64]),
     "mrlbm_samples": (c_int32, [c_void_p, _P(ctypes.c_float), _P(ctypes.c_float), c_int64, _P(c_int64)]),
@@ -400,6 +401,9 @@ class Batch:
 
     def set_schedule(self, stride):
         _check(lib().mrlbm_batch_set_schedule(self.h, int(stride)), self._err)
+
+    def set_launch_steps(self, steps):
+        _check(lib().mrlbm_batch_set_launch_steps(self.h, int(steps)), self._err)
 
     def get_schedule(self):
         t = c_int32()

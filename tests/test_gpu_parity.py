@@ -278,6 +278,7 @@ def test_schedule_does_not_change_results():
         a.step(25)
         b.step(25)
         b.set_schedule(1)
+        b.set_launch_steps(3)  # 7 steps as launches of 3, 3, 1
         a.step(7)
         b.step(7)
         for i in range(len(cases)):
