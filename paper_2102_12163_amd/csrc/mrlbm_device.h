@@ -15,6 +15,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 namespace mrl {
@@ -341,6 +343,21 @@ struct VP {
 // a window position's parent position depends only on the parity of (tA + 2G) >> (L - l):
 // the whole window stays in registers. Out-of-range cells under clamp copy the edge cell.
 // Under clamp the targets must already be in range.
+// c ? a : b on the values (a select of two registers, never a select of their addresses,
+// which would keep a register array in scratch memory)
+template <typename T>
+DEV T pick(bool c, T a, T b) {
+    typedef typename std::conditional<sizeof(T) == 8, unsigned long long, unsigned int>::type U;
+    U ua, ub;
+    __builtin_memcpy(&ua, &a, sizeof(T));
+    __builtin_memcpy(&ub, &b, sizeof(T));
+    const U m = c ? ~(U)0 : (U)0;
+    const U r = (ua & m) | (ub & ~m);
+    T out;
+    __builtin_memcpy(&out, &r, sizeof(T));
+    return out;
+}
+
 template <typename T, int G, int NP, class PM, class V>
 DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, int jmin, int L, int bc, const T* cc, int tA,
                int tB, T* outA, T* outB, int lstart) {
@@ -394,13 +411,29 @@ DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, int jmin, int
         const int N = 1 << l;
         const bool par = (u & 1) != 0;
         const int wbl = wbase(jmin, l);
+        // children of the parents at window positions G..3G (prediction, Sec. 3.1): the even
+        // child of parent G + j is kid[2j] = f + corr, the odd one kid[2j+1] = f - corr, and
+        // window position i of this level is kid[i + parity]
+        T kid[NP][WM + 1];
+#pragma unroll
+        for (int m = 0; m < NP; ++m)
+#pragma unroll
+            for (int j = 0; j <= 2 * G; ++j) {
+                T acc = (T)0;
+#pragma unroll
+                for (int a = 1; a <= G; ++a) {
+                    const T t = cc[a - 1] * (win[m][G + j + a] - win[m][G + j - a]);
+                    acc = (a == 1) ? t : acc + t;
+                }
+                kid[m][2 * j] = win[m][G + j] + acc;
+                kid[m][2 * j + 1] = win[m][G + j] - acc;
+            }
         T nw[NP][WM];
         bool any = false;
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
             const int x = lo + i;
             const int xx = bcx(x, N, bc);
-            const bool odd = ((i + (par ? 1 : 0)) & 1) != 0;
             bool inr = false;
             int s = 0;
             if (anyr && i <= hi - lo) {
@@ -414,20 +447,8 @@ DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, int jmin, int
 #pragma unroll
                 for (int m = 0; m < NP; ++m) nw[m][i] = Vx.ld(PM::h(m), s);
             } else {
-                constexpr int pa = G;  // parent position of i for even parity: G + i/2
 #pragma unroll
-                for (int m = 0; m < NP; ++m) {
-                    const T f0 = par ? win[m][pa + ((i + 1) >> 1)] : win[m][pa + (i >> 1)];
-                    T acc = (T)0;
-#pragma unroll
-                    for (int a = 1; a <= G; ++a) {
-                        const T fp = par ? win[m][pa + ((i + 1) >> 1) + a] : win[m][pa + (i >> 1) + a];
-                        const T fm = par ? win[m][pa + ((i + 1) >> 1) - a] : win[m][pa + (i >> 1) - a];
-                        const T t = cc[a - 1] * (fp - fm);
-                        acc = (a == 1) ? t : acc + t;
-                    }
-                    nw[m][i] = odd ? f0 - acc : f0 + acc;
-                }
+                for (int m = 0; m < NP; ++m) nw[m][i] = pick(par, kid[m][i + 1], kid[m][i]);
             }
         }
         anyr = any;
