@@ -241,9 +241,48 @@ struct Block {
     // level first (Sec. 3.1, Definition Projection operator).
     template <class V>
     DEV void project_up(const V& Vx, const uint64_t* sp, const uint64_t* R, const uint32_t* RP, WordList sl) {
-        for (int l = J - 1; l >= jmin; --l) {
+        // Two levels per barrier: the thread of a split cell (l-1, p) first takes the average
+        // of each split child (l, 2p + c) from its own children, stores it, then stores its own
+        // average of the two children. Every split cell of level l has a split parent, so the
+        // pass over level l-1 covers level l; each value is still half the sum of its two
+        // children, children first.
+        int l = J - 1;
+        for (; l - 1 >= jmin; l -= 2) {
+            const int lp = l - 1;
+            const int n = sl.c[lp];
+            if (n == 0) continue;  // no split cell at lp, hence none at l
+            for (int t = wave; t < n; t += nwaves) {
+                const int w = sl.w[WB(lp) + t];
+                const uint64_t b = sp[WB(lp) + w];
+                if ((b >> lane) & 1ull) {
+                    const int p = (w << 6) + lane;
+                    T cv[2][Q];
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int k = 2 * p + c;
+                        const int sk = rank_of(R, RP, jmin, l, k);
+                        if (getbit(sp, WB(l), k)) {
+                            const int sg = rank_of(R, RP, jmin, l + 1, 2 * k);
+#pragma unroll
+                            for (int h = 0; h < Q; ++h) {
+                                const T v = (T)0.5 * (Vx.ld(h, sg) + Vx.ld(h, sg + 1));
+                                Vx.st(h, sk, v);
+                                cv[c][h] = v;
+                            }
+                        } else {
+#pragma unroll
+                            for (int h = 0; h < Q; ++h) cv[c][h] = Vx.ld(h, sk);
+                        }
+                    }
+                    const int so = rank_of(R, RP, jmin, lp, p);
+#pragma unroll
+                    for (int h = 0; h < Q; ++h) Vx.st(h, so, (T)0.5 * (cv[0][h] + cv[1][h]));
+                }
+            }
+            __syncthreads();
+        }
+        if (l == jmin) {  // one level left
             const int n = sl.c[l];
-            if (n == 0) continue;
             for (int t = wave; t < n; t += nwaves) {
                 const int w = sl.w[WB(l) + t];
                 const uint64_t b = sp[WB(l) + w];
@@ -255,7 +294,7 @@ struct Block {
                     for (int h = 0; h < Q; ++h) Vx.st(h, sp_, (T)0.5 * (Vx.ld(h, sc) + Vx.ld(h, sc + 1)));
                 }
             }
-            __syncthreads();
+            if (n) __syncthreads();
         }
     }
 
