@@ -263,11 +263,18 @@ struct Block {
                         const int sk = rank_of(R, RP, jmin, l, k);
                         if (getbit(sp, WB(l), k)) {
                             const int sg = rank_of(R, RP, jmin, l + 1, 2 * k);
+                            // every load before the stores: they cannot alias, but the
+                            // compiler would otherwise wait for each store before the next load
+                            T g0[Q], g1[Q];
 #pragma unroll
                             for (int h = 0; h < Q; ++h) {
-                                const T v = (T)0.5 * (Vx.ld(h, sg) + Vx.ld(h, sg + 1));
-                                Vx.st(h, sk, v);
-                                cv[c][h] = v;
+                                g0[h] = Vx.ld(h, sg);
+                                g1[h] = Vx.ld(h, sg + 1);
+                            }
+#pragma unroll
+                            for (int h = 0; h < Q; ++h) {
+                                cv[c][h] = (T)0.5 * (g0[h] + g1[h]);
+                                Vx.st(h, sk, cv[c][h]);
                             }
                         } else {
 #pragma unroll
@@ -290,8 +297,14 @@ struct Block {
                     const int p = (w << 6) + lane;
                     const int sc = rank_of(R, RP, jmin, l + 1, 2 * p);
                     const int sp_ = rank_of(R, RP, jmin, l, p);
+                    T g0[Q], g1[Q];
 #pragma unroll
-                    for (int h = 0; h < Q; ++h) Vx.st(h, sp_, (T)0.5 * (Vx.ld(h, sc) + Vx.ld(h, sc + 1)));
+                    for (int h = 0; h < Q; ++h) {
+                        g0[h] = Vx.ld(h, sc);
+                        g1[h] = Vx.ld(h, sc + 1);
+                    }
+#pragma unroll
+                    for (int h = 0; h < Q; ++h) Vx.st(h, sp_, (T)0.5 * (g0[h] + g1[h]));
                 }
             }
             if (n) __syncthreads();
@@ -645,6 +658,8 @@ struct Block {
             const uint32_t key = list[i];
             const int l = key >> 27, k = key & ((1u << 27) - 1u);
             const int s = rank_of(keep, rpn, jmin, l, k);
+            // all loads first, then the stores (they never alias; the compiler cannot tell)
+            T out[Q];
 #pragma unroll
             for (int h = 0; h < Q; ++h) {
                 const int wh = Sch<S>::w(h);
@@ -653,18 +668,19 @@ struct Block {
 #pragma unroll
                 for (int mm = 0; mm < NM; ++mm)
                     if (Sch<S>::mv(mm) == h) m = mm;
-                T out;
                 if (l == J) {
-                    out = wh > 0 ? (T)P[(2 * m) * stride + i] : (T)P[(2 * m + 1) * stride + i + 1];
+                    out[h] = wh > 0 ? (T)P[(2 * m) * stride + i] : (T)P[(2 * m + 1) * stride + i + 1];
                 } else {
                     const int side = wh > 0 ? 0 : 1;  // eta = -1 (cell e-1) or 0 (cell e)
                     const T a = (T)P[(2 * m + side) * stride + i];
                     const T b = (T)P[(2 * m + side) * stride + i + 1];
                     const T acc = a - b;
-                    out = Vx.ld(h, s) + (T)ldexp(wh > 0 ? acc : -acc, -(J - l));
+                    out[h] = Vx.ld(h, s) + (T)ldexp(wh > 0 ? acc : -acc, -(J - l));
                 }
-                Vx.st(h, s, out);
             }
+#pragma unroll
+            for (int h = 0; h < Q; ++h)
+                if (Sch<S>::w(h) != 0) Vx.st(h, s, out[h]);
         }
         for (int w = tid; w < lay.nwJ; w += NT) E[w] = 0ull;
         __syncthreads();
