@@ -46,9 +46,10 @@ __host__ __device__ inline Layout make_layout(int jmin, int J, int cap, int capS
     L.VB = o;
     o = al16(o + (unsigned)q * (unsigned)cap * (unsigned)tsz);
     // interface pairs: without the predictor they reuse the old value array, dead once the
-    // transfer has read it; the predictor's judge still reads it after the stream
+    // transfer has read it; with it the old values must survive the step (a redo restarts
+    // from them), so the pairs go to the run's HBM array instead: no LDS region either way
     L.PP = o;
-    if (learned) o = al16(o + 2u * (unsigned)nm * (unsigned)(capS > 0 ? capS + 1 : 0) * (unsigned)tsz);
+    (void)learned;
     L.rp = o;
     o = al16(o + 2u * (unsigned)(L.wt + 1) * 4u);
     L.scanE = o;
@@ -95,7 +96,6 @@ struct Block {
     uint32_t* scanE;  // exclusive prefix of popcount(E)
     LT* ldsA;         // on-chip value arrays (capacity lay.cap slots each)
     LT* ldsB;
-    LT* ldsP;         // on-chip interface pairs
     uint32_t* ldsL;   // on-chip leaf list
     T cc[3];
 
@@ -129,7 +129,6 @@ struct Block {
         lwl = {wl + 2 * wt, cnts + 64};
         ldsA = (LT*)(T*)(lds + L.VA);
         ldsB = (LT*)(T*)(lds + L.VB);
-        ldsP = (LT*)(T*)(lds + L.PP);
         ldsL = reinterpret_cast<uint32_t*>(lds + L.LL);
         for (int a = 0; a < 3; ++a) cc[a] = (T)d.c[a];
         any_declined = nullptr;
@@ -855,9 +854,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                     B.scan_edges();
                     B.write_list(B.ldsL);
                     B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
-                    LT* PB = LRN ? B.ldsP : (where == IN_LDS_A ? B.ldsA : B.ldsB);
-                    B.pairs(VN, B.ldsL, PB, n);
-                    B.combine(VN, B.ldsL, PB, n);
+                    if constexpr (LRN) {
+                        T* PH = reinterpret_cast<T*>(d.pairs);
+                        B.pairs(VN, B.ldsL, PH, n);
+                        B.combine(VN, B.ldsL, PH, n);
+                    } else {
+                        LT* PB = where == IN_LDS_A ? B.ldsA : B.ldsB;
+                        B.pairs(VN, B.ldsL, PB, n);
+                        B.combine(VN, B.ldsL, PB, n);
+                    }
                 }
                 if constexpr (LRN) {
                     if (judge && (d.pmode == 2 || s_dec)) {
