@@ -170,14 +170,16 @@ struct Block {
         }
         if (lane == 63) red[1 + wave] = x;
         __syncthreads();
-        if (tid == 0) {
-            uint32_t run = 0;
-            for (int wv = 0; wv < nwaves; ++wv) {
-                const uint32_t v = red[1 + wv];
-                red[1 + wv] = run;
-                run += v;
+        if (wave == 0) {  // exclusive scan of the wave totals, one lane per wave
+            const uint32_t v = lane < nwaves ? red[1 + lane] : 0u;
+            uint32_t y = v;
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+                const uint32_t z = __shfl_up(y, o, 64);
+                if (lane >= o) y += z;
             }
-            red[20] = run;
+            if (lane < nwaves) red[1 + lane] = y - v;
+            if (lane == nwaves - 1) red[20] = y;
         }
         __syncthreads();
         *tot = red[20];
