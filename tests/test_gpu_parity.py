@@ -290,3 +290,41 @@ def test_schedule_does_not_change_results():
     finally:
         a.close()
         b.close()
+
+
+def test_bench_workload_in_bench_launch_configuration():
+    """The full Burgers batch of the benchmark (510 runs, J = 14) in the launch configuration
+    the benchmark times (512 threads, on-chip capacity near 1000 cells, heavy/light schedule,
+    launches of 113 steps): sampled runs against the oracle, the rest against a batch with
+    the default launch shape (bit for bit)."""
+    cases = []
+    for s in (1.5, 1.9):
+        for eps in (1e-2, 1e-3, 1e-4):
+            for seed in range(85):
+                cases.append(W.burgers(seed, jmax=14, eps=eps, s=s))
+    announce("bench batch", len(cases))
+    ps, ms = [c[0] for c in cases], [c[1] for c in cases]
+    b = mrlbm.Batch(ps, ms)
+    ref = mrlbm.Batch(ps, ms)
+    try:
+        b.set_block(512)
+        b.set_capacity(999)
+        b.set_launch_steps(113)
+        b.step(113)
+        ref.step(113)
+        b.set_schedule(256)
+        b.step(113)
+        ref.step(113)
+        nsteps = 226
+        for i in (0, 170, 254, 425, 509):  # light and heavy runs of both relaxation rates
+            ora = make_oracle(ps[i], ms[i]).step(nsteps)
+            lv, ix = b.leaves(i)
+            olv, oix = ora.leaf_list()
+            assert np.array_equal(lv, olv) and np.array_equal(ix, oix), i
+            assert rel_err(b.moments(i), ora.leaf_conserved()) <= 1e-12, i
+        for i in range(0, len(cases), 17):
+            assert np.array_equal(b.moments(i), ref.moments(i)), i
+        assert b.total_updates() == ref.total_updates()
+    finally:
+        b.close()
+        ref.close()
