@@ -146,8 +146,9 @@ void mrlbm_destroy(mrlbm_t h);
 const char* mrlbm_last_error(mrlbm_t h);
 
 /* ---------------------------------------------------------------- batched engine
- * n independent runs advanced by one launch per call: one workgroup per run, every step
- * of the run inside the workgroup (intra-workgroup barriers only). All runs of one batch
+ * n independent runs advanced by one launch per call (or by launches of at most
+ * mrlbm_batch_set_launch_steps steps): one workgroup per run, every step of the run inside
+ * the workgroup (intra-workgroup barriers only). All runs of one batch
  * share scheme, precision and gamma; J, eps, physics and the other parameters may differ.
  * m_cons0[i] points to run i's [q_cons][2^j_max(i)] host array. The launch for a given
  * nsteps is captured once in a HIP graph and replayed. */
