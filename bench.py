@@ -333,6 +333,9 @@ def main():
         print(f"bench.py measures a single GPU (asked for {args.gpus}): the batched engine runs on one "
               f"device; across GPUs the independent runs would be split by instance", file=sys.stderr)
         return 2
+    if args.steps <= 0 or args.warmup < 0 or args.seeds <= 0 or args.launch_steps < 0:
+        print("bench.py needs --steps > 0, --warmup >= 0, --seeds > 0, --launch-steps >= 0", file=sys.stderr)
+        return 2
 
     from paper_2102_12163_amd import mrlbm
 
