@@ -241,12 +241,13 @@ struct Block {
     // Every split cell takes half the sum of its two children (adjacent slots), finest
     // level first (Sec. 3.1, Definition Projection operator).
     template <class V>
-    DEV void project_up(const V& Vx, const uint64_t* sp, const uint64_t* R, const uint32_t* RP, WordList sl) {
+    DEV bool project_up(const V& Vx, const uint64_t* sp, const uint64_t* R, const uint32_t* RP, WordList sl) {
         // Two levels per barrier: the thread of a split cell (l-1, p) first takes the average
         // of each split child (l, 2p + c) from its own children, stores it, then stores its own
         // average of the two children. Every split cell of level l has a split parent, so the
         // pass over level l-1 covers level l; each value is still half the sum of its two
         // children, children first.
+        bool synced = false;  // whether the last thing done was a barrier
         int l = J - 1;
         for (; l - 1 >= jmin; l -= 2) {
             const int lp = l - 1;
@@ -288,6 +289,7 @@ struct Block {
                 }
             }
             __syncthreads();
+            synced = true;
         }
         if (l == jmin) {  // one level left
             const int n = sl.c[l];
@@ -308,8 +310,12 @@ struct Block {
                     for (int h = 0; h < Q; ++h) Vx.st(h, sp_, (T)0.5 * (g0[h] + g1[h]));
                 }
             }
-            if (n) __syncthreads();
+            if (n) {
+                __syncthreads();
+                synced = true;
+            }
         }
+        return synced;
     }
 
     // ----------------------------------------------------------- A2-A4(b): details
@@ -591,7 +597,7 @@ struct Block {
 
     // Spatial rank of a leaf = number of leaf left edges before its own.
     template <class LP>
-    DEV void write_list(LP* list) {
+    DEV void write_list(LP* list, bool sync = true) {
         int first;
         const int ntask = list_tasks(lwl, &first);
         for (int task = wave; task < ntask; task += nwaves) {
@@ -609,7 +615,7 @@ struct Block {
                 }
             }
         }
-        __syncthreads();
+        if (sync) __syncthreads();
     }
 
     // ----------------------------------------------------------- B3: stream
@@ -854,8 +860,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                 B.transfer(VO, VN, scheme, &s_nan);
                 if (scheme) {
                     B.scan_edges();
-                    B.write_list(B.ldsL);
-                    B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
+                    // the list and the projection touch different arrays: the projection's
+                    // barriers (or one here, when it has none) order both before the pairs
+                    B.write_list(B.ldsL, false);
+                    if (!B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl)) __syncthreads();
                     if constexpr (LRN) {
                         T* PH = reinterpret_cast<T*>(d.pairs);
                         B.pairs(VN, B.ldsL, PH, n);
