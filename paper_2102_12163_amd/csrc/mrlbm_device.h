@@ -410,7 +410,6 @@ DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, int jmin, int
         const int hi = ((tB - 2 * G) >> sh) + 2 * G;
         const int N = 1 << l;
         const bool par = (u & 1) != 0;
-        const int wbl = wbase(jmin, l);
         // children of the parents at window positions G..3G (prediction, Sec. 3.1): the even
         // child of parent G + j is kid[2j] = f + corr, the odd one kid[2j+1] = f - corr, and
         // window position i of this level is kid[i + parity]
@@ -429,26 +428,27 @@ DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, int jmin, int
                 kid[m][2 * j + 1] = win[m][G + j] - acc;
             }
         T nw[NP][WM];
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+            for (int m = 0; m < NP; ++m) nw[m][i] = pick(par, kid[m][i + 1], kid[m][i]);
+        // window cells inside R(Lambda) take their stored values instead
         bool any = false;
+        if (anyr) {
+            const int wbl = wbase(jmin, l);
 #pragma unroll
-        for (int i = 0; i < WM; ++i) {
-            const int x = lo + i;
-            const int xx = bcx(x, N, bc);
-            bool inr = false;
-            int s = 0;
-            if (anyr && i <= hi - lo) {
-                const int w = wbl + (xx >> 6);
-                const uint64_t rw = R[w];
-                inr = (rw >> (xx & 63)) & 1ull;
-                if (inr) s = (int)RP[w] + __popcll(rw & ((1ull << (xx & 63)) - 1ull));
-            }
-            any = any || inr;
-            if (inr) {
+            for (int i = 0; i < WM; ++i) {
+                if (i <= hi - lo) {
+                    const int xx = bcx(lo + i, N, bc);
+                    const int w = wbl + (xx >> 6);
+                    const uint64_t rw = R[w];
+                    if ((rw >> (xx & 63)) & 1ull) {
+                        any = true;
+                        const int s = (int)RP[w] + __popcll(rw & ((1ull << (xx & 63)) - 1ull));
 #pragma unroll
-                for (int m = 0; m < NP; ++m) nw[m][i] = Vx.ld(PM::h(m), s);
-            } else {
-#pragma unroll
-                for (int m = 0; m < NP; ++m) nw[m][i] = pick(par, kid[m][i + 1], kid[m][i]);
+                        for (int m = 0; m < NP; ++m) nw[m][i] = Vx.ld(PM::h(m), s);
+                    }
+                }
             }
         }
         anyr = any;
