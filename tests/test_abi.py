@@ -106,3 +106,32 @@ def test_batch_rejects_mixed_schemes():
     with pytest.raises(mrlbm.MRLBMError) as e:
         mrlbm.Batch([p1, p2], [np.zeros((1, 256)), np.zeros((1, 256))])
     assert e.value.code == mrlbm.EINVAL
+
+
+def test_bench_refuses_several_gpus_and_empty_regions():
+    """bench.py measures one GPU: N > 1 and an empty timed region exit with status 2 and a
+    message, before touching the library."""
+    import subprocess
+    import sys as _sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for args in (["--gpus", "2"], ["--steps", "0"]):
+        r = subprocess.run([_sys.executable, os.path.join(root, "bench.py")] + args, capture_output=True, text=True,
+                           timeout=120)
+        assert r.returncode == 2, (args, r.returncode, r.stderr)
+        assert "bench.py" in r.stderr
+
+
+def test_profile_summaries_match_the_kernel_sources():
+    """The committed counter summary names the sha256 of the step-kernel sources it was taken
+    on; bench.py reports its traffic only while they match (this pins the hash function)."""
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    h = bench.kernel_source_hash()
+    assert len(h) == 64
+    t = bench.traffic_for(1.0e6)
+    with open(bench.COUNTER_FILE) as fh:
+        text = fh.read()
+    assert ("kernel_source_sha256: " + h in text) == (t is not None)
