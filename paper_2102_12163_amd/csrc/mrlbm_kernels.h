@@ -97,6 +97,10 @@ struct Block {
     LT* ldsA;         // on-chip value arrays (capacity lay.cap slots each)
     LT* ldsB;
     uint32_t* ldsL;   // on-chip leaf list
+    typedef __attribute__((address_space(3))) uint32_t LU;
+    LU* tab;          // split cells of the current tree: (own slot << 16) | slot of the even child
+    LU* toff;         // tab offsets per level: level l occupies [toff[l - jmin], toff[l - jmin + 1])
+    static constexpr int NOFF = 24;  // offset entries in front of the table (levels + 1 <= 17)
     T cc[3];
 
     DEV Block(const Desc& dd, const Layout& L, uint8_t* lds, uint32_t* red_, int* cnts)
@@ -130,6 +134,8 @@ struct Block {
         ldsA = (LT*)(T*)(lds + L.VA);
         ldsB = (LT*)(T*)(lds + L.VB);
         ldsL = reinterpret_cast<uint32_t*>(lds + L.LL);
+        tab = nullptr;
+        toff = nullptr;
         for (int a = 0; a < 3; ++a) cc[a] = (T)d.c[a];
         any_declined = nullptr;
     }
@@ -314,6 +320,87 @@ struct Block {
                 __syncthreads();
                 synced = true;
             }
+        }
+        return synced;
+    }
+
+    // Slot table of a tree (split bits sp, R bits, slot prefix RP, split-word list wl) written
+    // to dst (room for maxe words, in a dead part of a value array): NOFF words of per-level
+    // offsets (toff), then the split cells in level order, each as (own slot << 16) | slot of
+    // its even child. The tree must fit on chip (slots < 2^16) and its split words must
+    // number at most NT and nwJ (pre uses scanE, free at this point); returns false otherwise,
+    // or when the split cells outnumber maxe (no table). Ends with a barrier when it returns
+    // true.
+    DEV bool build_table(const uint64_t* sp, const uint64_t* R, const uint32_t* RP, WordList wl, LU* dst,
+                         int maxe) {
+        int first;
+        const int ntask = list_tasks(wl, &first);
+        if (ntask > NT || ntask > lay.nwJ || (int)RP[wt] > lay.cap || lay.cap > 65535) return false;
+        const int nlev = J - jmin + 1;
+        int li = 0, fl = 0;  // level of task tid, every lane
+        for (int i = 0; i < nlev; ++i) {
+            const int fi = __builtin_amdgcn_readlane(first, i);
+            if (fi <= tid) {
+                li = i;
+                fl = fi;
+            }
+        }
+        uint32_t cnt = 0;
+        if (tid < ntask) {
+            const int l = jmin + li;
+            cnt = (uint32_t)__popcll(sp[WB(l) + wl.w[WB(l) + (tid - fl)]]);
+        }
+        uint32_t tot;
+        const uint32_t base = block_scan(cnt, &tot);  // tasks are in level order
+        if (tot + NOFF > (uint32_t)maxe) return false;  // uniform: tot is the block total
+        toff = dst;
+        tab = dst + NOFF;
+        uint32_t* pre = scanE;
+        if (tid < ntask) pre[tid] = base;
+        __syncthreads();
+        // level jmin + i starts at its first task's base; an empty level starts where the next
+        // task's level does (its range is empty); lane nlev holds the total
+        if (wave == 0 && lane <= nlev) toff[lane] = first < ntask ? pre[first] : tot;
+        for (int task = wave; task < ntask; task += nwaves) {
+            int t;
+            const int l = task_level(task, first, &t);
+            const int w = wl.w[WB(l) + t];
+            const uint64_t b = sp[WB(l) + w];
+            if ((b >> lane) & 1ull) {
+                const int p = (w << 6) + lane;
+                const uint32_t so = (uint32_t)rank_of(R, RP, jmin, l, p);
+                const uint32_t sc = (uint32_t)rank_of(R, RP, jmin, l + 1, 2 * p);
+                tab[pre[task] + (uint32_t)__popcll(b & ((1ull << lane) - 1ull))] = (so << 16) | sc;
+            }
+        }
+        __syncthreads();
+        return true;
+    }
+
+    // Projection through the slot table (same arithmetic as project_up, one level per pass).
+    template <class V>
+    DEV bool project_table(const V& Vx) {
+        const int nlev = J - jmin + 1;
+        const int myoff = lane <= nlev ? (int)toff[lane] : 0;  // every wave keeps the offsets
+        bool synced = false;
+        for (int i = nlev - 2; i >= 0; --i) {            // levels J-1 .. jmin
+            const int a = __builtin_amdgcn_readlane(myoff, i);
+            const int b = __builtin_amdgcn_readlane(myoff, i + 1);
+            if (a == b) continue;
+            synced = true;
+            for (int e = a + tid; e < b; e += NT) {
+                const uint32_t en = tab[e];
+                const int so = (int)(en >> 16), sc = (int)(en & 0xFFFFu);
+                T g0[Q], g1[Q];
+#pragma unroll
+                for (int h = 0; h < Q; ++h) {
+                    g0[h] = Vx.ld(h, sc);
+                    g1[h] = Vx.ld(h, sc + 1);
+                }
+#pragma unroll
+                for (int h = 0; h < Q; ++h) Vx.st(h, so, (T)0.5 * (g0[h] + g1[h]));
+            }
+            __syncthreads();
         }
         return synced;
     }
@@ -807,6 +894,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
             __syncthreads();
         }
     }
+    // slot table of the current tree (plain kernels, trees on chip): projections without
+    // per-cell slot lookups
+    // (the table sits in the free array B)
+    bool tvalid = false;
+    if constexpr (!LRN)
+        if (where == IN_LDS_A)
+            tvalid = B.build_table(B.split, B.ro, B.rpo, B.swl, (typename B_t::LU*)(lds + lay.VB),
+                                   (int)(((unsigned)Q * (unsigned)cap * sizeof(T)) / 4u));
     const bool scheme = (mode & MODE_SCHEME) != 0;
     const bool judge = LRN && scheme && (d.pmode == 2 || (d.pmode == 1 && d.mlp != nullptr));
     long long upd = 0, misses = 0, redos = 0;
@@ -818,7 +913,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
             for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) B.forced[w] = 0ull;
         if (where <= IN_LDS_B) {
             VP<T, LT> VO{where == IN_LDS_A ? B.ldsA : B.ldsB, cap};
-            B.project_up(VO, B.split, B.ro, B.rpo, B.swl);
+            if (tvalid) B.project_table(VO);
+            else B.project_up(VO, B.split, B.ro, B.rpo, B.swl);
         } else {
             VP<T, T> VO{hbm_vals<T>(d, where - IN_HBM_0), Cg};
             B.project_up(VO, B.split, B.ro, B.rpo, B.swl);
@@ -854,16 +950,27 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
             fast = (where <= IN_LDS_B) && (nwhere <= IN_LDS_B) && (n <= capS) &&
                    (LRN || 2 * B_t::NM * (n + 1) <= Q * cap);
             if (threadIdx.x == 0) s_miss = 0;
+            if constexpr (!LRN) tvalid = false;
             if (fast) {
                 VP<T, LT> VO{where == IN_LDS_A ? B.ldsA : B.ldsB, cap};
                 VP<T, LT> VN{nwhere == IN_LDS_A ? B.ldsA : B.ldsB, cap};
                 B.transfer(VO, VN, scheme, &s_nan);
+                if constexpr (!LRN) {
+                    // the new tree's table goes to the old array behind the interface pairs:
+                    // dead there until the next transfer, after the next step's projection
+                    const int pe = 2 * B_t::NM * (n + 1);
+                    const unsigned off = (where == IN_LDS_A ? lay.VA : lay.VB) + (unsigned)pe * sizeof(T);
+                    tvalid = B.build_table(B.nsplit, B.keep, B.rpn, B.nswl, (typename B_t::LU*)(lds + off),
+                                           (int)(((unsigned)(Q * cap - pe) * sizeof(T)) / 4u));
+                }
                 if (scheme) {
                     B.scan_edges();
                     // the list and the projection touch different arrays: the projection's
                     // barriers (or one here, when it has none) order both before the pairs
                     B.write_list(B.ldsL, false);
-                    if (!B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl)) __syncthreads();
+                    const bool synced = tvalid ? B.project_table(VN)
+                                               : B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
+                    if (!synced) __syncthreads();
                     if constexpr (LRN) {
                         T* PH = reinterpret_cast<T*>(d.pairs);
                         B.pairs(VN, B.ldsL, PH, n);
