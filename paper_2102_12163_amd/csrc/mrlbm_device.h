@@ -127,22 +127,13 @@ DEV uint64_t r_word(const uint64_t* split, int jmin, int l, int w) {
     return spread32(x);
 }
 
-// Word w of level l dilated by r cells: bit i set iff some cell bc(i + s), |s| <= r, is set.
-// Clamp reads as zero fill (the clamped neighbours add nothing beyond the cell itself).
-DEV uint64_t dilate_word(const uint64_t* A, int wbl, int l, int w, int r, int bc) {
+// Word x of level l dilated by r cells, given its left and right neighbour words xl, xr
+// (levels of at least 64 cells; zero for a clamped edge): bit i set iff some cell i + s,
+// |s| <= r, is set. Levels of fewer than 64 cells are one word, wrapped or clamped in place.
+DEV uint64_t dilate_val(uint64_t x, uint64_t xl, uint64_t xr, int l, int r, int bc) {
     const int N = 1 << l;
-    const uint64_t x = A[wbl + w];
     uint64_t d = x;
     if (N >= 64) {
-        const int nw = N >> 6;
-        uint64_t xl, xr;
-        if (bc == PERIODIC) {
-            xl = A[wbl + ((w - 1) & (nw - 1))];
-            xr = A[wbl + ((w + 1) & (nw - 1))];
-        } else {
-            xl = w > 0 ? A[wbl + w - 1] : 0ull;
-            xr = w < nw - 1 ? A[wbl + w + 1] : 0ull;
-        }
         for (int s = 1; s <= r; ++s) {
             d |= (x << s) | (xl >> (64 - s));
             d |= (x >> s) | (xr << (64 - s));
@@ -163,6 +154,32 @@ DEV uint64_t dilate_word(const uint64_t* A, int wbl, int l, int w, int r, int bc
         }
     }
     return d;
+}
+
+// Word w of level l dilated by r cells: bit i set iff some cell bc(i + s), |s| <= r, is set.
+// Clamp reads as zero fill (the clamped neighbours add nothing beyond the cell itself).
+DEV uint64_t dilate_word(const uint64_t* A, int wbl, int l, int w, int r, int bc) {
+    const int N = 1 << l;
+    const uint64_t x = A[wbl + w];
+    uint64_t xl = 0ull, xr = 0ull;
+    if (N >= 64) {
+        const int nw = N >> 6;
+        if (bc == PERIODIC) {
+            xl = A[wbl + ((w - 1) & (nw - 1))];
+            xr = A[wbl + ((w + 1) & (nw - 1))];
+        } else {
+            xl = w > 0 ? A[wbl + w - 1] : 0ull;
+            xr = w < nw - 1 ? A[wbl + w + 1] : 0ull;
+        }
+    }
+    return dilate_val(x, xl, xr, l, r, bc);
+}
+
+// 64-bit lane exchange inside a wave (two 32-bit halves).
+DEV uint64_t shfl64(uint64_t v, int src) {
+    const int lo = __shfl((int)(uint32_t)v, src, 64);
+    const int hi = __shfl((int)(uint32_t)(v >> 32), src, 64);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
 // ------------------------------------------------------------------ schemes

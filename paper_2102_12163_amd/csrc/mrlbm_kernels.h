@@ -595,13 +595,43 @@ struct Block {
             grade_level(a, tid, NT);
             __syncthreads();
         }
-        if (wave == 0) {
-            for (; a > jmin; --a) {
-                grade_level(a, lane, 64);
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            }
-        }
+        if (wave == 0 && a > jmin) grade_wave(a);
         __syncthreads();
+    }
+
+    // Levels a .. jmin + 1 of the grading in one wave, the words in registers: at level a
+    // (at most 128 words) lane i holds words 2i and 2i + 1, takes its outer neighbours from
+    // lanes i - 1 and i + 1 and owns parent word i; parent words are stored as they come and
+    // regrouped in pairs for the next level by lane exchange.
+    DEV void grade_wave(int a) {
+        int cnw = nwords(a);
+        uint64_t x0 = 2 * lane < cnw ? nsplit[WB(a) + 2 * lane] : 0ull;
+        uint64_t x1 = 2 * lane + 1 < cnw ? nsplit[WB(a) + 2 * lane + 1] : 0ull;
+        uint64_t old = lane < nwords(a - 1) ? nsplit[WB(a - 1) + lane] : 0ull;
+        for (; a > jmin; --a) {
+            cnw = nwords(a);
+            const int pnw = nwords(a - 1);
+            const uint64_t onext = (a - 2 >= jmin && lane < nwords(a - 2)) ? nsplit[WB(a - 2) + lane] : 0ull;
+            uint64_t v;
+            if (cnw >= 2) {
+                const int h = cnw >> 1;  // lanes holding words of level a
+                const uint64_t pl = shfl64(x1, (lane - 1) & (h - 1));
+                const uint64_t nx = shfl64(x0, (lane + 1) & (h - 1));
+                const uint64_t xl = (bc == PERIODIC || lane > 0) ? pl : 0ull;
+                const uint64_t xr = (bc == PERIODIC || lane < h - 1) ? nx : 0ull;
+                v = compress64(dilate_val(x0, xl, x1, a, G, bc)) |
+                    (compress64(dilate_val(x1, x0, xr, a, G, bc)) << 32);
+            } else {
+                // one word: a level of 64 cells wraps onto itself (or reads zero when clamped)
+                const uint64_t e = bc == PERIODIC ? x0 : 0ull;
+                v = compress64(dilate_val(x0, e, e, a, G, bc));
+            }
+            const uint64_t pw = v | old;
+            if (lane < pnw) nsplit[WB(a - 1) + lane] = pw;
+            x0 = shfl64(pw, 2 * lane);
+            x1 = shfl64(pw, 2 * lane + 1);
+            old = onext;
+        }
     }
 
     DEV void grade_level(int a, int t0, int stride) {
