@@ -6,10 +6,13 @@ lambda = 1, periodic [-1, 1], J_min = 2, J = 14 (16384 finest cells), gamma = 1,
 mu_bar = 0; the sweep s in {1.5, 1.9} x eps in {1e-2, 1e-3, 1e-4}, with ``--seeds``
 seeded initial data per pair (Riemann data + sine, see workloads.burgers); the default
 85 seeds give 510 runs, about two per compute unit. All runs advance together in the
-batched engine (one workgroup per run, persistent over launches of 113 steps; after the
-warmup the built-in tuner picks the launch shape and the run-to-workgroup schedule on a
-snapshot); a "step" is one time step of every run. T = 0.4 is 3277 = 29 x 113 steps:
-113 warmup + 3164 timed steps by default.
+batched engine (one workgroup per run, persistent over the whole launch); a "step" is one
+time step of every run. The runs are checkpointed at t = 0; the warmup advances them (one
+launch) and they are restored to t = 0; the built-in tuner then picks the launch shape and
+the run-to-workgroup schedule with trials of the timed step count from t = 0 (restored after
+each), and the timed steps run from t = 0 as one launch. T = 0.4 is 3277 steps: by default
+the warmup and the timed region are each the whole run, so the two launches do the same
+work.
 
 Reported next to the throughput:
 * roofline of the step kernel: algorithmic bytes (2 q s_b + 8 per leaf-cell update: read
@@ -296,14 +299,15 @@ def traffic_for(upd):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3164)
-    ap.add_argument("--warmup", type=int, default=113)
-    ap.add_argument("--launch-steps", type=int, default=113,
-                    help="steps per kernel launch (the warmup and the timed steps are issued as launches of "
-                         "this many steps; 0: one launch per call)")
+    ap.add_argument("--steps", type=int, default=3277, help="timed steps (3277: the whole run to T=0.4)")
+    ap.add_argument("--warmup", type=int, default=3277,
+                    help="untimed steps before the timed region; the runs are then put back to t=0")
+    ap.add_argument("--launch-steps", type=int, default=0,
+                    help="steps per kernel launch (0: the warmup and the timed steps as one launch each)")
     ap.add_argument("--seeds", type=int, default=85, help="seeded runs per (s, eps) pair")
     ap.add_argument("--no-tune", action="store_true", help="skip the built-in launch-shape tuner")
-    ap.add_argument("--tune-steps", type=int, default=20)
+    ap.add_argument("--tune-steps", type=int, default=0,
+                    help="steps of each tuner trial, from t=0 (0: the timed step count)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: tuner)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -349,12 +353,16 @@ def main():
         batch.set_block(args.block)
     if args.capacity >= 0:
         batch.set_capacity(args.capacity)
+    batch.checkpoint()  # t = 0
     if args.warmup:
         batch.step(args.warmup)
-    # tuned after the warmup: the schedule pairs runs by their leaf counts, which the full
-    # initial tree does not tell apart (the tuner restores the runs after its trials)
+    # the timed steps start from t = 0 again: with the default counts the warmup launch and
+    # the timed launch do the same work
+    batch.restore()
+    # tuner trials from t = 0 (restored after each); the heavy/light schedule weighs the runs
+    # by their work in the last launch (the warmup, or the tuner's last trial)
     if not args.block and args.capacity < 0 and not args.no_tune:
-        tuned = batch.tune(args.tune_steps)
+        tuned = batch.tune(args.tune_steps or args.steps)
         print(f"[bench] tuner: {tuned[0]} threads per workgroup, on-chip capacity {tuned[1]} cells, "
               f"schedule stride {batch.get_schedule()}", file=sys.stderr, flush=True)
     if args.schedule >= 0:
@@ -368,8 +376,19 @@ def main():
     value = upd / (ms / 1e3)
     leaves_now = [batch.stats(i)["leaves"] for i in range(len(cases))]
     block = batch.get_block()
-    batch.close()
     print(f"[bench] timed region {ms:.1f} ms, {upd} leaf-cell updates", file=sys.stderr, flush=True)
+    chunked = None
+    if not args.no_extras and args.launch_steps == 0:
+        # the same timed steps as launches of 113 steps (all runs synchronise at every launch)
+        batch.restore()
+        batch.set_launch_steps(113)
+        c0 = batch.total_updates()
+        msc = batch.step_timed(args.steps)
+        uc = batch.total_updates() - c0
+        chunked = {"launch_steps": 113, "updates_per_s": uc / (msc / 1e3), "ms_per_step": msc / args.steps,
+                   "note": "timed steps as launches of 113 steps from t=0; every launch waits for its "
+                           "slowest run"}
+    batch.close()
 
     bpu = b_alg(Q, prec)
     launches = -(-args.steps // args.launch_steps) if args.launch_steps > 0 else 1
@@ -394,7 +413,8 @@ def main():
             "runs": len(cases), "seeds_per_pair": args.seeds, "finest_cells": 16384,
             "threads_per_workgroup": block, "onchip_capacity_cells": cap_cells, "schedule_stride": sched,
             "tuned": tuned is not None, "launch_steps": args.launch_steps,
-            "form": "batched engine, persistent workgroups, launches of launch_steps steps",
+            "form": "batched engine, persistent workgroups; timed steps from t=0 (checkpoint restored after "
+                    "the warmup), one launch (launch_steps 0) or launches of launch_steps steps",
             "mean_leaves_per_run": float(np.mean(leaves_now)),
         },
         "roofline": {
@@ -405,21 +425,8 @@ def main():
             "bytes_per_update": bpu, "launches": launches, "avg_launch_ms": ms / launches,
         },
     }
-    if not args.no_extras and args.launch_steps > 0:
-        # the same timed steps as one persistent launch (no synchronisation between launches)
-        b1 = mrlbm.Batch([c[0] for c in cases], [c[1] for c in cases])
-        b1.set_block(block)
-        b1.set_capacity(cap_cells)
-        if args.warmup:
-            b1.step(args.warmup)
-        b1.set_schedule(sched)
-        v0 = b1.total_updates()
-        ms1 = b1.step_timed(args.steps)
-        u1b = b1.total_updates() - v0
-        b1.close()
-        result["single_launch"] = {"updates_per_s": u1b / (ms1 / 1e3), "ms_per_step": ms1 / args.steps,
-                                   "note": "timed steps as one launch; the launches of the main figure "
-                                           "synchronise all runs every launch_steps steps"}
+    if chunked is not None:
+        result["chunked_launches"] = chunked
     if not args.no_extras:
         one = [c for c in cases if c[0]["eps"] == 1e-4][:1] * 1
         rate_plain, _ = plain_step_rate(mrlbm, one, 300)
@@ -430,22 +437,24 @@ def main():
             "batched_speedup_vs_per_run_launches": value / rate_plain_all,
         }
         sample = [c for c in cases if c[0]["s"][0] == 1.9 and c[0]["eps"] in (1e-3, 1e-4)][:: args.seeds]
-        worst, rows = delta_check(mrlbm, sample, args.warmup + args.steps)
+        worst, rows = delta_check(mrlbm, sample, args.steps)
         result["error_check"] = {"max_delta_over_eps": worst, "runs": rows,
                                  "reference": "eps=0 run of the same library (uniform finest scheme)"}
     if not args.no_extras and prec == 0:
         print("[bench] FP32-storage form", file=sys.stderr, flush=True)
         c32 = instances(args.seeds, 1)
         b32 = mrlbm.Batch([c[0] for c in c32], [c[1] for c in c32])
+        b32.checkpoint()
         if args.warmup:
             b32.step(args.warmup)
-        t32 = b32.tune(args.tune_steps) if not args.no_tune else None
+        b32.restore()
+        t32 = b32.tune(args.tune_steps or args.steps) if not args.no_tune else None
         v0 = b32.total_updates()
         ms32 = b32.step_timed(args.steps)
         u32 = b32.total_updates() - v0
         b32.close()
         sample32 = [c for c in c32 if c[0]["s"][0] == 1.9 and c[0]["eps"] in (1e-3, 1e-4)][:: args.seeds]
-        worst32, _ = delta_check(mrlbm, sample32, args.warmup + args.steps)
+        worst32, _ = delta_check(mrlbm, sample32, args.steps)
         result["fp32_form"] = {"updates_per_s": u32 / (ms32 / 1e3), "ms_per_step": ms32 / args.steps,
                                "tuned": list(t32) if t32 else None, "bytes_per_update": b_alg(Q, 1),
                                "speed_vs_fp64": (u32 / (ms32 / 1e3)) / value,

@@ -81,6 +81,10 @@ struct Engine {
     int nt = 0;          // threads per workgroup in use
     int nt_user = 0;     // 0: tuner choice
     bool numeric = false;
+    long long* d_work = nullptr;  // per run: leaf-cell updates of its last launch (not checkpointed)
+    char* ckpt = nullptr;      // checkpoint of the pool (mrlbm_batch_checkpoint)
+    State* ckpt_s = nullptr;   // and of the per-run states
+    bool ckpt_numeric = false;
     std::string err;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -297,6 +301,9 @@ void engine_free(Engine* e) {
     if (e->dd) (void)hipFree(e->dd);
     if (e->ds) (void)hipFree(e->ds);
     if (e->d_sched) (void)hipFree(e->d_sched);
+    if (e->d_work) (void)hipFree(e->d_work);
+    if (e->ckpt) (void)hipFree(e->ckpt);
+    if (e->ckpt_s) (void)hipFree(e->ckpt_s);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
     delete e;
 }
@@ -400,6 +407,7 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
     if ((st = hipMalloc(&e->pool, e->pool_bytes)) != hipSuccess) return fail(st, "hipMalloc(pool)");
     if ((st = hipMalloc(&e->dd, sizeof(Desc) * n)) != hipSuccess) return fail(st, "hipMalloc(desc)");
     if ((st = hipMalloc(&e->ds, sizeof(State) * n)) != hipSuccess) return fail(st, "hipMalloc(state)");
+    if ((st = hipMalloc(&e->d_work, sizeof(long long) * n)) != hipSuccess) return fail(st, "hipMalloc(work)");
     e->stage_elems = maxNJ * maxq;
     if ((st = hipMalloc(&e->stage, e->stage_elems * sizeof(double))) != hipSuccess) return fail(st, "hipMalloc(stage)");
     if (stream) {
@@ -412,6 +420,7 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
     if ((st = hipEventCreate(&e->ev0)) != hipSuccess) return fail(st, "hipEventCreate");
     if ((st = hipEventCreate(&e->ev1)) != hipSuccess) return fail(st, "hipEventCreate");
     if ((st = hipMemsetAsync(e->pool, 0, e->pool_bytes, e->stream)) != hipSuccess) return fail(st, "hipMemset");
+    if ((st = hipMemsetAsync(e->d_work, 0, sizeof(long long) * n, e->stream)) != hipSuccess) return fail(st, "hipMemset");
     for (int i = 0; i < n; ++i) {
         Desc& d = e->hd[i];
         d.va = e->pool + o_va[i];
@@ -419,6 +428,7 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
         d.split = reinterpret_cast<uint64_t*>(e->pool + o_split[i]);
         d.list = reinterpret_cast<uint32_t*>(e->pool + o_list[i]);
         d.pairs = e->pool + o_pairs[i];
+        d.work = e->d_work + i;
     }
     if ((st = hipMemcpyAsync(e->dd, e->hd.data(), sizeof(Desc) * n, hipMemcpyHostToDevice, e->stream)) != hipSuccess)
         return fail(st, "hipMemcpy(desc)");
@@ -466,6 +476,35 @@ int check_numeric(Engine* e) { return e->numeric ? MRLBM_ENUMERIC : MRLBM_OK; }
 
 static int launch_once(Engine* e, int nsteps, int mode, bool use_graph);
 
+// Graph of one launch of nsteps full steps in the current launch shape, captured once and
+// kept until the step count, the block size or the capacity changes.
+static int prepare_graph(Engine* e, int nsteps) {
+    StepK sk;
+    QueryK qk;
+    InitK ik;
+    kernels_for(e->prec, e->scheme, e->gamma, &sk, &qk, &ik);
+    if (e->lrn) sk = lrn_kernel(e->scheme);
+    const int nt = e->nt_user ? e->nt_user : e->nt;
+    if (e->gexec && e->gsteps == nsteps && e->gnt == nt && e->gcap == e->cap) return MRLBM_OK;
+    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    e->gexec = nullptr;
+    e->graph = nullptr;
+    hipError_t st;
+    if ((st = hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(e, st, "hipStreamBeginCapture");
+    hipLaunchKernelGGL(sk, dim3(e->n), dim3(nt), e->lds, e->stream, (const Desc*)e->dd, e->ds, (const int*)e->d_sched,
+                       nsteps, MODE_ADAPT | MODE_SCHEME, e->cap, e->capS);
+    st = hipStreamEndCapture(e->stream, &e->graph);
+    if (st != hipSuccess) return hip_fail(e, st, "hipStreamEndCapture");
+    if ((st = hipGraphInstantiate(&e->gexec, e->graph, nullptr, nullptr, 0)) != hipSuccess)
+        return hip_fail(e, st, "hipGraphInstantiate");
+    e->gsteps = nsteps;
+    e->gnt = nt;
+    e->gcap = e->cap;
+    return MRLBM_OK;
+}
+
 // nsteps steps as launches of at most e->launch_max steps each (0: one launch).
 int launch_steps(Engine* e, int nsteps, int mode, bool use_graph) {
     if (nsteps <= 0) return MRLBM_OK;
@@ -489,24 +528,8 @@ static int launch_once(Engine* e, int nsteps, int mode, bool use_graph) {
     const int nt = e->nt_user ? e->nt_user : e->nt;
     hipError_t st;
     if (use_graph && mode == (MODE_ADAPT | MODE_SCHEME)) {
-        if (!e->gexec || e->gsteps != nsteps || e->gnt != nt || e->gcap != e->cap) {
-            if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
-            if (e->graph) (void)hipGraphDestroy(e->graph);
-            e->gexec = nullptr;
-            e->graph = nullptr;
-            if ((st = hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-                return hip_fail(e, st, "hipStreamBeginCapture");
-            hipLaunchKernelGGL(sk, dim3(e->n), dim3(nt), e->lds, e->stream, (const Desc*)e->dd, e->ds,
-                               (const int*)e->d_sched, nsteps, mode,
-                               e->cap, e->capS);
-            st = hipStreamEndCapture(e->stream, &e->graph);
-            if (st != hipSuccess) return hip_fail(e, st, "hipStreamEndCapture");
-            if ((st = hipGraphInstantiate(&e->gexec, e->graph, nullptr, nullptr, 0)) != hipSuccess)
-                return hip_fail(e, st, "hipGraphInstantiate");
-            e->gsteps = nsteps;
-            e->gnt = nt;
-            e->gcap = e->cap;
-        }
+        const int rc = prepare_graph(e, nsteps);
+        if (rc != MRLBM_OK) return rc;
         if ((st = hipGraphLaunch(e->gexec, e->stream)) != hipSuccess) return hip_fail(e, st, "hipGraphLaunch");
         return MRLBM_OK;
     }
@@ -618,6 +641,11 @@ int engine_step_timed(Engine* e, int nsteps, bool graph, double* ms) {
     if (nsteps < 0 || !ms) {
         e->err = "bad timed-step arguments";
         return MRLBM_EINVAL;
+    }
+    // the graph of the first launch is made before the timed region starts
+    if (graph && nsteps > 0) {
+        const int rc0 = prepare_graph(e, e->launch_max > 0 ? std::min(e->launch_max, nsteps) : nsteps);
+        if (rc0 != MRLBM_OK) return rc0;
     }
     hipError_t st = hipEventRecord(e->ev0, e->stream);
     if (st != hipSuccess) return hip_fail(e, st, "hipEventRecord");
@@ -814,8 +842,17 @@ static int set_schedule(Engine* e, int stride) {
     std::vector<State> hs;
     int rc = read_states(e, hs);
     if (rc != MRLBM_OK) return rc;
+    // cost of a run: its leaf-cell updates in the last launch, or its leaf count before any
     std::vector<long long> cost(e->n);
-    for (int i = 0; i < e->n; ++i) cost[i] = hs[i].n_leaves;
+    hipError_t st;
+    if ((st = hipMemcpyAsync(cost.data(), e->d_work, sizeof(long long) * e->n, hipMemcpyDeviceToHost, e->stream)) !=
+            hipSuccess ||
+        (st = hipStreamSynchronize(e->stream)) != hipSuccess)
+        return hip_fail(e, st, "schedule costs");
+    bool launched = false;
+    for (long long c : cost) launched = launched || c > 0;
+    if (!launched)
+        for (int i = 0; i < e->n; ++i) cost[i] = hs[i].n_leaves;
     std::vector<int> perm;
     make_schedule(stride, cost, perm);
     std::vector<char> seen(e->n, 0);  // the kernel indexes runs through it: must be a permutation
@@ -826,7 +863,6 @@ static int set_schedule(Engine* e, int stride) {
         }
         seen[v] = 1;
     }
-    hipError_t st;
     if (!e->d_sched) {
         if ((st = hipMalloc(&e->d_sched, sizeof(int) * e->n)) != hipSuccess) return hip_fail(e, st, "hipMalloc(schedule)");
         e->gsteps = -1;  // a captured launch still has the null schedule
@@ -943,6 +979,48 @@ int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int
     if (threads) *threads = best_nt;
     if (cells) *cells = e->cap;
     return check_numeric(e);
+}
+
+int mrlbm_batch_checkpoint(mrlbm_batch_t b) {
+    if (!b) return MRLBM_EINVAL;
+    Engine* e = b->e;
+    hipError_t st;
+    if (!e->ckpt) {
+        if ((st = hipMalloc(&e->ckpt, e->pool_bytes)) != hipSuccess) {
+            e->ckpt = nullptr;
+            return hip_fail(e, st, "hipMalloc(checkpoint)");
+        }
+        if ((st = hipMalloc(&e->ckpt_s, sizeof(State) * e->n)) != hipSuccess) {
+            (void)hipFree(e->ckpt);
+            e->ckpt = nullptr;
+            e->ckpt_s = nullptr;
+            return hip_fail(e, st, "hipMalloc(checkpoint)");
+        }
+    }
+    if ((st = hipMemcpyAsync(e->ckpt, e->pool, e->pool_bytes, hipMemcpyDeviceToDevice, e->stream)) != hipSuccess ||
+        (st = hipMemcpyAsync(e->ckpt_s, e->ds, sizeof(State) * e->n, hipMemcpyDeviceToDevice, e->stream)) !=
+            hipSuccess ||
+        (st = hipStreamSynchronize(e->stream)) != hipSuccess)
+        return hip_fail(e, st, "checkpoint");
+    e->ckpt_numeric = e->numeric;
+    return MRLBM_OK;
+}
+
+int mrlbm_batch_restore(mrlbm_batch_t b) {
+    if (!b) return MRLBM_EINVAL;
+    Engine* e = b->e;
+    if (!e->ckpt) {
+        e->err = "restore: no checkpoint taken";
+        return MRLBM_EINVAL;
+    }
+    hipError_t st;
+    if ((st = hipMemcpyAsync(e->pool, e->ckpt, e->pool_bytes, hipMemcpyDeviceToDevice, e->stream)) != hipSuccess ||
+        (st = hipMemcpyAsync(e->ds, e->ckpt_s, sizeof(State) * e->n, hipMemcpyDeviceToDevice, e->stream)) !=
+            hipSuccess ||
+        (st = hipStreamSynchronize(e->stream)) != hipSuccess)
+        return hip_fail(e, st, "restore");
+    e->numeric = e->ckpt_numeric;
+    return MRLBM_OK;
 }
 
 int mrlbm_batch_set_launch_steps(mrlbm_batch_t b, int32_t steps) {

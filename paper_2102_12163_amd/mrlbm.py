@@ -80,6 +80,8 @@ SIGNATURES = {
     "mrlbm_batch_set_schedule": (c_int32, [c_void_p, c_int32]),
     "mrlbm_batch_get_schedule": (c_int32, [c_void_p, _P(c_int32)]),
     "mrlbm_batch_set_launch_steps": (c_int32, [c_void_p, c_int32]),
+    "mrlbm_batch_checkpoint": (c_int32, [c_void_p]),
+    "mrlbm_batch_restore": (c_int32, [c_void_p]),
     "mrlbm_set_predictor": (c_int32, [c_void_p, _P(ctypes.c_uint16), c_int32, c_double, c_int64]),
     "mrlbm_batch_set_predictor": (c_int32, [c_void_p, _P(ctypes.c_uint16), c_int32, c_double, c_int64]),
     "mrlbm_samples": (c_int32, [c_void_p, _P(ctypes.c_float), _P(ctypes.c_float), c_int64, _P(c_int64)]),
@@ -404,6 +406,14 @@ class Batch:
 
     def set_launch_steps(self, steps):
         _check(lib().mrlbm_batch_set_launch_steps(self.h, int(steps)), self._err)
+
+    def checkpoint(self):
+        """Keep every run's state on the device (one copy, overwritten by the next call)."""
+        _check(lib().mrlbm_batch_checkpoint(self.h), self._err)
+
+    def restore(self):
+        """Put every run back to the last checkpoint."""
+        _check(lib().mrlbm_batch_restore(self.h), self._err)
 
     def get_schedule(self):
         t = c_int32()

@@ -294,9 +294,10 @@ def test_schedule_does_not_change_results():
 
 def test_bench_workload_in_bench_launch_configuration():
     """The full Burgers batch of the benchmark (510 runs, J = 14) in the launch configuration
-    the benchmark times (512 threads, on-chip capacity near 1000 cells, heavy/light schedule,
-    launches of 113 steps): sampled runs against the oracle, the rest against a batch with
-    the default launch shape (bit for bit)."""
+    the benchmark times (512 threads, on-chip capacity near 1000 cells, heavy/light schedule
+    set after a warmup, runs restored to t = 0, the timed steps as one launch): sampled runs
+    against the oracle, the rest against a batch with the default launch shape (bit for
+    bit)."""
     cases = []
     for s in (1.5, 1.9):
         for eps in (1e-2, 1e-3, 1e-4):
@@ -309,13 +310,13 @@ def test_bench_workload_in_bench_launch_configuration():
     try:
         b.set_block(512)
         b.set_capacity(999)
-        b.set_launch_steps(113)
+        b.checkpoint()
         b.step(113)
-        ref.step(113)
         b.set_schedule(256)
-        b.step(113)
-        ref.step(113)
+        b.restore()
         nsteps = 226
+        b.step(nsteps)
+        ref.step(nsteps)
         for i in (0, 170, 254, 425, 509):  # light and heavy runs of both relaxation rates
             ora = make_oracle(ps[i], ms[i]).step(nsteps)
             lv, ix = b.leaves(i)
@@ -328,3 +329,33 @@ def test_bench_workload_in_bench_launch_configuration():
     finally:
         b.close()
         ref.close()
+
+
+def test_checkpoint_restore_repeats_the_same_steps():
+    """Steps taken after a restore give what the same steps gave after the checkpoint (bit
+    for bit, statistics included); restore without a checkpoint is an error."""
+    cases = [W.batch_instance(s, steps=0) for s in range(12)]
+    announce("checkpoint", len(cases))
+    ps, ms = [c[0] for c in cases], [c[1] for c in cases]
+    b = mrlbm.Batch(ps, ms)
+    try:
+        with pytest.raises(mrlbm.MRLBMError):
+            b.restore()
+        b.step(9)
+        b.checkpoint()
+        at = [b.stats(i) for i in range(len(cases))]
+        b.step(31)
+        first = [(b.leaves(i), b.moments(i), b.stats(i)) for i in range(len(cases))]
+        b.restore()
+        assert [b.stats(i) for i in range(len(cases))] == at
+        b.set_launch_steps(8)  # the repeat as launches of 8, 8, 8, 7 steps
+        b.step(31)
+        for i, ((lv, ix), m, st) in enumerate(first):
+            lv2, ix2 = b.leaves(i)
+            assert np.array_equal(lv, lv2) and np.array_equal(ix, ix2), i
+            assert np.array_equal(m, b.moments(i)), i
+            assert b.stats(i) == st, i
+        b.restore()  # the checkpoint stays until the next one
+        assert [b.stats(i) for i in range(len(cases))] == at
+    finally:
+        b.close()
