@@ -7,12 +7,12 @@ mu_bar = 0; the sweep s in {1.5, 1.9} x eps in {1e-2, 1e-3, 1e-4}, with ``--seed
 seeded initial data per pair (Riemann data + sine, see workloads.burgers); the default
 85 seeds give 510 runs, about two per compute unit. All runs advance together in the
 batched engine (one workgroup per run, persistent over the whole launch); a "step" is one
-time step of every run. The runs are checkpointed at t = 0; the warmup advances them (one
-launch) and they are restored to t = 0; the built-in tuner then picks the launch shape and
-the run-to-workgroup schedule with trials of the timed step count from t = 0 (restored after
-each), and the timed steps run from t = 0 as one launch. T = 0.4 is 3277 steps: by default
-the warmup and the timed region are each the whole run, so the two launches do the same
-work.
+time step of every run. The runs are checkpointed at t = 0; the built-in tuner picks the
+launch shape and the run-to-workgroup schedule with trials of the timed step count from
+t = 0 (restored after each); the warmup advances the runs in that configuration (one launch),
+they are restored to t = 0 and the timed steps run as one launch. T = 0.4 is 3277 steps: by
+default the warmup and the timed region are each the whole run, so the two launches are the
+same work in the same configuration.
 
 Reported next to the throughput:
 * roofline of the step kernel: algorithmic bytes (2 q s_b + 8 per leaf-cell update: read
@@ -354,13 +354,8 @@ def main():
     if args.capacity >= 0:
         batch.set_capacity(args.capacity)
     batch.checkpoint()  # t = 0
-    if args.warmup:
-        batch.step(args.warmup)
-    # the timed steps start from t = 0 again: with the default counts the warmup launch and
-    # the timed launch do the same work
-    batch.restore()
-    # tuner trials from t = 0 (restored after each); the heavy/light schedule weighs the runs
-    # by their work in the last launch (the warmup, or the tuner's last trial)
+    # launch shape and schedule fixed at t = 0 (tuner trials from t = 0, restored after each),
+    # so that the warmup launch runs in the timed configuration
     if not args.block and args.capacity < 0 and not args.no_tune:
         tuned = batch.tune(args.tune_steps or args.steps)
         print(f"[bench] tuner: {tuned[0]} threads per workgroup, on-chip capacity {tuned[1]} cells, "
@@ -369,6 +364,11 @@ def main():
         batch.set_schedule(args.schedule)
     cap_cells = batch.get_capacity()
     sched = batch.get_schedule()
+    if args.warmup:
+        batch.step(args.warmup)
+    # the timed steps start from t = 0 again: with the default counts the warmup launch and
+    # the timed launch do the same work
+    batch.restore()
     u0 = batch.total_updates()
     ms = batch.step_timed(args.steps)
     u1 = batch.total_updates()
@@ -445,10 +445,10 @@ def main():
         c32 = instances(args.seeds, 1)
         b32 = mrlbm.Batch([c[0] for c in c32], [c[1] for c in c32])
         b32.checkpoint()
+        t32 = b32.tune(args.tune_steps or args.steps) if not args.no_tune else None
         if args.warmup:
             b32.step(args.warmup)
         b32.restore()
-        t32 = b32.tune(args.tune_steps or args.steps) if not args.no_tune else None
         v0 = b32.total_updates()
         ms32 = b32.step_timed(args.steps)
         u32 = b32.total_updates() - v0

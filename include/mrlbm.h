@@ -175,19 +175,17 @@ int mrlbm_batch_set_capacity(mrlbm_batch_t b, int32_t cells);
 /* Built-in tuner: times trial_steps steps of the batch for every candidate launch shape
  * (threads per workgroup 128/256/384/512 x LDS capacity for 1, 2 or 3 runs per compute
  * unit), then for every candidate schedule (see mrlbm_batch_set_schedule: identity, the
- * device's CU count, 8; the costs are the runs' work in the trial before), restoring the
- * runs' state after each trial, and keeps the fastest
+ * device's CU count, 8), restoring the runs' state after each trial, and keeps the fastest
  * (leaf-cell updates/s). The runs end in the state they had before the call. Allocates a
  * temporary snapshot of the handle's device memory. Chosen values are returned when the
  * pointers are non-NULL. */
 int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int32_t* cells);
 /* Workgroup-to-run schedule of the batched launch (results do not depend on it). stride 0:
- * workgroup i advances run i. stride s > 0: runs sorted by their cost, the leaf-cell updates
- * of their last launch (their current leaf counts before the first launch); the workgroups i
- * with (i / s) even take the heaviest runs in order and workgroup i + s the lightest ones, so
- * that workgroups sharing a compute unit pair a heavy run with a light one (the launch lasts
- * as long as its slowest run). Computed from the costs at the call. get_schedule returns the
- * stride in use. */
+ * workgroup i advances run i. stride s > 0: runs ranked heaviest first by a-priori cost
+ * (larger j_max, then smaller eps, which keeps more cells, then more leaves at the call);
+ * the workgroups i with (i / s) even take the heaviest runs in order and workgroup i + s the
+ * lightest ones, so that workgroups sharing a compute unit pair a heavy run with a light one
+ * (the launch lasts as long as its slowest run). get_schedule returns the stride in use. */
 int mrlbm_batch_set_schedule(mrlbm_batch_t b, int32_t stride);
 int mrlbm_batch_get_schedule(mrlbm_batch_t b, int32_t* stride);
 /* Longest launch: a step call of more steps is issued as consecutive launches of at most
@@ -198,8 +196,8 @@ int mrlbm_batch_set_launch_steps(mrlbm_batch_t b, int32_t steps);
  * kept in device memory that the handle allocates at the first call (one more copy of the
  * batch's device pool) and frees with it; a later call overwrites it. restore puts every
  * run back to the checkpoint (MRLBM_EINVAL when none was taken); the launch shape, the
- * schedule, the schedule costs (work of the last launch) and the predictor settings are not
- * part of it. Both synchronise the handle's stream. */
+ * schedule and the predictor settings are not part of it. Both synchronise the handle's
+ * stream. */
 int mrlbm_batch_checkpoint(mrlbm_batch_t b);
 int mrlbm_batch_restore(mrlbm_batch_t b);
 int mrlbm_batch_get_capacity(mrlbm_batch_t b, int32_t* cells);

@@ -81,7 +81,6 @@ struct Engine {
     int nt = 0;          // threads per workgroup in use
     int nt_user = 0;     // 0: tuner choice
     bool numeric = false;
-    long long* d_work = nullptr;  // per run: leaf-cell updates of its last launch (not checkpointed)
     char* ckpt = nullptr;      // checkpoint of the pool (mrlbm_batch_checkpoint)
     State* ckpt_s = nullptr;   // and of the per-run states
     bool ckpt_numeric = false;
@@ -301,7 +300,6 @@ void engine_free(Engine* e) {
     if (e->dd) (void)hipFree(e->dd);
     if (e->ds) (void)hipFree(e->ds);
     if (e->d_sched) (void)hipFree(e->d_sched);
-    if (e->d_work) (void)hipFree(e->d_work);
     if (e->ckpt) (void)hipFree(e->ckpt);
     if (e->ckpt_s) (void)hipFree(e->ckpt_s);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
@@ -407,7 +405,6 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
     if ((st = hipMalloc(&e->pool, e->pool_bytes)) != hipSuccess) return fail(st, "hipMalloc(pool)");
     if ((st = hipMalloc(&e->dd, sizeof(Desc) * n)) != hipSuccess) return fail(st, "hipMalloc(desc)");
     if ((st = hipMalloc(&e->ds, sizeof(State) * n)) != hipSuccess) return fail(st, "hipMalloc(state)");
-    if ((st = hipMalloc(&e->d_work, sizeof(long long) * n)) != hipSuccess) return fail(st, "hipMalloc(work)");
     e->stage_elems = maxNJ * maxq;
     if ((st = hipMalloc(&e->stage, e->stage_elems * sizeof(double))) != hipSuccess) return fail(st, "hipMalloc(stage)");
     if (stream) {
@@ -420,7 +417,6 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
     if ((st = hipEventCreate(&e->ev0)) != hipSuccess) return fail(st, "hipEventCreate");
     if ((st = hipEventCreate(&e->ev1)) != hipSuccess) return fail(st, "hipEventCreate");
     if ((st = hipMemsetAsync(e->pool, 0, e->pool_bytes, e->stream)) != hipSuccess) return fail(st, "hipMemset");
-    if ((st = hipMemsetAsync(e->d_work, 0, sizeof(long long) * n, e->stream)) != hipSuccess) return fail(st, "hipMemset");
     for (int i = 0; i < n; ++i) {
         Desc& d = e->hd[i];
         d.va = e->pool + o_va[i];
@@ -428,7 +424,6 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
         d.split = reinterpret_cast<uint64_t*>(e->pool + o_split[i]);
         d.list = reinterpret_cast<uint32_t*>(e->pool + o_list[i]);
         d.pairs = e->pool + o_pairs[i];
-        d.work = e->d_work + i;
     }
     if ((st = hipMemcpyAsync(e->dd, e->hd.data(), sizeof(Desc) * n, hipMemcpyHostToDevice, e->stream)) != hipSuccess)
         return fail(st, "hipMemcpy(desc)");
@@ -842,17 +837,17 @@ static int set_schedule(Engine* e, int stride) {
     std::vector<State> hs;
     int rc = read_states(e, hs);
     if (rc != MRLBM_OK) return rc;
-    // cost of a run: its leaf-cell updates in the last launch, or its leaf count before any
+    // a-priori cost ranking: finer runs first, then smaller thresholds (more cells kept),
+    // then larger current trees; the rank is the cost
+    std::vector<int> idx(e->n);
+    for (int i = 0; i < e->n; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        if (e->P[a].j_max != e->P[b].j_max) return e->P[a].j_max > e->P[b].j_max;
+        if (e->P[a].eps != e->P[b].eps) return e->P[a].eps < e->P[b].eps;
+        return hs[a].n_leaves > hs[b].n_leaves;
+    });
     std::vector<long long> cost(e->n);
-    hipError_t st;
-    if ((st = hipMemcpyAsync(cost.data(), e->d_work, sizeof(long long) * e->n, hipMemcpyDeviceToHost, e->stream)) !=
-            hipSuccess ||
-        (st = hipStreamSynchronize(e->stream)) != hipSuccess)
-        return hip_fail(e, st, "schedule costs");
-    bool launched = false;
-    for (long long c : cost) launched = launched || c > 0;
-    if (!launched)
-        for (int i = 0; i < e->n; ++i) cost[i] = hs[i].n_leaves;
+    for (int r = 0; r < e->n; ++r) cost[idx[r]] = e->n - r;
     std::vector<int> perm;
     make_schedule(stride, cost, perm);
     std::vector<char> seen(e->n, 0);  // the kernel indexes runs through it: must be a permutation
@@ -863,6 +858,7 @@ static int set_schedule(Engine* e, int stride) {
         }
         seen[v] = 1;
     }
+    hipError_t st;
     if (!e->d_sched) {
         if ((st = hipMalloc(&e->d_sched, sizeof(int) * e->n)) != hipSuccess) return hip_fail(e, st, "hipMalloc(schedule)");
         e->gsteps = -1;  // a captured launch still has the null schedule

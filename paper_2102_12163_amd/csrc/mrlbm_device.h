@@ -51,7 +51,6 @@ struct Desc {
     double gate;            // the network decides only pairs with D < gate * rule-(b) threshold
     float* samples;         // [sample_cap][33]: 32 features and the label
     unsigned int* nsamples;
-    long long* work;        // leaf-cell updates of the run's last full-step launch
 };
 
 struct State {

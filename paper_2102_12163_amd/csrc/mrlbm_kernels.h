@@ -1085,7 +1085,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
         if (mode & MODE_SCHEME) {
             st.steps += nsteps;
             st.leaf_updates += upd;
-            *d.work = upd;
             if (last >= 0) st.n_leaves = last;
         }
         st.n_r = nR;
