@@ -22,6 +22,8 @@ Reported next to the throughput:
   and run, for comparison;
 * the error check: delta = ||M_ref - m_hathat||_1 on the conserved moment against an
   eps = 0 run of the same library (the uniform finest-grid scheme, bit for bit), as delta/eps;
+* the batched ensemble (FP64 and FP32): 4096 independent D1Q2 advection/Burgers instances
+  with J uniform in 8..14 in one launch, against one launch per time step and instance;
 * the learned-refinement form: on D1Q2^3 Euler Riemann problems (J = 14, eps = 1e-4) the
   network is trained on the rule-(b) pairs the method records, then unseen runs advance with
   and without it: leaf-cell updates/s, delta/eps, misses and redos of the judge;
@@ -127,6 +129,36 @@ def euler_runs(seeds, jmax, eps, steps):
         ps.append(p)
         ms.append(mc)
     return ps, ms
+
+
+def ensemble_form(mrlbm, n, steps, prec, tune):
+    """The batched ensemble: n independent D1Q2 advection/Burgers instances with J uniform
+    in 8..14 and eps in {1e-3, 1e-4} (workloads.batch_instance) in one launch, against the
+    same instances advanced by one launch per time step and instance (a sample of them)."""
+    cases = []
+    for seed in range(n):
+        p, mc = W.batch_instance(seed, steps=steps)
+        p["precision"] = prec
+        cases.append((p, mc))
+    b = mrlbm.Batch([c[0] for c in cases], [c[1] for c in cases])
+    b.checkpoint()
+    t = b.tune(steps) if tune else None
+    b.step(steps)
+    b.restore()
+    u0 = b.total_updates()
+    ms = b.step_timed(steps)
+    upd = b.total_updates() - u0
+    shape = [b.get_block(), b.get_capacity(), b.get_schedule()]
+    b.close()
+    sample = cases[:: max(1, n // 64)]
+    rate_plain, _ = plain_step_rate(mrlbm, sample, 100)
+    js = [c[0]["jmax"] for c in cases]
+    return {"runs": n, "steps": steps, "j_max_range": [min(js), max(js)], "updates_per_s": upd / (ms / 1e3),
+            "ms": ms, "leaf_updates": upd, "tuned": t is not None,
+            "threads_capacity_schedule": shape,
+            "per_instance_launches_updates_per_s": rate_plain,
+            "speedup_vs_per_instance_launches": (upd / (ms / 1e3)) / rate_plain,
+            "per_instance_sample": len(sample)}
 
 
 def learned_form(mrlbm, n_train, n_test, steps, jmax=14, eps=1e-4, pos_weight=16.0, gate=8.0):
@@ -315,6 +347,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-step and delta checks")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-refinement form")
     ap.add_argument("--learned-steps", type=int, default=2400)
+    ap.add_argument("--ensemble-runs", type=int, default=4096, help="instances of the batched ensemble")
+    ap.add_argument("--ensemble-steps", type=int, default=512)
     ap.add_argument("--capacity", type=int, default=-1, help="on-chip capacity in cells (-1: tuner or default)")
     ap.add_argument("--schedule", type=int, default=-1, help="workgroup schedule stride (-1: tuner or identity)")
     ap.add_argument("--profile-summary", default="", help="only summarize rocprofv3 CSV output in this folder")
@@ -337,8 +371,10 @@ def main():
         print(f"bench.py measures a single GPU (asked for {args.gpus}): the batched engine runs on one "
               f"device; across GPUs the independent runs would be split by instance", file=sys.stderr)
         return 2
-    if args.steps <= 0 or args.warmup < 0 or args.seeds <= 0 or args.launch_steps < 0:
-        print("bench.py needs --steps > 0, --warmup >= 0, --seeds > 0, --launch-steps >= 0", file=sys.stderr)
+    if (args.steps <= 0 or args.warmup < 0 or args.seeds <= 0 or args.launch_steps < 0 or args.ensemble_runs <= 0
+            or args.ensemble_steps <= 0):
+        print("bench.py needs --steps > 0, --warmup >= 0, --seeds > 0, --launch-steps >= 0, --ensemble-runs > 0, "
+              "--ensemble-steps > 0", file=sys.stderr)
         return 2
 
     from paper_2102_12163_amd import mrlbm
@@ -460,6 +496,11 @@ def main():
                                "speed_vs_fp64": (u32 / (ms32 / 1e3)) / value,
                                "max_delta_over_eps": worst32,
                                "reference": "eps=0 FP64 run of the same library"}
+    if not args.no_extras and prec == 0:
+        print("[bench] batched ensemble", file=sys.stderr, flush=True)
+        result["ensemble_form"] = {
+            "fp64": ensemble_form(mrlbm, args.ensemble_runs, args.ensemble_steps, 0, not args.no_tune),
+            "fp32": ensemble_form(mrlbm, args.ensemble_runs, args.ensemble_steps, 1, not args.no_tune)}
     if not args.no_learned and prec == 0:
         print("[bench] learned-refinement form", file=sys.stderr, flush=True)
         result["learned_form"] = learned_form(mrlbm, 8, 64, args.learned_steps)

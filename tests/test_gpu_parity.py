@@ -359,3 +359,31 @@ def test_checkpoint_restore_repeats_the_same_steps():
         assert [b.stats(i) for i in range(len(cases))] == at
     finally:
         b.close()
+
+
+def test_batched_ensemble_at_full_size():
+    """The batched ensemble at its full size (4096 instances, J uniform in 8..14, advection
+    and Burgers, eps in {1e-3, 1e-4}) in the tuner's launch shape, as one launch: one sampled
+    instance per J_max against the oracle (leaves bit for bit, moments to 1e-12)."""
+    cases = [W.batch_instance(s, steps=0) for s in range(4096)]
+    announce("ensemble", len(cases))
+    ps, ms = [c[0] for c in cases], [c[1] for c in cases]
+    b = mrlbm.Batch(ps, ms)
+    try:
+        b.tune(8)
+        nsteps = 40
+        b.step(nsteps)
+        picked = {}
+        for i, p in enumerate(ps):
+            picked.setdefault(p["jmax"], i)
+        assert sorted(picked) == list(range(8, 15))
+        for j, i in sorted(picked.items()):
+            announce("ensemble instance", i, "J", j)
+            ora = make_oracle(ps[i], ms[i]).step(nsteps)
+            lv, ix = b.leaves(i)
+            olv, oix = ora.leaf_list()
+            assert np.array_equal(lv, olv) and np.array_equal(ix, oix), i
+            assert rel_err(b.moments(i), ora.leaf_conserved()) <= 1e-12, i
+        assert all(b.stats(i)["steps"] == nsteps for i in range(0, len(cases), 97))
+    finally:
+        b.close()
