@@ -99,6 +99,7 @@ struct Block {
     uint32_t* ldsL;   // on-chip leaf list
     typedef __attribute__((address_space(3))) uint32_t LU;
     LU* tab;          // split cells of the current tree: (own slot << 16) | slot of the even child
+    LU* tabp;         // and their cell indices p (same order)
     LU* toff;         // tab offsets per level: level l occupies [toff[l - jmin], toff[l - jmin + 1])
     static constexpr int NOFF = 24;  // offset entries in front of the table (levels + 1 <= 17)
     T cc[3];
@@ -135,6 +136,7 @@ struct Block {
         ldsB = (LT*)(T*)(lds + L.VB);
         ldsL = reinterpret_cast<uint32_t*>(lds + L.LL);
         tab = nullptr;
+        tabp = nullptr;
         toff = nullptr;
         for (int a = 0; a < 3; ++a) cc[a] = (T)d.c[a];
         any_declined = nullptr;
@@ -327,7 +329,8 @@ struct Block {
     // Slot table of a tree (split bits sp, R bits, slot prefix RP, split-word list wl) written
     // to dst (room for maxe words, in a dead part of a value array): NOFF words of per-level
     // offsets (toff), then the split cells in level order, each as (own slot << 16) | slot of
-    // its even child. The tree must fit on chip (slots < 2^16) and its split words must
+    // its even child, then their cell indices in the same order. The tree must fit on chip
+    // (slots < 2^16) and its split words must
     // number at most NT and nwJ (pre uses scanE, free at this point); returns false otherwise,
     // or when the split cells outnumber maxe (no table). Ends with a barrier when it returns
     // true.
@@ -352,9 +355,10 @@ struct Block {
         }
         uint32_t tot;
         const uint32_t base = block_scan(cnt, &tot);  // tasks are in level order
-        if (tot + NOFF > (uint32_t)maxe) return false;  // uniform: tot is the block total
+        if (2 * tot + NOFF > (uint32_t)maxe) return false;  // uniform: tot is the block total
         toff = dst;
         tab = dst + NOFF;
+        tabp = tab + tot;
         uint32_t* pre = scanE;
         if (tid < ntask) pre[tid] = base;
         __syncthreads();
@@ -370,7 +374,9 @@ struct Block {
                 const int p = (w << 6) + lane;
                 const uint32_t so = (uint32_t)rank_of(R, RP, jmin, l, p);
                 const uint32_t sc = (uint32_t)rank_of(R, RP, jmin, l + 1, 2 * p);
-                tab[pre[task] + (uint32_t)__popcll(b & ((1ull << lane) - 1ull))] = (so << 16) | sc;
+                const uint32_t e = pre[task] + (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
+                tab[e] = (so << 16) | sc;
+                tabp[e] = (uint32_t)p;
             }
         }
         __syncthreads();
@@ -558,6 +564,58 @@ struct Block {
                 }
                 (void)rw;
             }
+        }
+    }
+
+    // Details and decisions of the current tree from its slot table: one thread per split
+    // cell (all levels at once), the same arithmetic as details(); the keep and rule-(b)
+    // bits are set with LDS atomics (the words start cleared). Plain kernels only.
+    template <class V>
+    DEV void details_table(const V& Vx, int* nanflag) {
+        const int nlev = J - jmin + 1;
+        const int myoff = lane <= nlev ? (int)toff[lane] : 0;
+        const int total = __builtin_amdgcn_readlane(myoff, nlev - 1);  // start of level J
+        for (int e = tid; e < total; e += NT) {
+            int li = 0;
+            for (int i = 1; i < nlev - 1; ++i)
+                if (__builtin_amdgcn_readlane(myoff, i) <= e) li = i;
+            const int l = jmin + li;
+            const int N = 1 << l;
+            const uint32_t en = tab[e];
+            const int p = (int)tabp[e];
+            const int s0 = (int)(en >> 16), sc = (int)(en & 0xFFFFu);
+            int sp_[G], sm_[G];
+#pragma unroll
+            for (int a = 1; a <= G; ++a) {
+                sp_[a - 1] = rank_of(ro, rpo, jmin, l, bcx(p + a, N, bc));
+                sm_[a - 1] = rank_of(ro, rpo, jmin, l, bcx(p - a, N, bc));
+            }
+            double D = 0.0;
+            bool bad = false;
+#pragma unroll
+            for (int h = 0; h < Q; ++h) {
+                const double f0 = (double)Vx.ld(h, s0);
+                double acc = 0.0;
+#pragma unroll
+                for (int a = 1; a <= G; ++a) {
+                    const double tt = d.c[a - 1] * ((double)Vx.ld(h, sp_[a - 1]) - (double)Vx.ld(h, sm_[a - 1]));
+                    acc = (a == 1) ? tt : acc + tt;
+                }
+                const double pred = f0 + acc;
+                const double dd = (double)Vx.ld(h, sc) - pred;
+                const double ad = fabs(dd);
+                bad = bad || (ad != ad);
+                D = ad > D ? ad : D;
+            }
+            if (bad) *nanflag = 1;
+            const double thr = ldexp(d.eps, l + 1 - J);
+            const double thrb = ldexp(d.eps, d.mu_bar + 1 + l + 1 - J);
+            const bool kb = bad || (D >= thr);
+            const bool rbb = kb && (l + 1 < J) && (bad || D >= thrb);
+            const int wi = WB(l) + (p >> 6);
+            const unsigned long long bit = 1ull << (p & 63);
+            if (kb) atomicOr((unsigned long long*)&keep[wi], bit);
+            if (rbb) atomicOr((unsigned long long*)&ruleb[wi], bit);
         }
     }
 
@@ -963,7 +1021,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
             __syncthreads();
             if (where <= IN_LDS_B) {
                 VP<T, LT> VO{where == IN_LDS_A ? B.ldsA : B.ldsB, cap};
-                B.details(VO, &s_nan);
+                if (!LRN && tvalid) B.details_table(VO, &s_nan);
+                else B.details(VO, &s_nan);
             } else {
                 VP<T, T> VO{hbm_vals<T>(d, where - IN_HBM_0), Cg};
                 B.details(VO, &s_nan);
