@@ -97,25 +97,36 @@ DEV int bcx(int i, int n, int bc) {
 DEV uint64_t lowmask(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
 
 // 32 parent bits -> 64 child bits (each bit doubled).
+// Bit i of a 16-bit value to bit 2i (32-bit operations: the compiler fuses each shift-or-mask
+// step into one three-input bit operation).
+DEV uint32_t spread16(uint32_t y) {
+    y = (y | (y << 8)) & 0x00FF00FFu;
+    y = (y | (y << 4)) & 0x0F0F0F0Fu;
+    y = (y | (y << 2)) & 0x33333333u;
+    y = (y | (y << 1)) & 0x55555555u;
+    return y;
+}
+// 32 parent bits (low half of x) -> 64 child bits, each parent bit to both its children.
 DEV uint64_t spread32(uint64_t x) {
-    uint64_t y = x & 0xFFFFFFFFull;
-    y = (y | (y << 16)) & 0x0000FFFF0000FFFFull;
-    y = (y | (y << 8)) & 0x00FF00FF00FF00FFull;
-    y = (y | (y << 4)) & 0x0F0F0F0F0F0F0F0Full;
-    y = (y | (y << 2)) & 0x3333333333333333ull;
-    y = (y | (y << 1)) & 0x5555555555555555ull;
-    return y | (y << 1);
+    uint32_t lo = spread16((uint32_t)x & 0xFFFFu);
+    uint32_t hi = spread16(((uint32_t)x) >> 16);
+    lo |= lo << 1;
+    hi |= hi << 1;
+    return ((uint64_t)hi << 32) | lo;
 }
 
+// 32 child bits -> 16 parent bits (OR of each sibling pair).
+DEV uint32_t compress32(uint32_t x) {
+    uint32_t y = (x | (x >> 1)) & 0x55555555u;
+    y = (y | (y >> 1)) & 0x33333333u;
+    y = (y | (y >> 2)) & 0x0F0F0F0Fu;
+    y = (y | (y >> 4)) & 0x00FF00FFu;
+    y = (y | (y >> 8)) & 0x0000FFFFu;
+    return y;
+}
 // 64 child bits -> 32 parent bits (OR of each sibling pair).
 DEV uint64_t compress64(uint64_t x) {
-    uint64_t y = (x | (x >> 1)) & 0x5555555555555555ull;
-    y = (y | (y >> 1)) & 0x3333333333333333ull;
-    y = (y | (y >> 2)) & 0x0F0F0F0F0F0F0F0Full;
-    y = (y | (y >> 4)) & 0x00FF00FF00FF00FFull;
-    y = (y | (y >> 8)) & 0x0000FFFF0000FFFFull;
-    y = (y | (y >> 16)) & 0x00000000FFFFFFFFull;
-    return y;
+    return (uint64_t)(compress32((uint32_t)x) | (compress32((uint32_t)(x >> 32)) << 16));
 }
 
 DEV bool getbit(const uint64_t* A, int wbl, int k) { return (A[wbl + (k >> 6)] >> (k & 63)) & 1ull; }
@@ -173,6 +184,13 @@ DEV uint64_t dilate_word(const uint64_t* A, int wbl, int l, int w, int r, int bc
         }
     }
     return dilate_val(x, xl, xr, l, r, bc);
+}
+
+// Lane src's 64-bit value, as a wave-uniform value (src uniform).
+DEV uint64_t readlane64(uint64_t v, int src) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, src);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // 64-bit lane exchange inside a wave (two 32-bit halves).

@@ -662,33 +662,37 @@ struct Block {
     // lanes i - 1 and i + 1 and owns parent word i; parent words are stored as they come and
     // regrouped in pairs for the next level by lane exchange.
     DEV void grade_wave(int a) {
+        // the words of the single-word levels below min(a, 6) (level l < 6 is word l - jmin)
+        const int ncoarse = (a < 6 ? a : 6) - jmin;
+        const uint64_t cw = lane < ncoarse ? nsplit[lane] : 0ull;
         int cnw = nwords(a);
         uint64_t x0 = 2 * lane < cnw ? nsplit[WB(a) + 2 * lane] : 0ull;
         uint64_t x1 = 2 * lane + 1 < cnw ? nsplit[WB(a) + 2 * lane + 1] : 0ull;
         uint64_t old = lane < nwords(a - 1) ? nsplit[WB(a - 1) + lane] : 0ull;
-        for (; a > jmin; --a) {
+        for (; a > jmin && nwords(a) >= 2; --a) {
             cnw = nwords(a);
             const int pnw = nwords(a - 1);
             const uint64_t onext = (a - 2 >= jmin && lane < nwords(a - 2)) ? nsplit[WB(a - 2) + lane] : 0ull;
-            uint64_t v;
-            if (cnw >= 2) {
-                const int h = cnw >> 1;  // lanes holding words of level a
-                const uint64_t pl = shfl64(x1, (lane - 1) & (h - 1));
-                const uint64_t nx = shfl64(x0, (lane + 1) & (h - 1));
-                const uint64_t xl = (bc == PERIODIC || lane > 0) ? pl : 0ull;
-                const uint64_t xr = (bc == PERIODIC || lane < h - 1) ? nx : 0ull;
-                v = compress64(dilate_val(x0, xl, x1, a, G, bc)) |
-                    (compress64(dilate_val(x1, x0, xr, a, G, bc)) << 32);
-            } else {
-                // one word: a level of 64 cells wraps onto itself (or reads zero when clamped)
-                const uint64_t e = bc == PERIODIC ? x0 : 0ull;
-                v = compress64(dilate_val(x0, e, e, a, G, bc));
-            }
+            const int h = cnw >> 1;  // lanes holding words of level a
+            const uint64_t pl = shfl64(x1, (lane - 1) & (h - 1));
+            const uint64_t nx = shfl64(x0, (lane + 1) & (h - 1));
+            const uint64_t xl = (bc == PERIODIC || lane > 0) ? pl : 0ull;
+            const uint64_t xr = (bc == PERIODIC || lane < h - 1) ? nx : 0ull;
+            const uint64_t v = compress64(dilate_val(x0, xl, x1, a, G, bc)) |
+                               (compress64(dilate_val(x1, x0, xr, a, G, bc)) << 32);
             const uint64_t pw = v | old;
             if (lane < pnw) nsplit[WB(a - 1) + lane] = pw;
             x0 = shfl64(pw, 2 * lane);
             x1 = shfl64(pw, 2 * lane + 1);
             old = onext;
+        }
+        // single-word levels (at most 64 cells): the word is uniform, so the chain runs on
+        // the scalar unit; a level of 64 cells wraps onto itself (or reads zero when clamped)
+        uint64_t xs = readlane64(x0, 0);
+        for (; a > jmin; --a) {
+            const uint64_t e = bc == PERIODIC ? xs : 0ull;
+            xs = compress64(dilate_val(xs, e, e, a, G, bc)) | readlane64(cw, a - 1 - jmin);
+            if (lane == 0) nsplit[a - 1 - jmin] = xs;
         }
     }
 
