@@ -186,6 +186,20 @@ DEV uint64_t dilate_word(const uint64_t* A, int wbl, int l, int w, int r, int bc
     return dilate_val(x, xl, xr, l, r, bc);
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave with data-parallel-primitive moves:
+// within each row of 16 lanes by shifts of 1, 2, 4 and 8 (lanes shifted in from outside the
+// row read zero), then row 0's total into row 1 and row 2's into row 3 (row broadcast of lane
+// 15), then the total of rows 0-1 into rows 2 and 3 (row broadcast of lane 31).
+DEV uint32_t wave_scan(uint32_t x) {
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x111, 0xF, 0xF, true);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x112, 0xF, 0xF, true);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x114, 0xF, 0xF, true);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x118, 0xF, 0xF, true);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x142, 0xA, 0xF, false);  // row_bcast:15, rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x143, 0xC, 0xF, false);  // row_bcast:31, rows 2, 3
+    return x;
+}
+
 // Lane src's 64-bit value, as a wave-uniform value (src uniform).
 DEV uint64_t readlane64(uint64_t v, int src) {
     const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, src);

@@ -149,43 +149,28 @@ struct Block {
     DEV int list_tasks(WordList wl, int* first) const {
         const int nlev = J - jmin + 1;
         const int c = lane < nlev ? wl.c[jmin + lane] : 0;
-        int x = c;
-#pragma unroll
-        for (int o = 1; o < 32; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
+        const int x = (int)wave_scan((uint32_t)c);
         *first = x - c;
-        return __shfl(x, nlev - 1, 64);
+        return __builtin_amdgcn_readlane(x, nlev - 1);
     }
     // Level of task k (wave-uniform) and its position t inside the level's list.
     DEV int task_level(int k, int first, int* t) const {
         const int nlev = J - jmin + 1;
         const uint64_t m = __ballot(lane < nlev && first <= k);
         const int i = __popcll(m) - 1;
-        *t = k - __shfl(first, i, 64);
+        *t = k - __builtin_amdgcn_readlane(first, i);
         return jmin + i;
     }
 
     // ----------------------------------------------------------- block scan
     // Exclusive prefix of per-thread values; returns this thread's base, total in *tot.
     DEV uint32_t block_scan(uint32_t s, uint32_t* tot) {
-        uint32_t x = s;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
+        const uint32_t x = wave_scan(s);
         if (lane == 63) red[1 + wave] = x;
         __syncthreads();
         if (wave == 0) {  // exclusive scan of the wave totals, one lane per wave
             const uint32_t v = lane < nwaves ? red[1 + lane] : 0u;
-            uint32_t y = v;
-#pragma unroll
-            for (int o = 1; o < 16; o <<= 1) {
-                const uint32_t z = __shfl_up(y, o, 64);
-                if (lane >= o) y += z;
-            }
+            const uint32_t y = wave_scan(v);
             if (lane < nwaves) red[1 + lane] = y - v;
             if (lane == nwaves - 1) red[20] = y;
         }
