@@ -99,7 +99,7 @@ struct Block {
     uint32_t* ldsL;   // on-chip leaf list
     typedef __attribute__((address_space(3))) uint32_t LU;
     LU* tab;          // split cells of the current tree: (own slot << 16) | slot of the even child
-    LU* tabp;         // and their cell indices p (same order)
+    LU* tabp;         // and their keys (level << 27) | p (same order)
     LU* toff;         // tab offsets per level: level l occupies [toff[l - jmin], toff[l - jmin + 1])
     static constexpr int NOFF = 24;  // offset entries in front of the table (levels + 1 <= 17)
     T cc[3];
@@ -314,11 +314,10 @@ struct Block {
     // Slot table of a tree (split bits sp, R bits, slot prefix RP, split-word list wl) written
     // to dst (room for maxe words, in a dead part of a value array): NOFF words of per-level
     // offsets (toff), then the split cells in level order, each as (own slot << 16) | slot of
-    // its even child, then their cell indices in the same order. The tree must fit on chip
-    // (slots < 2^16) and its split words must
-    // number at most NT and nwJ (pre uses scanE, free at this point); returns false otherwise,
-    // or when the split cells outnumber maxe (no table). Ends with a barrier when it returns
-    // true.
+    // its even child, then their keys (level << 27) | p in the same order. The tree must fit
+    // on chip (slots < 2^16) and its split words must number at most NT and nwJ (pre uses
+    // scanE, free at this point); returns false otherwise, or when the table outgrows maxe
+    // (no table). Ends with a barrier when it returns true.
     DEV bool build_table(const uint64_t* sp, const uint64_t* R, const uint32_t* RP, WordList wl, LU* dst,
                          int maxe) {
         int first;
@@ -361,7 +360,7 @@ struct Block {
                 const uint32_t sc = (uint32_t)rank_of(R, RP, jmin, l + 1, 2 * p);
                 const uint32_t e = pre[task] + (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
                 tab[e] = (so << 16) | sc;
-                tabp[e] = (uint32_t)p;
+                tabp[e] = ((uint32_t)l << 27) | (uint32_t)p;
             }
         }
         __syncthreads();
@@ -561,13 +560,10 @@ struct Block {
         const int myoff = lane <= nlev ? (int)toff[lane] : 0;
         const int total = __builtin_amdgcn_readlane(myoff, nlev - 1);  // start of level J
         for (int e = tid; e < total; e += NT) {
-            int li = 0;
-            for (int i = 1; i < nlev - 1; ++i)
-                if (__builtin_amdgcn_readlane(myoff, i) <= e) li = i;
-            const int l = jmin + li;
+            const uint32_t key = tabp[e];
+            const int l = (int)(key >> 27), p = (int)(key & ((1u << 27) - 1u));
             const int N = 1 << l;
             const uint32_t en = tab[e];
-            const int p = (int)tabp[e];
             const int s0 = (int)(en >> 16), sc = (int)(en & 0xFFFFu);
             int sp_[G], sm_[G];
 #pragma unroll
