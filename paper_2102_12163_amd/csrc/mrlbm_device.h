@@ -372,6 +372,15 @@ DEV int rank_of(const uint64_t* R, const uint32_t* RP, int jmin, int l, int k) {
     const int w = wbase(jmin, l) + (k >> 6);
     return (int)RP[w] + __popcll(R[w] & ((1ull << (k & 63)) - 1ull));
 }
+// Number of set bits of x below the calling lane's index (masked bit count).
+DEV uint32_t popc_below_lane(uint64_t x) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(x >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)x, 0u));
+}
+// rank_of for the cell (l, 64 w + lane) of the calling lane.
+DEV int rank_lane(const uint64_t* R, const uint32_t* RP, int jmin, int l, int w) {
+    const int wi = wbase(jmin, l) + w;
+    return (int)RP[wi] + (int)popc_below_lane(R[wi]);
+}
 DEV bool rbit(const uint64_t* R, int jmin, int l, int k) { return (R[wbase(jmin, l) + (k >> 6)] >> (k & 63)) & 1ull; }
 
 template <typename T, typename P>

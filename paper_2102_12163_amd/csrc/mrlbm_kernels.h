@@ -292,7 +292,7 @@ struct Block {
                 if ((b >> lane) & 1ull) {
                     const int p = (w << 6) + lane;
                     const int sc = rank_of(R, RP, jmin, l + 1, 2 * p);
-                    const int sp_ = rank_of(R, RP, jmin, l, p);
+                    const int sp_ = rank_lane(R, RP, jmin, l, w);
                     T g0[Q], g1[Q];
 #pragma unroll
                     for (int h = 0; h < Q; ++h) {
@@ -356,9 +356,9 @@ struct Block {
             const uint64_t b = sp[WB(l) + w];
             if ((b >> lane) & 1ull) {
                 const int p = (w << 6) + lane;
-                const uint32_t so = (uint32_t)rank_of(R, RP, jmin, l, p);
+                const uint32_t so = (uint32_t)rank_lane(R, RP, jmin, l, w);
                 const uint32_t sc = (uint32_t)rank_of(R, RP, jmin, l + 1, 2 * p);
-                const uint32_t e = pre[task] + (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
+                const uint32_t e = pre[task] + popc_below_lane(b);
                 tab[e] = (so << 16) | sc;
                 tabp[e] = ((uint32_t)l << 27) | (uint32_t)p;
             }
@@ -485,7 +485,7 @@ struct Block {
                 if ((b >> lane) & 1ull) {
                     const int p = (w << 6) + lane;
                     const int sc = rank_of(ro, rpo, jmin, l + 1, 2 * p);
-                    const int s0 = rank_of(ro, rpo, jmin, l, p);
+                    const int s0 = rank_lane(ro, rpo, jmin, l, w);
                     int sp_[G], sm_[G];
 #pragma unroll
                     for (int a = 1; a <= G; ++a) {
@@ -708,7 +708,7 @@ struct Block {
                     const int k = (w << 6) + lane;
                     T f[Q];
                     if (rbit(ro, jmin, l, k)) {
-                        const int so = rank_of(ro, rpo, jmin, l, k);
+                        const int so = rank_lane(ro, rpo, jmin, l, w);
 #pragma unroll
                         for (int h = 0; h < Q; ++h) f[h] = VO.ld(h, so);
                     } else {
@@ -724,7 +724,7 @@ struct Block {
                         const int e = k << (J - l);
                         atomicOr((unsigned long long*)&E[e >> 6], 1ull << (e & 63));
                     }
-                    const int sn = rank_of(keep, rpn, jmin, l, k);
+                    const int sn = rank_lane(keep, rpn, jmin, l, w);
 #pragma unroll
                     for (int h = 0; h < Q; ++h) VN.st(h, sn, f[h]);
                 }
