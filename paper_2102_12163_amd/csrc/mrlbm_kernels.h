@@ -324,12 +324,14 @@ struct Block {
         const int ntask = list_tasks(wl, &first);
         if (ntask > NT || ntask > lay.nwJ || (int)RP[wt] > lay.cap || lay.cap > 65535) return false;
         const int nlev = J - jmin + 1;
-        int li = 0, fl = 0;  // level of task tid, every lane
-        for (int i = 0; i < nlev; ++i) {
-            const int fi = __builtin_amdgcn_readlane(first, i);
-            if (fi <= tid) {
-                li = i;
-                fl = fi;
+        int li = 0, fl = 0;  // level of task tid (waves that hold tasks)
+        if (wave * 64 < ntask) {
+            for (int i = 0; i < nlev; ++i) {
+                const int fi = __builtin_amdgcn_readlane(first, i);
+                if (fi <= tid) {
+                    li = i;
+                    fl = fi;
+                }
             }
         }
         uint32_t cnt = 0;
