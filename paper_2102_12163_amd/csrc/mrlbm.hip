@@ -184,6 +184,10 @@ Coef make_coef(const mrlbm_params* p, const SchemeInfo& si) {
     }
     c.physics = p->physics;
     c.qc = si.qc;
+    int ex = 0;
+    c.lam_pow2 = std::frexp(p->lambda, &ex) == 0.5 ? 1 : 0;
+    c.ilam = 1.0 / c.lam;
+    c.ilam2 = 1.0 / c.lam2;
     return c;
 }
 

@@ -31,7 +31,9 @@ constexpr int ADVECTION = 0, BURGERS = 1, SHALLOW_WATER = 2, EULER = 3;
 struct Coef {
     double lam, lam2, V, alam2, g2, gam, k3, gm1, k5;
     double s[MAXQ], oms[MAXQ];
+    double ilam, ilam2;  // 1 / lam and 1 / lam^2 (exact when lam_pow2)
     int physics, qc;
+    int lam_pow2;        // lam is a power of two: dividing by lam or lam^2 is an exact scaling
 };
 
 struct Desc {
@@ -245,16 +247,26 @@ template <int S> struct AllPops { DEV static constexpr int h(int m) { return m; 
 // Leaves collision (Sec. 4.5, eq. LeavesCollision) with the equilibria of Sec. 5: the
 // conserved moments stay, every other moment relaxes m* = (1 - s) m + s m_eq. The
 // expression order is fixed (it is the order the FP64 checks were written against).
+// x / d; when d is a power of two, x * (1 / d) instead: the same correctly rounded value
+// (both are the exact scaling of x), without the division sequence.
+template <typename T>
+DEV T div_by(T x, T d, T inv, bool pow2) {
+    if (pow2) return x * inv;
+    return x / d;
+}
+
 template <typename T, int S>
 DEV void collide(const Coef& c, T* f) {
     const T lam = (T)c.lam;
+    const T ilam = (T)c.ilam;
+    const bool p2 = c.lam_pow2 != 0;
     const T half = (T)0.5;
     if constexpr (S == 0) {
         const T u = f[0] + f[1];
         const T m1 = lam * (f[0] - f[1]);
         const T eq = c.physics == ADVECTION ? (T)c.V * u : (u * u) * half;
         const T m1s = (T)c.oms[0] * m1 + (T)c.s[0] * eq;
-        const T r = m1s / lam;
+        const T r = div_by(m1s, lam, ilam, p2);
         f[0] = half * (u + r);
         f[1] = half * (u - r);
     } else if constexpr (S == 1) {
@@ -273,8 +285,8 @@ DEV void collide(const Coef& c, T* f) {
             m1s = m1;
             m2s = (T)c.oms[0] * m2 + (T)c.s[0] * eq2;
         }
-        const T a = m2s / lam2;
-        const T b = m1s / lam;
+        const T a = div_by(m2s, lam2, (T)c.ilam2, p2);
+        const T b = div_by(m1s, lam, ilam, p2);
         f[0] = m0 - a;
         f[1] = half * (a + b);
         f[2] = half * (a - b);
@@ -295,7 +307,7 @@ DEV void collide(const Coef& c, T* f) {
         for (int b = 0; b < NB; ++b) {
             const T n = lam * (f[2 * b] - f[2 * b + 1]);
             const T ns = (T)c.oms[b] * n + (T)c.s[b] * eq[b];
-            const T r = ns / lam;
+            const T r = div_by(ns, lam, ilam, p2);
             f[2 * b] = half * (cc[b] + r);
             f[2 * b + 1] = half * (cc[b] - r);
         }
