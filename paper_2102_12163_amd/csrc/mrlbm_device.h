@@ -202,6 +202,22 @@ DEV uint32_t wave_scan(uint32_t x) {
     return x;
 }
 
+// 64-bit value of the previous lane (lane 0: zero) and of the next lane (lane 63: zero), by
+// whole-wave DPP shifts; the 32-bit value of the other lane of each even/odd lane pair.
+DEV uint64_t from_prev_lane(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)v, 0x138, 0xF, 0xF, false);  // wave_shr:1
+    const uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(v >> 32), 0x138, 0xF, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+DEV uint64_t from_next_lane(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)v, 0x130, 0xF, 0xF, false);  // wave_shl:1
+    const uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(v >> 32), 0x130, 0xF, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+DEV uint32_t from_pair_lane(uint32_t v) {
+    return __builtin_amdgcn_update_dpp(0u, v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+}
+
 // Lane src's 64-bit value, as a wave-uniform value (src uniform).
 DEV uint64_t readlane64(uint64_t v, int src) {
     const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, src);

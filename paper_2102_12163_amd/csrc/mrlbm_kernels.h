@@ -648,30 +648,45 @@ struct Block {
         // the words of the single-word levels below min(a, 6) (level l < 6 is word l - jmin)
         const int ncoarse = (a < 6 ? a : 6) - jmin;
         const uint64_t cw = lane < ncoarse ? nsplit[lane] : 0ull;
-        int cnw = nwords(a);
-        uint64_t x0 = 2 * lane < cnw ? nsplit[WB(a) + 2 * lane] : 0ull;
-        uint64_t x1 = 2 * lane + 1 < cnw ? nsplit[WB(a) + 2 * lane + 1] : 0ull;
-        uint64_t old = lane < nwords(a - 1) ? nsplit[WB(a - 1) + lane] : 0ull;
-        for (; a > jmin && nwords(a) >= 2; --a) {
-            cnw = nwords(a);
-            const int pnw = nwords(a - 1);
-            const uint64_t onext = (a - 2 >= jmin && lane < nwords(a - 2)) ? nsplit[WB(a - 2) + lane] : 0ull;
-            const int h = cnw >> 1;  // lanes holding words of level a
+        // a level of 128 words (two per lane): its parents, one per lane
+        if (a > jmin && nwords(a) > 64) {
+            const int h = nwords(a) >> 1;  // 64
+            const uint64_t x0 = nsplit[WB(a) + 2 * lane], x1 = nsplit[WB(a) + 2 * lane + 1];
+            const uint64_t old = nsplit[WB(a - 1) + lane];
             const uint64_t pl = shfl64(x1, (lane - 1) & (h - 1));
             const uint64_t nx = shfl64(x0, (lane + 1) & (h - 1));
             const uint64_t xl = (bc == PERIODIC || lane > 0) ? pl : 0ull;
             const uint64_t xr = (bc == PERIODIC || lane < h - 1) ? nx : 0ull;
-            const uint64_t v = compress64(dilate_val(x0, xl, x1, a, G, bc)) |
-                               (compress64(dilate_val(x1, x0, xr, a, G, bc)) << 32);
-            const uint64_t pw = v | old;
-            if (lane < pnw) nsplit[WB(a - 1) + lane] = pw;
-            x0 = shfl64(pw, 2 * lane);
-            x1 = shfl64(pw, 2 * lane + 1);
+            const uint64_t pw = old | compress64(dilate_val(x0, xl, x1, a, G, bc)) |
+                                (compress64(dilate_val(x1, x0, xr, a, G, bc)) << 32);
+            nsplit[WB(a - 1) + lane] = pw;
+            --a;
+        }
+        // levels of 2..64 words: word i of the level in lane i
+        uint64_t x = lane < nwords(a) ? nsplit[WB(a) + lane] : 0ull;
+        uint64_t old = lane < nwords(a - 1) ? nsplit[WB(a - 1) + lane] : 0ull;
+        for (; a > jmin && nwords(a) >= 2; --a) {
+            const int cnw = nwords(a);
+            const int pnw = cnw >> 1;
+            const uint64_t onext = (a - 2 >= jmin && lane < nwords(a - 2)) ? nsplit[WB(a - 2) + lane] : 0ull;
+            // neighbour words from the adjacent lanes; the ends wrap within the cnw lanes
+            // (periodic) or read zero (clamp)
+            const uint64_t wl = bc == PERIODIC ? readlane64(x, cnw - 1) : 0ull;
+            const uint64_t wr = bc == PERIODIC ? readlane64(x, 0) : 0ull;
+            const uint64_t pv = from_prev_lane(x), nv = from_next_lane(x);
+            const uint64_t xl = lane == 0 ? wl : pv;
+            const uint64_t xr = lane == cnw - 1 ? wr : nv;
+            // half of parent word i >> 1 (low half from the even word)
+            const uint32_t c = (uint32_t)compress64(dilate_val(x, xl, xr, a, G, bc));
+            const uint32_t o = from_pair_lane(c);
+            const uint64_t pe = (uint64_t)c | ((uint64_t)o << 32);  // parent word lane / 2, even lanes
+            x = shfl64(pe, 2 * lane) | old;                          // parent word j in lane j
+            if (lane < pnw) nsplit[WB(a - 1) + lane] = x;
             old = onext;
         }
         // single-word levels (at most 64 cells): the word is uniform, so the chain runs on
         // the scalar unit; a level of 64 cells wraps onto itself (or reads zero when clamped)
-        uint64_t xs = readlane64(x0, 0);
+        uint64_t xs = readlane64(x, 0);
         for (; a > jmin; --a) {
             const uint64_t e = bc == PERIODIC ? xs : 0ull;
             xs = compress64(dilate_val(xs, e, e, a, G, bc)) | readlane64(cw, a - 1 - jmin);
