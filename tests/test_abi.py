@@ -108,6 +108,17 @@ def test_batch_rejects_mixed_schemes():
     assert e.value.code == mrlbm.EINVAL
 
 
+def test_batch_calls_reject_null_handles():
+    """Every batch call checks its handle and arguments on the host before any device work."""
+    L = mrlbm.lib()
+    assert L.mrlbm_batch_checkpoint(None) == mrlbm.EINVAL
+    assert L.mrlbm_batch_restore(None) == mrlbm.EINVAL
+    assert L.mrlbm_batch_set_launch_steps(None, 10) == mrlbm.EINVAL
+    assert L.mrlbm_batch_set_schedule(None, 0) == mrlbm.EINVAL
+    assert L.mrlbm_batch_tune(None, 10, None, None) == mrlbm.EINVAL
+    assert L.mrlbm_batch_step(None, 1) == mrlbm.EINVAL
+
+
 def test_bench_refuses_several_gpus_and_empty_regions():
     """bench.py measures one GPU: N > 1 and an empty timed region exit with status 2 and a
     message, before touching the library."""
