@@ -175,8 +175,8 @@ int mrlbm_batch_set_capacity(mrlbm_batch_t b, int32_t cells);
 /* Built-in tuner: times trial_steps steps of the batch for every candidate launch shape
  * (threads per workgroup 128/256/384/512 x LDS capacity for 1, 2 or 3 runs per compute
  * unit), then for every candidate schedule (see mrlbm_batch_set_schedule: identity, the
- * device's CU count, 8), restoring the runs' state after each trial, and keeps the fastest
- * (leaf-cell updates/s). The runs end in the state they had before the call. Allocates a
+ * device's CU count, 8, heaviest first), restoring the runs' state after each trial, and
+ * keeps the fastest (leaf-cell updates/s). The runs end in the state they had before the call. Allocates a
  * temporary snapshot of the handle's device memory. Chosen values are returned when the
  * pointers are non-NULL. */
 int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int32_t* cells);
@@ -185,7 +185,9 @@ int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int
  * (larger j_max, then smaller eps, which keeps more cells, then more leaves at the call);
  * the workgroups i with (i / s) even take the heaviest runs in order and workgroup i + s the
  * lightest ones, so that workgroups sharing a compute unit pair a heavy run with a light one
- * (the launch lasts as long as its slowest run). get_schedule returns the stride in use. */
+ * (the launch lasts as long as its slowest run). stride >= the number of runs: heaviest
+ * first (for batches larger than the device holds at once, the light runs fill the slots
+ * the heavy ones free). get_schedule returns the stride in use. */
 int mrlbm_batch_set_schedule(mrlbm_batch_t b, int32_t stride);
 int mrlbm_batch_get_schedule(mrlbm_batch_t b, int32_t* stride);
 /* Longest launch: a step call of more steps is issued as consecutive launches of at most

@@ -825,10 +825,14 @@ static void make_schedule(int stride, const std::vector<long long>& cost, std::v
     const int n = (int)cost.size();
     perm.resize(n);
     for (int i = 0; i < n; ++i) perm[i] = i;
-    if (stride <= 0 || stride >= n) return;
+    if (stride <= 0) return;
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    if (stride >= n) {  // heaviest first: later workgroups fill the slots the light runs free
+        perm = order;
+        return;
+    }
     int hi = 0, lo = n - 1;
     for (int b = 0; b < n; ++b) {
         if ((b / stride) % 2) continue;
@@ -949,10 +953,10 @@ int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int
         int dev = 0, ncu = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        const int strides[3] = {0, ncu, 8};
+        const int strides[4] = {0, ncu, 8, e->n};
         double best_s = -1.0;
-        for (int si = 0; si < 3 && rc == MRLBM_OK; ++si) {
-            if (si > 0 && (strides[si] <= 0 || strides[si] >= e->n)) continue;
+        for (int si = 0; si < 4 && rc == MRLBM_OK; ++si) {
+            if (si > 0 && si < 3 && (strides[si] <= 0 || strides[si] >= e->n)) continue;
             if ((rc = set_schedule(e, strides[si])) != MRLBM_OK) break;
             double rate = 0.0;
             if ((rc = trial(&rate)) != MRLBM_OK) break;

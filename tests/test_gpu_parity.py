@@ -277,6 +277,10 @@ def test_schedule_does_not_change_results():
         assert b.get_schedule() == 5
         a.step(25)
         b.step(25)
+        b.set_schedule(len(cases))  # heaviest first
+        assert b.get_schedule() == len(cases)
+        a.step(4)
+        b.step(4)
         b.set_schedule(1)
         b.set_launch_steps(3)  # 7 steps as launches of 3, 3, 1
         a.step(7)
