@@ -25,7 +25,7 @@ template <> struct LdsT<float> { typedef __attribute__((address_space(3))) float
 
 // Byte offsets of the dynamic LDS of one workgroup.
 struct Layout {
-    int wt, nwJ, cap, capS;
+    int wt, ws, nwJ, cap, capS;
     unsigned bits, E, VA, VB, PP, rp, scanE, LL, wl, total;
 };
 __host__ __device__ inline unsigned al16(unsigned x) { return (x + 15u) & ~15u; }
@@ -33,12 +33,13 @@ __host__ __device__ inline Layout make_layout(int jmin, int J, int cap, int capS
                                               bool learned = false) {
     Layout L;
     L.wt = wbase(jmin, J + 1);
+    L.ws = wbase(jmin, J);  // levels Jmin..J-1: the split-bit arrays (no split cell at J)
     L.nwJ = nwords(J);
     L.cap = cap;
     L.capS = capS;
     unsigned o = 0;
     L.bits = o;
-    o = al16(o + (learned ? 7u : 5u) * (unsigned)L.wt * 8u);
+    o = al16(o + ((learned ? 4u : 2u) * (unsigned)L.ws + 3u * (unsigned)L.wt) * 8u);
     L.E = o;
     o = al16(o + (unsigned)L.nwJ * 8u);
     L.VA = o;
@@ -77,7 +78,7 @@ struct Block {
 
     const Desc& d;
     int tid, NT, lane, wave, nwaves;
-    int jmin, J, bc, wt;
+    int jmin, J, bc, wt, ws;
     Layout lay;
     uint32_t* red;    // small scratch: [0] leaf count, [1..16] wave partials
     // tree arrays, rotated at the end of each step
@@ -115,14 +116,15 @@ struct Block {
         J = d.jmax;
         bc = d.bc;
         wt = L.wt;
+        ws = L.ws;
         uint64_t* bits = reinterpret_cast<uint64_t*>(lds + L.bits);
         split = bits;
-        nsplit = bits + wt;
-        keep = bits + 2 * wt;
-        ruleb = bits + 3 * wt;
-        ro = bits + 4 * wt;
-        forced = LRN ? bits + 5 * wt : nullptr;
-        declined = LRN ? bits + 6 * wt : nullptr;
+        nsplit = bits + ws;
+        keep = bits + 2 * ws;
+        ruleb = keep + wt;
+        ro = ruleb + wt;
+        forced = LRN ? ro + wt : nullptr;
+        declined = LRN ? ro + wt + ws : nullptr;
         E = reinterpret_cast<uint64_t*>(lds + L.E);
         uint32_t* rp = reinterpret_cast<uint32_t*>(lds + L.rp);
         rpo = rp;
@@ -608,7 +610,7 @@ struct Block {
     // both children of a flagged cell are split. Writes every word of nsplit.
     DEV void enlarge() {
         const int ra = 1;  // ceil(sigma / 2) for sigma = 1 (every built-in scheme)
-        for (int w = tid; w < wt; w += NT) {
+        for (int w = tid; w < ws; w += NT) {
             int t;
             const int l = level_of_word(jmin, w, &t);
             uint64_t v = 0;
@@ -966,7 +968,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
     }
     if (threadIdx.x < 24) s_red[threadIdx.x] = 0;
     const int wsplit = wbase(d.jmin, d.jmax);
-    for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) B.split[w] = w < wsplit ? d.split[w] : 0ull;
+    for (int w = threadIdx.x; w < lay.ws; w += blockDim.x) B.split[w] = d.split[w];
     for (int w = threadIdx.x; w < lay.nwJ; w += blockDim.x) B.E[w] = 0ull;
     __syncthreads();
     B.build_tree(B.split, B.ro, B.rpo, B.swl, nullptr, B.lwl);
@@ -1000,7 +1002,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
     for (int stp = 0; stp < nsteps; ++stp) {
         // ---- projection of f^n up the old tree (once per step, kept through redos)
         if constexpr (LRN)
-            for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) B.forced[w] = 0ull;
+            for (int w = threadIdx.x; w < lay.ws; w += blockDim.x) B.forced[w] = 0ull;
         if (where <= IN_LDS_B) {
             VP<T, LT> VO{where == IN_LDS_A ? B.ldsA : B.ldsB, cap};
             if (tvalid) B.project_table(VO);
@@ -1017,7 +1019,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
             for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) {
                 B.keep[w] = 0ull;
                 B.ruleb[w] = 0ull;
-                if constexpr (LRN) B.declined[w] = 0ull;
+                if constexpr (LRN)
+                    if (w < lay.ws) B.declined[w] = 0ull;
             }
             if (threadIdx.x == 0) s_dec = 0;
             __syncthreads();
@@ -1111,7 +1114,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
             if constexpr (LRN) {
                 // after a few redos every rule-(b) pair is forced: the plain rule, no misses
                 if (attempt >= 8)
-                    for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) B.forced[w] = ~0ull;
+                    for (int w = threadIdx.x; w < lay.ws; w += blockDim.x) B.forced[w] = ~0ull;
             }
         }
         B.rotate();
@@ -1208,12 +1211,11 @@ __global__ __launch_bounds__(512) void k_query(const Desc* __restrict__ descs, S
     B_t B(d, lay, lds, s_red, s_cnt);
     const int Cg = (1 << (d.jmax + 1)) - (1 << d.jmin);
     if (threadIdx.x < 24) s_red[threadIdx.x] = 0;
-    const int wsplit = wbase(d.jmin, d.jmax);
-    for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) B.split[w] = w < wsplit ? d.split[w] : 0ull;
+    for (int w = threadIdx.x; w < lay.ws; w += blockDim.x) B.split[w] = d.split[w];
     for (int w = threadIdx.x; w < lay.nwJ; w += blockDim.x) B.E[w] = 0ull;
     __syncthreads();
     // The current tree plays the role of the "new" tree of a step (keep = R bits, ruleb = leaf bits).
-    for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) B.nsplit[w] = B.split[w];
+    for (int w = threadIdx.x; w < lay.ws; w += blockDim.x) B.nsplit[w] = B.split[w];
     __syncthreads();
     B.build_tree(B.nsplit, B.keep, B.rpn, B.nswl, B.ruleb, B.lwl);
     const int n = (int)B.red[0];
