@@ -391,3 +391,38 @@ def test_batched_ensemble_at_full_size():
         assert all(b.stats(i)["steps"] == nsteps for i in range(0, len(cases), 97))
     finally:
         b.close()
+
+
+def test_bench_workload_whole_run_sampled():
+    """The benchmark's timed region in full: the 510-run Burgers batch from t = 0 to T = 0.4
+    (3277 steps) as one launch at on-chip capacity 999, where the heaviest trees outgrow the
+    LDS at times and those steps take the HBM path; the heaviest run of each eps against the
+    oracle at the end (leaves bit for bit, moments to 1e-12)."""
+    cases = []
+    for s in (1.5, 1.9):
+        for eps in (1e-2, 1e-3, 1e-4):
+            for seed in range(85):
+                cases.append(W.burgers(seed, jmax=14, eps=eps, s=s))
+    announce("bench whole run", len(cases))
+    ps, ms = [c[0] for c in cases], [c[1] for c in cases]
+    b = mrlbm.Batch(ps, ms)
+    try:
+        b.set_block(512)
+        b.set_capacity(999)
+        b.set_schedule(256)
+        nsteps = 3277
+        b.step(nsteps)
+        picked = []
+        for eps in (1e-2, 1e-3, 1e-4):
+            idx = [i for i, p in enumerate(ps) if p["eps"] == eps and p["s"][0] == 1.9]
+            picked.append(max(idx, key=lambda i: b.stats(i)["tree_cells"]))
+        for i in picked:
+            announce("whole-run instance", i, "tree cells", b.stats(i)["tree_cells"])
+            ora = make_oracle(ps[i], ms[i]).step(nsteps)
+            lv, ix = b.leaves(i)
+            olv, oix = ora.leaf_list()
+            assert np.array_equal(lv, olv) and np.array_equal(ix, oix), i
+            assert rel_err(b.moments(i), ora.leaf_conserved()) <= 1e-12, i
+            assert b.stats(i)["leaf_updates"] == ora.leaf_updates, i
+    finally:
+        b.close()
