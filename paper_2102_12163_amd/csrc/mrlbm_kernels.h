@@ -55,10 +55,12 @@ __host__ __device__ inline Layout make_layout(int jmin, int J, int cap, int capS
     o = al16(o + 2u * (unsigned)(L.wt + 1) * 4u);
     L.scanE = o;
     o = al16(o + (unsigned)L.nwJ * 4u);
+    // leaf list: without the predictor it lives in the old value array behind the pairs
+    // (written after the transfer, read until the next one)
     L.LL = o;
-    o = al16(o + (unsigned)capS * 4u);
+    if (learned) o = al16(o + (unsigned)capS * 4u);
     L.wl = o;
-    o = al16(o + 3u * (unsigned)L.wt * 2u);
+    o = al16(o + (2u * (unsigned)L.ws + (unsigned)L.wt) * 2u);  // split words: levels < J
     L.total = o;
     return L;
 }
@@ -132,11 +134,11 @@ struct Block {
         scanE = reinterpret_cast<uint32_t*>(lds + L.scanE);
         uint16_t* wl = reinterpret_cast<uint16_t*>(lds + L.wl);
         swl = {wl, cnts};
-        nswl = {wl + wt, cnts + 32};
-        lwl = {wl + 2 * wt, cnts + 64};
+        nswl = {wl + ws, cnts + 32};
+        lwl = {wl + 2 * ws, cnts + 64};
         ldsA = (LT*)(T*)(lds + L.VA);
         ldsB = (LT*)(T*)(lds + L.VB);
-        ldsL = reinterpret_cast<uint32_t*>(lds + L.LL);
+        ldsL = LRN ? reinterpret_cast<uint32_t*>(lds + L.LL) : nullptr;  // plain: set per step
         tab = nullptr;
         tabp = nullptr;
         toff = nullptr;
@@ -1042,7 +1044,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
             if (where <= IN_LDS_B) nwhere = (nR <= cap) ? (IN_LDS_B - where) : IN_HBM_0;
             else nwhere = (nR <= cap) ? IN_LDS_A : (where == IN_HBM_0 ? IN_HBM_1 : IN_HBM_0);
             fast = (where <= IN_LDS_B) && (nwhere <= IN_LDS_B) && (n <= capS) &&
-                   (LRN || 2 * B_t::NM * (n + 1) <= Q * cap);
+                   (LRN || (unsigned)(2 * B_t::NM * (n + 1)) * sizeof(T) + 4u * (unsigned)n <=
+                               (unsigned)(Q * cap) * sizeof(T));
             if (threadIdx.x == 0) s_miss = 0;
             if constexpr (!LRN) tvalid = false;
             if (fast) {
@@ -1050,12 +1053,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                 VP<T, LT> VN{nwhere == IN_LDS_A ? B.ldsA : B.ldsB, cap};
                 B.transfer(VO, VN, scheme, &s_nan);
                 if constexpr (!LRN) {
-                    // the new tree's table goes to the old array behind the interface pairs:
-                    // dead there until the next transfer, after the next step's projection
+                    // the old array, dead until the next transfer, holds the interface pairs,
+                    // then this step's leaf list, then the new tree's table (read by the next
+                    // step's projection and details)
                     const int pe = 2 * B_t::NM * (n + 1);
-                    const unsigned off = (where == IN_LDS_A ? lay.VA : lay.VB) + (unsigned)pe * sizeof(T);
-                    tvalid = B.build_table(B.nsplit, B.keep, B.rpn, B.nswl, (typename B_t::LU*)(lds + off),
-                                           (int)(((unsigned)(Q * cap - pe) * sizeof(T)) / 4u));
+                    const unsigned loff = (where == IN_LDS_A ? lay.VA : lay.VB) + (unsigned)pe * sizeof(T);
+                    B.ldsL = reinterpret_cast<uint32_t*>(lds + loff);
+                    const unsigned toff_ = loff + 4u * (unsigned)n;
+                    tvalid = B.build_table(B.nsplit, B.keep, B.rpn, B.nswl, (typename B_t::LU*)(lds + toff_),
+                                           (int)(((unsigned)(Q * cap - pe) * sizeof(T) - 4u * (unsigned)n) / 4u));
                 }
                 if (scheme) {
                     B.scan_edges();
