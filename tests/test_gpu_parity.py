@@ -298,7 +298,7 @@ def test_schedule_does_not_change_results():
 
 def test_bench_workload_in_bench_launch_configuration():
     """The full Burgers batch of the benchmark (510 runs, J = 14) in the launch configuration
-    the benchmark times (512 threads, on-chip capacity 1081 cells, heavy/light schedule
+    the benchmark times (512 threads, on-chip capacity 1148 cells, heavy/light schedule
     set after a warmup, runs restored to t = 0, the timed steps as one launch): sampled runs
     against the oracle, the rest against a batch with the default launch shape (bit for
     bit)."""
@@ -313,7 +313,7 @@ def test_bench_workload_in_bench_launch_configuration():
     ref = mrlbm.Batch(ps, ms)
     try:
         b.set_block(512)
-        b.set_capacity(1081)
+        b.set_capacity(1148)
         b.checkpoint()
         b.step(113)
         b.set_schedule(256)
