@@ -252,7 +252,7 @@ def test_tuner_keeps_state_and_results():
     a.step(10)
     b.step(10)
     threads, cells = a.tune(5)
-    assert threads in (128, 256, 512) and cells >= 0
+    assert threads in (128, 256, 384, 512) and cells >= 0
     assert all(a.stats(i)["steps"] == 10 for i in range(len(cases)))
     a.step(25)
     b.step(25)
@@ -260,6 +260,31 @@ def test_tuner_keeps_state_and_results():
         assert np.array_equal(a.moments(i), b.moments(i))
     a.close()
     b.close()
+
+
+def test_block_size_does_not_change_results():
+    """FP32-storage runs give the same bits at 128 and 384 threads per workgroup as at 512
+    (every thread count reaches the same per-cell arithmetic)."""
+    cases = [W.batch_instance(s, steps=0) for s in range(8)]
+    ps = [dict(c[0], precision=mrlbm.FP32_STORAGE) for c in cases]
+    ms = [c[1] for c in cases]
+    announce("block sizes", [p["jmax"] for p in ps])
+    ref = mrlbm.Batch(ps, ms)
+    ref.set_block(512)
+    ref.step(40)
+    for nt in (384, 128):
+        b = mrlbm.Batch(ps, ms)
+        b.set_block(nt)
+        assert b.get_block() == nt
+        b.step(25)
+        b.step(15)
+        for i in range(len(ps)):
+            assert np.array_equal(b.moments(i), ref.moments(i)), (nt, i)
+            lv, ix = b.leaves(i)
+            rlv, rix = ref.leaves(i)
+            assert np.array_equal(lv, rlv) and np.array_equal(ix, rix), (nt, i)
+        b.close()
+    ref.close()
 
 
 def test_schedule_does_not_change_results():
