@@ -237,7 +237,8 @@ struct Block {
     // ----------------------------------------------------------- A1 / B2: projection
     // Every split cell takes half the sum of its two children (adjacent slots), finest
     // level first (Sec. 3.1, Definition Projection operator).
-    template <class V>
+    // PM / NP: the populations projected (all of them by default).
+    template <class PM = AllPops<S>, int NP = Q, class V>
     DEV bool project_up(const V& Vx, const uint64_t* sp, const uint64_t* R, const uint32_t* RP, WordList sl) {
         // Two levels per barrier: the thread of a split cell (l-1, p) first takes the average
         // of each split child (l, 2p + c) from its own children, stores it, then stores its own
@@ -255,7 +256,7 @@ struct Block {
                 const uint64_t b = sp[WB(lp) + w];
                 if ((b >> lane) & 1ull) {
                     const int p = (w << 6) + lane;
-                    T cv[2][Q];
+                    T cv[2][NP];
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
                         const int k = 2 * p + c;
@@ -264,25 +265,25 @@ struct Block {
                             const int sg = rank_of(R, RP, jmin, l + 1, 2 * k);
                             // every load before the stores: they cannot alias, but the
                             // compiler would otherwise wait for each store before the next load
-                            T g0[Q], g1[Q];
+                            T g0[NP], g1[NP];
 #pragma unroll
-                            for (int h = 0; h < Q; ++h) {
-                                g0[h] = Vx.ld(h, sg);
-                                g1[h] = Vx.ld(h, sg + 1);
+                            for (int h = 0; h < NP; ++h) {
+                                g0[h] = Vx.ld(PM::h(h), sg);
+                                g1[h] = Vx.ld(PM::h(h), sg + 1);
                             }
 #pragma unroll
-                            for (int h = 0; h < Q; ++h) {
+                            for (int h = 0; h < NP; ++h) {
                                 cv[c][h] = (T)0.5 * (g0[h] + g1[h]);
-                                Vx.st(h, sk, cv[c][h]);
+                                Vx.st(PM::h(h), sk, cv[c][h]);
                             }
                         } else {
 #pragma unroll
-                            for (int h = 0; h < Q; ++h) cv[c][h] = Vx.ld(h, sk);
+                            for (int h = 0; h < NP; ++h) cv[c][h] = Vx.ld(PM::h(h), sk);
                         }
                     }
                     const int so = rank_of(R, RP, jmin, lp, p);
 #pragma unroll
-                    for (int h = 0; h < Q; ++h) Vx.st(h, so, (T)0.5 * (cv[0][h] + cv[1][h]));
+                    for (int h = 0; h < NP; ++h) Vx.st(PM::h(h), so, (T)0.5 * (cv[0][h] + cv[1][h]));
                 }
             }
             __syncthreads();
@@ -297,14 +298,14 @@ struct Block {
                     const int p = (w << 6) + lane;
                     const int sc = rank_of(R, RP, jmin, l + 1, 2 * p);
                     const int sp_ = rank_lane(R, RP, jmin, l, w);
-                    T g0[Q], g1[Q];
+                    T g0[NP], g1[NP];
 #pragma unroll
-                    for (int h = 0; h < Q; ++h) {
-                        g0[h] = Vx.ld(h, sc);
-                        g1[h] = Vx.ld(h, sc + 1);
+                    for (int h = 0; h < NP; ++h) {
+                        g0[h] = Vx.ld(PM::h(h), sc);
+                        g1[h] = Vx.ld(PM::h(h), sc + 1);
                     }
 #pragma unroll
-                    for (int h = 0; h < Q; ++h) Vx.st(h, sp_, (T)0.5 * (g0[h] + g1[h]));
+                    for (int h = 0; h < NP; ++h) Vx.st(PM::h(h), sp_, (T)0.5 * (g0[h] + g1[h]));
                 }
             }
             if (n) {
@@ -374,7 +375,8 @@ struct Block {
     }
 
     // Projection through the slot table (same arithmetic as project_up, one level per pass).
-    template <class V>
+    // PM / NP: the populations projected (all of them by default).
+    template <class PM = AllPops<S>, int NP = Q, class V>
     DEV bool project_table(const V& Vx) {
         const int nlev = J - jmin + 1;
         const int myoff = lane <= nlev ? (int)toff[lane] : 0;  // every wave keeps the offsets
@@ -387,14 +389,14 @@ struct Block {
             for (int e = a + tid; e < b; e += NT) {
                 const uint32_t en = tab[e];
                 const int so = (int)(en >> 16), sc = (int)(en & 0xFFFFu);
-                T g0[Q], g1[Q];
+                T g0[NP], g1[NP];
 #pragma unroll
-                for (int h = 0; h < Q; ++h) {
-                    g0[h] = Vx.ld(h, sc);
-                    g1[h] = Vx.ld(h, sc + 1);
+                for (int h = 0; h < NP; ++h) {
+                    g0[h] = Vx.ld(PM::h(h), sc);
+                    g1[h] = Vx.ld(PM::h(h), sc + 1);
                 }
 #pragma unroll
-                for (int h = 0; h < Q; ++h) Vx.st(h, so, (T)0.5 * (g0[h] + g1[h]));
+                for (int h = 0; h < NP; ++h) Vx.st(PM::h(h), so, (T)0.5 * (g0[h] + g1[h]));
             }
             __syncthreads();
         }
@@ -1068,8 +1070,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                     // the list and the projection touch different arrays: the projection's
                     // barriers (or one here, when it has none) order both before the pairs
                     B.write_list(B.ldsL, false);
-                    const bool synced = tvalid ? B.project_table(VN)
-                                               : B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
+                    // the stream reads only the moving populations above the leaves, and the
+                    // next step projects every population again from the leaves
+                    const bool synced =
+                        tvalid ? B.template project_table<MovingPops<S>, B_t::NM>(VN)
+                               : B.template project_up<MovingPops<S>, B_t::NM>(VN, B.nsplit, B.keep, B.rpn, B.nswl);
                     if (!synced) __syncthreads();
                     if constexpr (LRN) {
                         T* PH = reinterpret_cast<T*>(d.pairs);
@@ -1098,7 +1103,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                 if (scheme) {
                     B.scan_edges();
                     B.write_list(d.list);
-                    B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
+                    B.template project_up<MovingPops<S>, B_t::NM>(VN, B.nsplit, B.keep, B.rpn, B.nswl);
                     T* P = reinterpret_cast<T*>(d.pairs);
                     B.pairs(VN, d.list, P, n);
                     B.combine(VN, d.list, P, n);
