@@ -105,20 +105,26 @@ def plain_step_rate(mrlbm, cases, nsteps):
     return (u1 - u0) / dt, dt
 
 
-def cpu_baseline(sample_steps):
-    """The FP64 oracle, as it stands, on one run of the workload (s = 1.9, eps = 1e-4)."""
+def cpu_baseline(sample_runs):
+    """The FP64 oracle, as it stands, on whole runs of the workload (s = 1.9, eps = 1e-4,
+    seeds 0 .. sample_runs-1, 3277 steps each): about 7 s of single-core work per run."""
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     from oracle.adaptive import AdaptiveMRLBM
     from oracle.lattice import scheme_from_params
-    p, mc = W.burgers(0, jmax=14, eps=1e-4, s=1.9)
-    a = AdaptiveMRLBM(scheme_from_params(p), p["jmin"], p["jmax"], p["gamma"], p["eps"], p["mu_bar"],
-                      p["bc"], mc)
-    t0 = time.perf_counter()
-    a.step(sample_steps)
-    dt = time.perf_counter() - t0
-    return {"value": a.leaf_updates / dt, "unit": "leaf-cell updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one D1Q3 Burgers run (J=14, s=1.9, eps=1e-4, seed 0), first {sample_steps} steps, "
-                      f"{a.leaf_updates} leaf-cell updates in {dt:.2f} s, single-threaded numpy",
+    upd, dt, steps = 0, 0.0, 0
+    for seed in range(sample_runs):
+        p, mc = W.burgers(seed, jmax=14, eps=1e-4, s=1.9)
+        a = AdaptiveMRLBM(scheme_from_params(p), p["jmin"], p["jmax"], p["gamma"], p["eps"], p["mu_bar"],
+                          p["bc"], mc)
+        t0 = time.perf_counter()
+        a.step(p["steps"])
+        dt += time.perf_counter() - t0
+        upd += a.leaf_updates
+        steps = p["steps"]
+    return {"value": upd / dt, "unit": "leaf-cell updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample_runs} whole D1Q3 Burgers runs of the workload (J=14, s=1.9, eps=1e-4, "
+                      f"seeds 0..{sample_runs - 1}, {steps} steps each), {upd} leaf-cell updates in "
+                      f"{dt:.2f} s, single-threaded numpy",
             "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
 
 
@@ -375,7 +381,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: tuner)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=2500)
+    ap.add_argument("--cpu-sample-runs", type=int, default=2)
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-step and delta checks")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-refinement form")
     ap.add_argument("--learned-steps", type=int, default=2400)
@@ -547,7 +553,7 @@ def main():
         print("[bench] learned-refinement form", file=sys.stderr, flush=True)
         result["learned_form"] = learned_form(mrlbm, 8, 64, args.learned_steps)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(args.cpu_sample_steps)
+        result["cpu_baseline"] = cpu_baseline(args.cpu_sample_runs)
     print(json.dumps(result))
     return 0
 
