@@ -451,3 +451,34 @@ def test_bench_workload_whole_run_sampled():
             assert b.stats(i)["leaf_updates"] == ora.leaf_updates, i
     finally:
         b.close()
+
+
+def test_table2_column_I_configuration():
+    """The configuration of the paper's Table 2, column I (D1Q2 advection of exp(-20 x^2) on
+    [-3, 3], clamp boundaries, J = 9, eps = 1e-4, mu_bar = 30) through the C ABI: leaf set
+    bit-exact with the oracle at the final step, and the ratio E / delta equal to the
+    oracle's at every relaxation rate of the table."""
+    import math
+    W9, XMIN, XMAX = 9, -3.0, 3.0
+    width = 1.0 / math.sqrt(20.0)
+    e = W.edges(W9, XMIN, XMAX)
+    u0 = W.avg_gauss_periodic(e, 1.0, 0.0, width, period=XMAX - XMIN, images=(0,))
+    n_steps = W.n_steps(0.4, 1.0, W9, XMIN, XMAX)
+    t = n_steps * (XMAX - XMIN) / 2 ** W9
+    exact = W.avg_gauss_periodic(e, 1.0, 0.75 * t, width, period=XMAX - XMIN, images=(0,))
+    for s in (0.75, 1.0, 1.25, 1.5, 1.75):
+        p = W.base_params(scheme=W.D1Q2, physics=W.ADVECTION, lam=1.0, s=[s], phys=[0.75, 1.0, 1.4, 0.9],
+                          jmin=2, jmax=W9, eps=1e-4, mu_bar=30, bc=W.CLAMP, x_min=XMIN, x_max=XMAX)
+        announce("table 2 column I", "s", s)
+        run = mrlbm.MRLBM(p, u0[None, :])
+        run.step(n_steps)
+        ora = make_oracle(p, u0[None, :]).step(n_steps)
+        lv, ix = run.leaves()
+        olv, oix = ora.leaf_list()
+        assert np.array_equal(lv, olv) and np.array_equal(ix, oix)
+        ref = UniformLBM(scheme_from_params(p), W9, W.CLAMP, u0[None, :]).step(n_steps)
+        E = metrics.delta(exact[None, :], ref.conserved(), XMIN, XMAX)[0]
+        d_gpu = metrics.delta(ref.conserved(), run.moments(mrlbm.FINEST), XMIN, XMAX)[0]
+        d_ora = metrics.delta(ref.conserved(), ora.finest_conserved(), XMIN, XMAX)[0]
+        assert abs(E / d_gpu - E / d_ora) <= 1e-9 * (E / d_ora), (s, E / d_gpu, E / d_ora)
+        run.close()
