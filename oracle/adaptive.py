@@ -20,7 +20,9 @@ complete leaves) is, in the paper's order:
   5. grading G: smallest graded tree (Sec. 3.3, Definition Graded tree),
   6. data transfer: coarsened cells keep their projections, added cells are predicted
      from their parents, coarse to fine (Sec. 4.1.1),
-  7. leaves collision on S(Lambda^{n+1}) (Sec. 4.5, eq. LeavesCollision),
+  7. leaves collision on S(Lambda^{n+1}) (Sec. 4.5, eq. LeavesCollision), or with
+     collision="reconstructed" the reconstructed collision (Sec. 4.3.1,
+     eq. reconstructedCollision),
   8. projection of the collided values up the new tree, reconstruction f-double-hat to
      the finest level by level-by-level prediction (Sec. 3.3), and the compact
      reconstructed stream (Sec. 4.3.2, eq. AdaptiveStreamPhase). Leaves already at the
@@ -45,9 +47,13 @@ class AdaptiveMRLBM:
     saying which kept pairs get both children refined. ``None`` uses the paper's rule.
     """
 
-    def __init__(self, scheme, jmin, jmax, gamma, eps, mu_bar, bc, mc0, refine_rule=None):
+    def __init__(self, scheme, jmin, jmax, gamma, eps, mu_bar, bc, mc0, refine_rule=None,
+                 collision="leaves"):
         if not (0 <= jmin <= jmax):
             raise ValueError("need 0 <= J_min <= J")
+        if collision not in ("leaves", "reconstructed"):
+            raise ValueError("collision is 'leaves' or 'reconstructed'")
+        self.collision = collision
         self.sch = scheme
         self.jmin, self.jmax = int(jmin), int(jmax)
         self.gamma, self.eps, self.mu_bar, self.bc = int(gamma), float(eps), int(mu_bar), int(bc)
@@ -196,6 +202,35 @@ class AdaptiveMRLBM:
             if k.size:
                 self.F[l][:, k] = self.sch.collide(self.F[l][:, k])
 
+    def leaf_mean_equilibria(self):
+        """Per complete leaf (l, k): the mean over its finest cells (J, k 2^(J-l) + delta),
+        delta = 0 .. 2^(J-l) - 1, of the equilibria of the reconstructed conserved moments
+        (those of the reconstructed populations, equal in exact arithmetic) (Sec. 4.3.1,
+        eq. reconstructedCollision). The leaf values are projected up the tree first; the sum
+        runs over delta in increasing order and is scaled by 2^-(J-l) (exact). Returns
+        {l: (k, eqbar)} with eqbar of shape (q - qc, #k)."""
+        J = self.jmax
+        self.project_up()
+        eqJ = self.sch.equilibria(self.reconstruct()[J])  # (q - qc, 2^J)
+        out = {}
+        for l, mask in self.leaves().items():
+            k = np.nonzero(mask)[0]
+            if k.size == 0:
+                continue
+            d = J - l
+            acc = eqJ[:, k << d].copy()
+            for delta in range(1, 2 ** d):
+                acc = acc + eqJ[:, (k << d) + delta]
+            out[l] = (k, np.ldexp(acc, -d))
+        return out
+
+    def collide_reconstructed(self):
+        """Reconstructed collision on S(Lambda^{n+1}) (Sec. 4.3.1, eq. reconstructedCollision):
+        every non-conserved moment of a leaf relaxes towards the leaf's mean equilibrium over
+        its finest cells; the conserved moments stay."""
+        for l, (k, eqbar) in self.leaf_mean_equilibria().items():
+            self.F[l][:, k] = self.sch.collide_with_equilibria(self.F[l][:, k], eqbar)
+
     def reconstruct(self):
         """f-double-hat on every level: G[J_min] = F[J_min]; G[l+1] = prediction of G[l],
         overwritten by F on R(Lambda). Returns the dict of levels."""
@@ -245,7 +280,10 @@ class AdaptiveMRLBM:
     def step(self, nsteps=1):
         for _ in range(int(nsteps)):
             self.adapt()
-            self.collide_leaves()
+            if self.collision == "reconstructed":
+                self.collide_reconstructed()
+            else:
+                self.collide_leaves()
             self.project_up()
             self.stream()
             nl = self.n_leaves()

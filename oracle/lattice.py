@@ -149,6 +149,72 @@ class Scheme:
                 out[2 * b + 1] = 0.5 * (c[b] - r)
         return out
 
+    def equilibria(self, f):
+        """Equilibria of the non-conserved moments, shape (q - qc, n), from the conserved
+        moments of populations f (q, n): the expressions ``collide`` uses (Sec. 5)."""
+        f = np.asarray(f, dtype=np.float64)
+        lam = self.lam
+        if self.scheme == D1Q2:
+            u = f[0] + f[1]
+            return np.array([self.V * u if self.physics == ADVECTION else (u * u) * 0.5])
+        if self.scheme == D1Q3:
+            lam2 = lam * lam
+            m0 = (f[0] + f[1]) + f[2]
+            if self.physics == BURGERS:
+                return np.array([(m0 * m0) * 0.5, (self.alpha * lam2) * m0])
+            m1 = lam * (f[1] - f[2])
+            g2 = 0.5 * self.g
+            return np.array([(m1 * m1) / m0 + g2 * (m0 * m0)])
+        nb = self.q // 2
+        return np.array(self._eq_vectorial([f[2 * b] + f[2 * b + 1] for b in range(nb)]))
+
+    def collide_with_equilibria(self, f, eq):
+        """``collide`` with the non-conserved moments relaxed towards the given equilibria eq
+        (q - qc, n) instead of those of f itself; the conserved moments stay (Sec. 4.3.1,
+        eq. reconstructedCollision, where eq is the mean over a leaf's finest cells).
+        collide_with_equilibria(f, equilibria(f)) is collide(f)."""
+        f = np.asarray(f, dtype=np.float64)
+        eq = np.asarray(eq, dtype=np.float64)
+        lam = self.lam
+        out = np.empty_like(f)
+        if self.scheme == D1Q2:
+            u = f[0] + f[1]
+            m1 = lam * (f[0] - f[1])
+            s = self.s[0]
+            m1s = (1.0 - s) * m1 + s * eq[0]
+            r = m1s / lam
+            out[0] = 0.5 * (u + r)
+            out[1] = 0.5 * (u - r)
+        elif self.scheme == D1Q3:
+            lam2 = lam * lam
+            m0 = (f[0] + f[1]) + f[2]
+            m1 = lam * (f[1] - f[2])
+            m2 = lam2 * (f[1] + f[2])
+            if self.physics == BURGERS:
+                s1, s2 = self.s
+                m1s = (1.0 - s1) * m1 + s1 * eq[0]
+                m2s = (1.0 - s2) * m2 + s2 * eq[1]
+            else:
+                s2 = self.s[0]
+                m1s = m1
+                m2s = (1.0 - s2) * m2 + s2 * eq[0]
+            a = m2s / lam2
+            b = m1s / lam
+            out[0] = m0 - a
+            out[1] = 0.5 * (a + b)
+            out[2] = 0.5 * (a - b)
+        else:
+            nb = self.q // 2
+            for b in range(nb):
+                c = f[2 * b] + f[2 * b + 1]
+                s = self.s[b]
+                n = lam * (f[2 * b] - f[2 * b + 1])
+                ns = (1.0 - s) * n + s * eq[b]
+                r = ns / lam
+                out[2 * b] = 0.5 * (c + r)
+                out[2 * b + 1] = 0.5 * (c - r)
+        return out
+
     def equilibrium(self, mc):
         """Populations at equilibrium for conserved moments mc of shape (qc, n) (Sec. 2.1.1:
         the initial datum is taken at equilibrium)."""

@@ -1,0 +1,107 @@
+"""Pins of the oracle's reconstructed collision (Sec. 4.3.1, eq. reconstructedCollision):
+identities it must satisfy whatever the data, the special cases where it reduces to the
+leaves collision, the sign Jensen's inequality fixes for a convex flux, and the Sec. 4.4
+error estimate (which is stated for this collision)."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import metrics
+from oracle.adaptive import AdaptiveMRLBM
+from oracle.lattice import BURGERS, D1Q3, VALID_PAIRS, Scheme, scheme_from_params
+from oracle.reference import UniformLBM
+
+KINDS = ["advection", "burgers", "burgers_d1q2", "shallow", "euler"]
+
+
+def build(p, mc, eps=None, collision="reconstructed"):
+    sch = scheme_from_params(p)
+    e = p["eps"] if eps is None else eps
+    return AdaptiveMRLBM(sch, p["jmin"], p["jmax"], p["gamma"], e, p["mu_bar"], p["bc"], mc,
+                         collision=collision)
+
+
+def test_collide_with_own_equilibria_is_collide():
+    """Relaxing towards a cell's own equilibria is the plain collision, bit for bit, for
+    every scheme and physics pair."""
+    rng = np.random.default_rng(5)
+    n = 64
+    for scheme, physics in sorted(VALID_PAIRS):
+        if scheme == D1Q3 and physics == BURGERS:
+            sch = Scheme(scheme, physics, 1.0, [1.5, 1.2], alpha=0.9)
+        else:
+            sch = Scheme(scheme, physics, 2.0, [1.7], V=0.75, g=1.0, gamma_gas=1.4)
+        # density in [1, 1.5], momenta small, energy (third conserved moment) well above kinetic
+        mc = [1.0 + 0.5 * rng.random(n)] + [0.2 * rng.standard_normal(n) for _ in range(sch.qc - 1)]
+        if sch.qc == 3:
+            mc[2] = 2.0 + np.abs(mc[2])
+        f = sch.equilibrium(np.vstack(mc)) + 1e-3 * rng.standard_normal((sch.q, n))
+        assert np.array_equal(sch.collide(f), sch.collide_with_equilibria(f, sch.equilibria(f))), (scheme, physics)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_eps_zero_reconstructed_is_uniform_scheme(kind):
+    """eps = 0 keeps every cell at the finest level, where a leaf's only finest cell is
+    itself: the reconstructed collision is the uniform scheme, bit for bit."""
+    p, mc = W.small_case(kind, seed=2, jmax=7)
+    a = build(p, mc, eps=0.0).step(25)
+    r = UniformLBM(scheme_from_params(p), p["jmax"], p["bc"], mc).step(25)
+    assert a.n_leaves() == 2 ** p["jmax"]
+    assert np.array_equal(a.finest_populations(), r.F)
+
+
+def test_linear_equilibria_mean_is_leaf_equilibrium():
+    """Advection (equilibrium linear in u): the prediction keeps cell averages (Sec. 3.1),
+    so the mean equilibrium over a leaf's finest cells is the leaf's own equilibrium up to
+    rounding, and the reconstructed collision equals the leaves collision."""
+    p, mc = W.advection(3, jmax=9, eps=1e-3)
+    a = build(p, mc, collision="leaves").step(40)
+    a.adapt()
+    means = a.leaf_mean_equilibria()
+    coarse = 0
+    for l, (k, eqbar) in means.items():
+        own = a.sch.equilibria(a.F[l][:, k])
+        assert np.allclose(eqbar, own, rtol=0, atol=1e-14 * max(1.0, np.abs(own).max())), l
+        coarse += int(l < a.jmax) * k.size
+    assert coarse > 0  # leaves coarser than J exist, so the identity is not trivial
+
+
+def test_convex_flux_mean_equilibrium_is_not_below_leaf_equilibrium():
+    """Burgers (equilibrium u^2 / 2, convex): by Jensen's inequality the mean over a leaf's
+    finest cells of u^2 / 2 is at least (mean u)^2 / 2, and the mean of the reconstructed u
+    is the leaf's u; strictly above where the reconstruction varies inside the leaf."""
+    p, mc = W.small_case("burgers_d1q2", seed=4, jmax=9, eps=1e-3)
+    a = build(p, mc, collision="leaves").step(60)
+    a.adapt()
+    above = 0
+    for l, (k, eqbar) in a.leaf_mean_equilibria().items():
+        own = a.sch.equilibria(a.F[l][:, k])
+        assert np.all(eqbar[0] >= own[0] - 1e-15), l
+        above += int(np.sum(eqbar[0] > own[0] + 1e-15))
+    assert above > 0
+
+
+def test_reconstructed_delta_scales_with_eps():
+    """Sec. 4.4: delta <= C eps with the reconstructed collision, on Burgers (nonlinear, where
+    it differs from the leaves collision); slope near one."""
+    p, mc = W.small_case("burgers_d1q2", seed=1, jmax=9)
+    ref = UniformLBM(scheme_from_params(p), 9, p["bc"], mc).step(120)
+    ds = []
+    epss = [1e-3, 1e-4, 1e-5]
+    for eps in epss:
+        a = build(p, mc, eps=eps).step(120)
+        ds.append(metrics.delta(ref.conserved(), a.finest_conserved(), p["x_min"], p["x_max"])[0])
+    assert ds[0] > ds[1] > ds[2] > 0
+    slopes = np.diff(np.log10(ds)) / np.diff(np.log10(epss))
+    assert np.all((slopes > 0.6) & (slopes < 1.4)), slopes
+    assert max(d / e for d, e in zip(ds, epss)) < 20.0
+
+
+def test_reconstructed_differs_from_leaves_on_burgers():
+    """On a nonlinear flux the two collisions give different runs (the comparison above would
+    otherwise pin nothing new)."""
+    p, mc = W.small_case("burgers_d1q2", seed=1, jmax=8, eps=1e-3)
+    a = build(p, mc).step(40)
+    b = build(p, mc, collision="leaves").step(40)
+    assert not np.array_equal(a.finest_populations(), b.finest_populations())

@@ -1,4 +1,4 @@
-"""The oracle against the only numbers the paper prints for its method: Table 2 of Sec. 6
+"""The oracle against the only numbers the paper prints for its method: Table 2 of Sec. 5.1
 (ratio E^{0,N} / delta^{0,N} of the reference scheme's error against the exact solution to
 the adaptive method's perturbation error, D1Q2, J = 9, eps = 1e-4).
 
