@@ -62,6 +62,18 @@ enum mrlbm_where { MRLBM_LEAVES = 0, MRLBM_FINEST = 1 };
 /* Largest finest level supported on one GPU workgroup's LDS. */
 #define MRLBM_MAX_J 16
 
+/* Collision of the adaptive step (mrlbm_params.flags). Default (0): the leaves collision
+ * (Sec. 4.5, eq. LeavesCollision), every complete leaf collides on its own value.
+ * MRLBM_FLAG_RECONSTRUCTED_COLLISION: the reconstructed collision (Sec. 4.3.1,
+ * eq. reconstructedCollision): the leaf values of the new tree are projected up, every
+ * complete leaf (l, k) reconstructs its 2^(J-l) finest cells, and its non-conserved moments
+ * relax towards the mean over them of the equilibria of the reconstructed conserved moments
+ * (summed in cell order, scaled by 2^-(J-l)); its conserved moments stay. It costs
+ * O(2^(J-l) (J-l)) per leaf and is the collision the paper's error estimate covers. Not
+ * available together with the refinement predictor (mrlbm_set_predictor returns
+ * MRLBM_EINVAL). */
+#define MRLBM_FLAG_RECONSTRUCTED_COLLISION 1u
+
 typedef struct {
     int32_t abi_version; /* must be MRLBM_ABI_VERSION                                    */
     int32_t scheme;      /* enum mrlbm_scheme                                              */
@@ -80,7 +92,7 @@ typedef struct {
     int32_t gamma;       /* prediction half-width 1..3 (Sec. 3.1)                          */
     int32_t mu_bar;      /* regularity guess of enlargement rule (b), 0..30 (Sec. 4.2)      */
     double eps;          /* threshold eps >= 0, finite; eps_j = 2^(j-J) eps (Sec. 3.4)       */
-    uint32_t flags;      /* reserved, must be 0                                             */
+    uint32_t flags;      /* 0 or MRLBM_FLAG_RECONSTRUCTED_COLLISION                         */
     int32_t reserved;
 } mrlbm_params;
 

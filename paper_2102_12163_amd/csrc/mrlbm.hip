@@ -31,7 +31,8 @@ namespace mrl {
     extern template __global__ void k_query<T, S, 1>(const Desc*, State*, int, int, double*);    \
     extern template __global__ void k_query<T, S, 2>(const Desc*, State*, int, int, double*);    \
     extern template __global__ void k_query<T, S, 3>(const Desc*, State*, int, int, double*);          \
-    extern template __global__ void k_steps<T, S, 1, true>(const Desc*, State*, const int*, int, int, int, int);
+    extern template __global__ void k_steps<T, S, 1, true>(const Desc*, State*, const int*, int, int, int, int); \
+    extern template __global__ void k_steps<T, S, 1, false, true>(const Desc*, State*, const int*, int, int, int, int);
 MRL_EXTERN(double, 0)
 MRL_EXTERN(double, 1)
 MRL_EXTERN(double, 2)
@@ -44,7 +45,8 @@ MRL_EXTERN(double, 3)
     extern template __global__ void k_steps<T, S, 3>(const Desc*, State*, const int*, int, int, int, int);   \
     extern template __global__ void k_query<T, S, 1>(const Desc*, State*, int, int, double*);    \
     extern template __global__ void k_query<T, S, 2>(const Desc*, State*, int, int, double*);    \
-    extern template __global__ void k_query<T, S, 3>(const Desc*, State*, int, int, double*);
+    extern template __global__ void k_query<T, S, 3>(const Desc*, State*, int, int, double*);         \
+    extern template __global__ void k_steps<T, S, 1, false, true>(const Desc*, State*, const int*, int, int, int, int);
 MRL_EXTERN32(float, 0)
 MRL_EXTERN32(float, 1)
 MRL_EXTERN32(float, 2)
@@ -91,6 +93,7 @@ struct Engine {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // refinement predictor
     bool lrn = false;             // launch the predictor-capable kernels
+    bool any_recon = false;       // some run uses the reconstructed collision
     uint16_t* d_mlp = nullptr;
     float* d_samples = nullptr;
     unsigned int* d_nsamples = nullptr;
@@ -151,7 +154,10 @@ int validate(const mrlbm_params* p, std::string* why) {
         return bad("periodic coarsest level needs 2^j_min >= 2 gamma + 1");
     if (p->mu_bar < 0 || p->mu_bar > 30) return bad("mu_bar must be in 0..30");
     if (!(p->eps >= 0.0) || !isfinite(p->eps)) return bad("eps must be finite and >= 0");
-    if (p->flags != 0) return bad("flags must be 0");
+    if ((p->flags & ~(uint32_t)MRLBM_FLAG_RECONSTRUCTED_COLLISION) != 0)
+        return bad("flags: only MRLBM_FLAG_RECONSTRUCTED_COLLISION is defined");
+    if ((p->flags & MRLBM_FLAG_RECONSTRUCTED_COLLISION) && p->gamma != 1)
+        return bad("the reconstructed collision runs with gamma = 1");
     if (p->physics == MRLBM_SHALLOW_WATER && !(p->phys[1] > 0.0)) return bad("gravity must be > 0");
     if (p->physics == MRLBM_EULER && !(p->phys[2] > 1.0)) return bad("gamma_gas must be > 1");
     if (p->scheme == MRLBM_D1Q3 && p->physics == MRLBM_BURGERS && !(p->phys[3] > 0.0))
@@ -256,6 +262,24 @@ StepK lrn_kernel(int scheme) {
         case 1: return k_steps<double, 1, 1, true>;
         case 2: return k_steps<double, 2, 1, true>;
         default: return k_steps<double, 3, 1, true>;
+    }
+}
+
+// Step kernels that can run the reconstructed collision (gamma = 1).
+StepK rc_kernel(int prec, int scheme) {
+    if (prec == MRLBM_FP64) {
+        switch (scheme) {
+            case 0: return k_steps<double, 0, 1, false, true>;
+            case 1: return k_steps<double, 1, 1, false, true>;
+            case 2: return k_steps<double, 2, 1, false, true>;
+            default: return k_steps<double, 3, 1, false, true>;
+        }
+    }
+    switch (scheme) {
+        case 0: return k_steps<float, 0, 1, false, true>;
+        case 1: return k_steps<float, 1, 1, false, true>;
+        case 2: return k_steps<float, 2, 1, false, true>;
+        default: return k_steps<float, 3, 1, false, true>;
     }
 }
 
@@ -394,6 +418,8 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
         d.q = si.q;
         d.qc = si.qc;
         d.nm = si.nm;
+        d.recon = (p.flags & MRLBM_FLAG_RECONSTRUCTED_COLLISION) ? 1 : 0;
+        e->any_recon = e->any_recon || d.recon;
         d.eps = p.eps;
         pred_coeffs(p.gamma, d.c);
         d.cf = make_coef(&p, si);
@@ -465,6 +491,9 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
     e->lds_budget = (size_t)std::max(0, maxlds - 1024);
     choose_capacity(e);
     (void)hipFuncSetAttribute((const void*)sk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)e->lds);
+    if (e->any_recon)
+        (void)hipFuncSetAttribute((const void*)rc_kernel(e->prec, e->scheme), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)e->lds);
     (void)hipFuncSetAttribute((const void*)qk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)e->lds_query);
     e->nt = default_block(e->maxJ);
     *out = e;
@@ -483,6 +512,7 @@ static int prepare_graph(Engine* e, int nsteps) {
     InitK ik;
     kernels_for(e->prec, e->scheme, e->gamma, &sk, &qk, &ik);
     if (e->lrn) sk = lrn_kernel(e->scheme);
+    else if (e->any_recon) sk = rc_kernel(e->prec, e->scheme);
     const int nt = e->nt_user ? e->nt_user : e->nt;
     if (e->gexec && e->gsteps == nsteps && e->gnt == nt && e->gcap == e->cap) return MRLBM_OK;
     if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
@@ -524,6 +554,7 @@ static int launch_once(Engine* e, int nsteps, int mode, bool use_graph) {
     InitK ik;
     kernels_for(e->prec, e->scheme, e->gamma, &sk, &qk, &ik);
     if (e->lrn) sk = lrn_kernel(e->scheme);
+    else if (e->any_recon) sk = rc_kernel(e->prec, e->scheme);
     const int nt = e->nt_user ? e->nt_user : e->nt;
     hipError_t st;
     if (use_graph && mode == (MODE_ADAPT | MODE_SCHEME)) {
@@ -1053,6 +1084,10 @@ static int set_predictor(Engine* e, const uint16_t* params, int32_t mode, double
     }
     if (mode != MRLBM_PRED_OFF && (e->prec != MRLBM_FP64 || e->gamma != 1)) {
         e->err = "the refinement predictor runs with FP64 storage and gamma = 1";
+        return MRLBM_EINVAL;
+    }
+    if (mode != MRLBM_PRED_OFF && e->any_recon) {
+        e->err = "the refinement predictor runs with the leaves collision only";
         return MRLBM_EINVAL;
     }
     // steps still in flight on the handle's stream read the weights and samples replaced here

@@ -38,6 +38,7 @@ struct Coef {
 
 struct Desc {
     int jmin, jmax, gamma, mu_bar, bc, q, qc, nm;
+    int recon;  // 1: reconstructed collision (Sec. 4.3.1), 0: leaves collision (Sec. 4.5)
     double eps;
     double c[3];
     Coef cf;
@@ -326,6 +327,92 @@ DEV void collide(const Coef& c, T* f) {
             const T r = div_by(ns, lam, ilam, p2);
             f[2 * b] = half * (cc[b] + r);
             f[2 * b + 1] = half * (cc[b] - r);
+        }
+    }
+}
+
+// Number of non-conserved moments with an equilibrium (at most, for D1Q3: 2 for Burgers,
+// 1 for shallow water).
+template <int S> struct NEq { static constexpr int N = S == 0 ? 1 : (S == 3 ? 3 : 2); };
+
+// Equilibria of the non-conserved moments from the conserved moments of f, with the
+// expressions of collide (Sec. 5).
+template <typename T, int S>
+DEV void eq_moments(const Coef& c, const T* f, T* eq) {
+    const T half = (T)0.5;
+    if constexpr (S == 0) {
+        const T u = f[0] + f[1];
+        eq[0] = c.physics == ADVECTION ? (T)c.V * u : (u * u) * half;
+    } else if constexpr (S == 1) {
+        const T m0 = (f[0] + f[1]) + f[2];
+        if (c.physics == BURGERS) {
+            eq[0] = (m0 * m0) * half;
+            eq[1] = (T)c.alam2 * m0;
+        } else {
+            const T m1 = (T)c.lam * (f[1] - f[2]);
+            eq[0] = (m1 * m1) / m0 + (T)c.g2 * (m0 * m0);
+            eq[1] = (T)0;
+        }
+    } else {
+        constexpr int NB = Sch<S>::Q / 2;
+        T cc[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) cc[b] = f[2 * b] + f[2 * b + 1];
+        if constexpr (S == 2) {
+            eq[0] = cc[1];
+            eq[1] = (cc[1] * cc[1]) / cc[0] + (T)c.g2 * (cc[0] * cc[0]);
+        } else {
+            eq[0] = cc[1];
+            eq[1] = (T)c.k3 * ((cc[1] * cc[1]) / cc[0]) + (T)c.gm1 * cc[2];
+            eq[2] = (T)c.gam * ((cc[2] * cc[1]) / cc[0]) + (T)c.k5 * (((cc[1] * cc[1]) * cc[1]) / (cc[0] * cc[0]));
+        }
+    }
+}
+
+// collide with the non-conserved moments relaxed towards the given equilibria eq instead of
+// f's own (Sec. 4.3.1, eq. reconstructedCollision, where eq is a leaf's mean over its finest
+// cells); the conserved moments stay. relax_to(c, f, eq_moments(c, f)) is collide(c, f).
+template <typename T, int S>
+DEV void relax_to(const Coef& c, T* f, const T* eq) {
+    const T lam = (T)c.lam;
+    const T ilam = (T)c.ilam;
+    const bool p2 = c.lam_pow2 != 0;
+    const T half = (T)0.5;
+    if constexpr (S == 0) {
+        const T u = f[0] + f[1];
+        const T m1 = lam * (f[0] - f[1]);
+        const T m1s = (T)c.oms[0] * m1 + (T)c.s[0] * eq[0];
+        const T r = div_by(m1s, lam, ilam, p2);
+        f[0] = half * (u + r);
+        f[1] = half * (u - r);
+    } else if constexpr (S == 1) {
+        const T lam2 = (T)c.lam2;
+        const T m0 = (f[0] + f[1]) + f[2];
+        const T m1 = lam * (f[1] - f[2]);
+        const T m2 = lam2 * (f[1] + f[2]);
+        T m1s, m2s;
+        if (c.physics == BURGERS) {
+            m1s = (T)c.oms[0] * m1 + (T)c.s[0] * eq[0];
+            m2s = (T)c.oms[1] * m2 + (T)c.s[1] * eq[1];
+        } else {
+            m1s = m1;
+            m2s = (T)c.oms[0] * m2 + (T)c.s[0] * eq[0];
+        }
+        const T a = div_by(m2s, lam2, (T)c.ilam2, p2);
+        const T b = div_by(m1s, lam, ilam, p2);
+        f[0] = m0 - a;
+        f[1] = half * (a + b);
+        f[2] = half * (a - b);
+    } else {
+        constexpr int NB = Sch<S>::Q / 2;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const T cb = f[2 * b] + f[2 * b + 1];
+            const T n = lam * (f[2 * b] - f[2 * b + 1]);
+            const T ns = (T)c.oms[b] * n + (T)c.s[b] * eq[b];
+            const T r = div_by(ns, lam, ilam, p2);
+            f[2 * b] = half * (cb + r);
+            f[2 * b + 1] = half * (cb - r);
         }
     }
 }

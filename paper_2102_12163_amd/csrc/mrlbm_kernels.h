@@ -718,7 +718,7 @@ struct Block {
     // reconstruction from Lambda^n, i.e. level-by-level prediction (Sec. 4.1.1). With collide
     // set the leaf is collided right away (Sec. 4.5) and its left edge is marked in E.
     template <class VO_, class VN_>
-    DEV void transfer(const VO_& VO, const VN_& VN, bool collide_mark, int* nanflag) {
+    DEV void transfer(const VO_& VO, const VN_& VN, bool collide_leaf, bool mark, int* nanflag) {
         int first;
         const int ntask = list_tasks(lwl, &first);
         for (int task = wave; task < ntask; task += nwaves) {
@@ -738,12 +738,14 @@ struct Block {
                         T g[Q];
                         chain<T, G, Q, AllPops<S>>(VO, ro, rpo, jmin, l, bc, cc, k, k, f, g, l);
                     }
-                    if (collide_mark) {
-                        collide<T, S>(d.cf, f);
-                        bool bad = false;
+                    if (mark) {
+                        if (collide_leaf) {
+                            collide<T, S>(d.cf, f);
+                            bool bad = false;
 #pragma unroll
-                        for (int h = 0; h < Q; ++h) bad = bad || (f[h] != f[h]);
-                        if (bad) *nanflag = 1;
+                            for (int h = 0; h < Q; ++h) bad = bad || (f[h] != f[h]);
+                            if (bad) *nanflag = 1;
+                        }
                         const int e = k << (J - l);
                         atomicOr((unsigned long long*)&E[e >> 6], 1ull << (e & 63));
                     }
@@ -799,6 +801,57 @@ struct Block {
             }
         }
         if (sync) __syncthreads();
+    }
+
+    // ----------------------------------------------------------- B1': reconstructed collision
+    // Reconstructed collision (Sec. 4.3.1, eq. reconstructedCollision), one thread per leaf of
+    // the spatial list: the values of R(Lambda^{n+1}) hold f^n projected up the tree; the
+    // leaf's finest cells are reconstructed one by one, the equilibria of their conserved
+    // moments summed in cell order and scaled by 2^-(J-l) (exact), and the leaf relaxes
+    // towards that mean. The collided values wait in scratch (Q * n values) until every leaf
+    // has read what it needs, then replace the leaf values.
+    template <class V, class LP, class SP>
+    DEV void recon_collide(const V& Vx, const LP* list, SP* scr, int n, int* nanflag) {
+        constexpr int NE = NEq<S>::N;
+        for (int i = tid; i < n; i += NT) {
+            const uint32_t key = list[i];
+            const int l = key >> 27, k = key & ((1u << 27) - 1u);
+            const int dl = J - l;
+            T acc[NE];
+            for (int dd = 0; dd < (1 << dl); ++dd) {
+                const int m = (k << dl) + dd;
+                T a[Q], b[Q];
+                chain<T, G, Q, AllPops<S>>(Vx, keep, rpn, jmin, J, bc, cc, m, m, a, b, l);
+                T e[NE];
+                eq_moments<T, S>(d.cf, a, e);
+#pragma unroll
+                for (int x = 0; x < NE; ++x) acc[x] = dd == 0 ? e[x] : acc[x] + e[x];
+            }
+            const T sc = (T)ldexp(1.0, -dl);
+#pragma unroll
+            for (int x = 0; x < NE; ++x) acc[x] = acc[x] * sc;
+            const int s = rank_of(keep, rpn, jmin, l, k);
+            T f[Q];
+#pragma unroll
+            for (int h = 0; h < Q; ++h) f[h] = Vx.ld(h, s);
+            relax_to<T, S>(d.cf, f, acc);
+            bool bad = false;
+#pragma unroll
+            for (int h = 0; h < Q; ++h) {
+                bad = bad || (f[h] != f[h]);
+                scr[h * n + i] = f[h];
+            }
+            if (bad) *nanflag = 1;
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += NT) {
+            const uint32_t key = list[i];
+            const int l = key >> 27, k = key & ((1u << 27) - 1u);
+            const int s = rank_of(keep, rpn, jmin, l, k);
+#pragma unroll
+            for (int h = 0; h < Q; ++h) Vx.st(h, s, (T)scr[h * n + i]);
+        }
+        __syncthreads();
     }
 
     // ----------------------------------------------------------- B3: stream
@@ -946,9 +999,10 @@ DEV T* hbm_vals(const Desc& d, int which) { return reinterpret_cast<T*>(which ? 
 
 // nsteps time steps (or adaptations only) of run sched[blockIdx.x]. cap / capS: on-chip capacity in
 // R(Lambda) cells and in leaves (0 = always use the HBM arrays). LRN: the variant that can run
-// the refinement predictor (d.pmode != 0).
-template <typename T, int S, int G, bool LRN = false>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && !LRN && S <= 1) ? 4 : 1))) void k_steps(const Desc* __restrict__ descs, State* __restrict__ states,
+// the refinement predictor (d.pmode != 0). RC: the variant that can run the reconstructed
+// collision (runs with d.recon set; the others in the same launch use the leaves collision).
+template <typename T, int S, int G, bool LRN = false, bool RC = false>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && !LRN && !RC && S <= 1) ? 4 : 1))) void k_steps(const Desc* __restrict__ descs, State* __restrict__ states,
                                                const int* __restrict__ sched, int nsteps, int mode, int cap, int capS) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t s_red[24];
@@ -999,6 +1053,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
             tvalid = B.build_table(B.split, B.ro, B.rpo, B.swl, (typename B_t::LU*)(lds + lay.VB),
                                    (int)(((unsigned)Q * (unsigned)cap * sizeof(T)) / 4u));
     const bool scheme = (mode & MODE_SCHEME) != 0;
+    // reconstructed collision: only the RC instances carry its code (it would raise the
+    // register count of every other kernel)
+    const bool recon = RC && !LRN && d.recon != 0;
     const bool judge = LRN && scheme && (d.pmode == 2 || (d.pmode == 1 && d.mlp != nullptr));
     long long upd = 0, misses = 0, redos = 0;
     int last = -1;
@@ -1053,7 +1110,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
             if (fast) {
                 VP<T, LT> VO{where == IN_LDS_A ? B.ldsA : B.ldsB, cap};
                 VP<T, LT> VN{nwhere == IN_LDS_A ? B.ldsA : B.ldsB, cap};
-                B.transfer(VO, VN, scheme, &s_nan);
+                B.transfer(VO, VN, scheme && !recon, scheme, &s_nan);
                 if constexpr (!LRN) {
                     // the old array, dead until the next transfer, holds the interface pairs,
                     // then this step's leaf list, then the new tree's table (read by the next
@@ -1070,6 +1127,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                     // the list and the projection touch different arrays: the projection's
                     // barriers (or one here, when it has none) order both before the pairs
                     B.write_list(B.ldsL, false);
+                    if constexpr (RC && !LRN) {
+                        if (recon) {
+                            // f^n up the new tree, then the leaves collide on its reconstruction
+                            // (the pairs region is free until the stream)
+                            const bool sy = tvalid ? B.project_table(VN)
+                                                   : B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
+                            if (!sy) __syncthreads();
+                            B.recon_collide(VN, B.ldsL, where == IN_LDS_A ? B.ldsA : B.ldsB, n, &s_nan);
+                        }
+                    }
                     // the stream reads only the moving populations above the leaves, and the
                     // next step projects every population again from the leaves
                     const bool synced =
@@ -1099,12 +1166,18 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                 const int sn = nwhere <= IN_LDS_B ? cap : Cg;
                 VP<T, T> VO{po, so};
                 VP<T, T> VN{pn, sn};
-                B.transfer(VO, VN, scheme, &s_nan);
+                B.transfer(VO, VN, scheme && !recon, scheme, &s_nan);
                 if (scheme) {
                     B.scan_edges();
                     B.write_list(d.list);
-                    B.template project_up<MovingPops<S>, B_t::NM>(VN, B.nsplit, B.keep, B.rpn, B.nswl);
                     T* P = reinterpret_cast<T*>(d.pairs);
+                    if constexpr (RC && !LRN) {
+                        if (recon) {
+                            if (!B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl)) __syncthreads();
+                            B.recon_collide(VN, d.list, P, n, &s_nan);
+                        }
+                    }
+                    B.template project_up<MovingPops<S>, B_t::NM>(VN, B.nsplit, B.keep, B.rpn, B.nswl);
                     B.pairs(VN, d.list, P, n);
                     B.combine(VN, d.list, P, n);
                 }

@@ -19,6 +19,7 @@ D1Q2, D1Q3, D1Q2x2, D1Q2x3 = 0, 1, 2, 3
 ADVECTION, BURGERS, SHALLOW_WATER, EULER = 0, 1, 2, 3
 PERIODIC, CLAMP = 0, 1
 FP64, FP32_STORAGE = 0, 1
+FLAG_RECONSTRUCTED_COLLISION = 1  # mrlbm_params.flags: reconstructed collision (Sec. 4.3.1)
 LEAVES, FINEST = 0, 1
 MAX_J = 16
 PRED_OFF, PRED_LEARNED, PRED_RECORD = 0, 1, 2
@@ -123,7 +124,8 @@ def _dptr(a):
 
 def make_params(p):
     """Params struct from a dict with keys scheme, physics, bc, precision, lam, s, phys,
-    x_min, x_max, jmin, jmax, gamma, mu_bar, eps (the workload dictionaries)."""
+    x_min, x_max, jmin, jmax, gamma, mu_bar, eps (the workload dictionaries), and optionally
+    collision = "leaves" (default) or "reconstructed"."""
     s = list(np.atleast_1d(np.asarray(p.get("s", [1.0]), dtype=np.float64)))
     phys = list(p.get("phys", [0.0, 1.0, 1.4, 0.9])) + [0.0] * 4
     P = Params()
@@ -145,7 +147,7 @@ def make_params(p):
     P.gamma = p.get("gamma", 1)
     P.mu_bar = p.get("mu_bar", 0)
     P.eps = p["eps"]
-    P.flags = p.get("flags", 0)
+    P.flags = p.get("flags", 0) | (FLAG_RECONSTRUCTED_COLLISION if p.get("collision", "leaves") == "reconstructed" else 0)
     return P
 
 

@@ -17,7 +17,8 @@ FLIP_MARGIN = 1e-12
 
 def make_oracle(p, mc, eps=None):
     e = p["eps"] if eps is None else eps
-    return AdaptiveMRLBM(scheme_from_params(p), p["jmin"], p["jmax"], p["gamma"], e, p["mu_bar"], p["bc"], mc)
+    return AdaptiveMRLBM(scheme_from_params(p), p["jmin"], p["jmax"], p["gamma"], e, p["mu_bar"], p["bc"], mc,
+                         collision=p.get("collision", "leaves"))
 
 
 def threshold_margin(ora):

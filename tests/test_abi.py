@@ -48,11 +48,22 @@ def good():
     ("abi_version", 99), ("scheme", 7), ("physics", 9), ("bc", 5), ("precision", 3), ("lam", 0.0),
     ("lam", -1.0), ("lam", float("inf")), ("s", [0.0]), ("s", [2.5]), ("s", [1.0, 1.0, 1.0]),
     ("x_max", -2.0), ("jmin", 0), ("jmin", 9), ("gamma", 0), ("gamma", 4), ("mu_bar", -1), ("eps", -1e-3),
-    ("eps", float("nan")), ("flags", 1),
+    ("eps", float("nan")), ("flags", 2), ("flags", 0x80000000),
 ])
 def test_validation_rejects(field, value):
     p = good()
     p[field] = value
+    assert mrlbm.validate(p) == mrlbm.EINVAL
+
+
+def test_validation_reconstructed_collision_flag():
+    """Bit 0 of flags selects the reconstructed collision, which runs with gamma = 1."""
+    p = good()
+    p["collision"] = "reconstructed"
+    assert mrlbm.make_params(p).flags == mrlbm.FLAG_RECONSTRUCTED_COLLISION
+    assert mrlbm.validate(p) == mrlbm.OK
+    p["gamma"] = 2
+    p["jmin"] = 3
     assert mrlbm.validate(p) == mrlbm.EINVAL
 
 

@@ -482,3 +482,78 @@ def test_table2_column_I_configuration():
         d_ora = metrics.delta(ref.conserved(), ora.finest_conserved(), XMIN, XMAX)[0]
         assert abs(E / d_gpu - E / d_ora) <= 1e-9 * (E / d_ora), (s, E / d_gpu, E / d_ora)
         run.close()
+
+
+# ------------------------------------------------------------------ reconstructed collision
+@pytest.mark.parametrize("kind", KINDS)
+def test_reconstructed_collision_parity(kind):
+    """Reconstructed collision (Sec. 4.3.1, eq. reconstructedCollision) through the C ABI
+    against the oracle's: leaf sets bit-exact and moments within 1e-12 every 15 steps, with
+    leaves down to J_min = 2 (up to 2^7 finest cells reconstructed per leaf)."""
+    p, mc = W.small_case(kind, seed=3, jmax=9, eps=1e-3)
+    run_pair(dict(p, collision="reconstructed"), mc, 60, 15, f"recon {kind}")
+    if kind == "burgers_d1q2":
+        # the flag reaches the kernel: on a nonlinear flux the two collisions differ
+        a, b = mrlbm.MRLBM(dict(p, collision="reconstructed"), mc), mrlbm.MRLBM(p, mc)
+        a.step(30)
+        b.step(30)
+        assert not np.array_equal(a.moments(mrlbm.FINEST), b.moments(mrlbm.FINEST))
+        a.close()
+        b.close()
+
+
+def test_reconstructed_collision_hbm_path_and_mixed_batch():
+    """Runs with the reconstructed collision next to runs with the leaves collision in one
+    batch (one kernel serves both), on chip and with every tree in HBM (capacity 0): each run
+    equals its oracle bit for bit in its leaf set."""
+    ps, ms = [], []
+    for i, kind in enumerate(["burgers_d1q2", "advection", "burgers_d1q2"]):
+        p, mc = W.small_case(kind, seed=10 + i, jmax=8, eps=1e-3)
+        ps.append(dict(p, collision="reconstructed" if i != 1 else "leaves"))
+        ms.append(mc)
+    for cap in (-1, 0):
+        announce("recon mixed batch", "capacity", cap)
+        b = mrlbm.Batch(ps, ms)
+        if cap >= 0:
+            b.set_capacity(cap)
+        b.step(20)
+        b.step(20)
+        for i, (p, mc) in enumerate(zip(ps, ms)):
+            ora = make_oracle(p, mc).step(40)
+            lv, ix = b.leaves(i)
+            olv, oix = ora.leaf_list()
+            assert np.array_equal(lv, olv) and np.array_equal(ix, oix), (cap, i)
+            assert rel_err(b.moments(i), ora.leaf_conserved()) <= 1e-12, (cap, i)
+        b.close()
+
+
+def test_reconstructed_collision_fp32_within_bound():
+    """FP32 storage with the reconstructed collision: within 1e-5 relative plus the eps bound
+    of the FP64 oracle run."""
+    p, mc = W.small_case("burgers_d1q2", seed=5, jmax=9, eps=1e-4)
+    p = dict(p, collision="reconstructed")
+    announce("recon fp32")
+    n = 60
+    run = mrlbm.MRLBM(dict(p, precision=mrlbm.FP32_STORAGE), mc)
+    run.step(n)
+    ora = make_oracle(p, mc).step(n)
+    ref = UniformLBM(scheme_from_params(p), p["jmax"], p["bc"], mc).step(n)
+    m32 = run.moments(mrlbm.FINEST)
+    m64 = ora.finest_conserved()
+    d64 = metrics.delta(ref.conserved(), m64, p["x_min"], p["x_max"])
+    d3264 = metrics.delta(m64, m32, p["x_min"], p["x_max"])
+    norm = metrics.delta(np.zeros_like(m64), m64, p["x_min"], p["x_max"])
+    for c in range(m64.shape[0]):
+        assert d3264[c] <= 1e-5 * norm[c] + 2.0 * max(d64[c], p["eps"]), (c, d3264, d64)
+    run.close()
+
+
+def test_reconstructed_collision_refuses_the_predictor():
+    """The refinement predictor runs with the leaves collision only."""
+    p, mc = W.small_case("burgers_d1q2", seed=1, jmax=8, eps=1e-3)
+    run = mrlbm.MRLBM(dict(p, collision="reconstructed"), mc)
+    with pytest.raises(mrlbm.MRLBMError):
+        run.set_predictor(None, mrlbm.PRED_RECORD, sample_capacity=1000)
+    run.step(3)
+    assert run.stats()["steps"] == 3
+    run.close()
