@@ -167,6 +167,34 @@ def ensemble_form(mrlbm, n, steps, prec, tune):
             "per_instance_sample": len(sample)}
 
 
+def reconstructed_form(mrlbm, seeds, steps):
+    """The reconstructed collision (Sec. 4.3.1) on the benchmark's workload (the 510-run D1Q3
+    Burgers batch, J = 14): the first `steps` steps from t = 0, against the leaves collision
+    on the same steps and launch shape (512 threads, full on-chip capacity, heavy/light
+    schedule), and delta/eps of two runs against the eps = 0 run."""
+    out = {"steps": steps}
+    for coll in ("leaves", "reconstructed"):
+        cases = instances(seeds, 0)
+        b = mrlbm.Batch([dict(c[0], collision=coll) for c in cases], [c[1] for c in cases])
+        b.set_block(512)
+        b.set_schedule(256)
+        b.checkpoint()
+        b.step(steps)
+        b.restore()
+        u0 = b.total_updates()
+        ms = b.step_timed(steps)
+        upd = b.total_updates() - u0
+        out[coll] = {"updates_per_s": upd / (ms / 1e3), "ms_per_step": ms / steps, "leaf_updates": upd}
+        b.close()
+    out["reconstructed_over_leaves"] = out["reconstructed"]["updates_per_s"] / out["leaves"]["updates_per_s"]
+    sample = [(dict(p, collision="reconstructed"), mc) for p, mc in instances(1, 0)
+              if p["s"][0] == 1.9 and p["eps"] in (1e-3, 1e-4)]
+    worst, rows = delta_check(mrlbm, sample, steps)
+    out["max_delta_over_eps"] = worst
+    out["delta_runs"] = rows
+    return out
+
+
 def learned_form(mrlbm, n_train, n_test, steps, jmax=14, eps=1e-4, pos_weight=16.0, gate=8.0):
     """The learned-refinement form on the D1Q2^3 Euler Riemann problems (J = 14, eps = 1e-4):
     record the rule-(b) pairs of n_train runs, train the network on the GPU, then advance
@@ -387,6 +415,7 @@ def main():
     ap.add_argument("--learned-steps", type=int, default=2400)
     ap.add_argument("--ensemble-runs", type=int, default=4096, help="instances of the batched ensemble")
     ap.add_argument("--ensemble-steps", type=int, default=512)
+    ap.add_argument("--recon-steps", type=int, default=200, help="steps of the reconstructed-collision form")
     ap.add_argument("--capacity", type=int, default=-1, help="on-chip capacity in cells (-1: tuner or default)")
     ap.add_argument("--schedule", type=int, default=-1, help="workgroup schedule stride (-1: tuner or identity)")
     ap.add_argument("--profile-summary", default="", help="only summarize rocprofv3 CSV output in this folder")
@@ -549,6 +578,9 @@ def main():
         result["ensemble_form"] = {
             "fp64": ensemble_form(mrlbm, args.ensemble_runs, args.ensemble_steps, 0, not args.no_tune),
             "fp32": ensemble_form(mrlbm, args.ensemble_runs, args.ensemble_steps, 1, not args.no_tune)}
+    if not args.no_extras and prec == 0:
+        print("[bench] reconstructed collision", file=sys.stderr, flush=True)
+        result["reconstructed_form"] = reconstructed_form(mrlbm, args.seeds, args.recon_steps)
     if not args.no_learned and prec == 0:
         print("[bench] learned-refinement form", file=sys.stderr, flush=True)
         result["learned_form"] = learned_form(mrlbm, 8, 64, args.learned_steps)

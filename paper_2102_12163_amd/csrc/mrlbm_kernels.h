@@ -804,29 +804,41 @@ struct Block {
     }
 
     // ----------------------------------------------------------- B1': reconstructed collision
-    // Reconstructed collision (Sec. 4.3.1, eq. reconstructedCollision), one thread per leaf of
-    // the spatial list: the values of R(Lambda^{n+1}) hold f^n projected up the tree; the
-    // leaf's finest cells are reconstructed one by one, the equilibria of their conserved
-    // moments summed in cell order and scaled by 2^-(J-l) (exact), and the leaf relaxes
-    // towards that mean. The collided values wait in scratch (Q * n values) until every leaf
-    // has read what it needs, then replace the leaf values.
-    template <class V, class LP, class SP>
-    DEV void recon_collide(const V& Vx, const LP* list, SP* scr, int n, int* nanflag) {
+    // Reconstructed collision (Sec. 4.3.1, eq. reconstructedCollision). The values of
+    // R(Lambda^{n+1}) hold f^n projected up the tree. First one thread per finest cell m:
+    // the leaf holding m (the last leaf edge at or before m, from the edge bits and their
+    // prefix), the reconstruction of m from that leaf's level, and the equilibria of its
+    // conserved moments, written to eqs (NE planes of 2^J values). Then one thread per leaf
+    // of the spatial list: the sum of its cells' equilibria in cell order, scaled by
+    // 2^-(J-l) (exact), and the relaxation of the leaf towards that mean, in place (no
+    // thread reads another leaf's values any more).
+    template <class V, class LP>
+    DEV void recon_collide(const V& Vx, const LP* list, T* eqs, int n, int* nanflag) {
         constexpr int NE = NEq<S>::N;
+        const int NJ = 1 << J;
+        for (int m = tid; m < NJ; m += NT) {
+            const uint64_t upto = E[m >> 6] & ((2ull << (m & 63)) - 1ull);  // edges at or before m
+            const int i = (int)(scanE[m >> 6] + (uint32_t)__popcll(upto)) - 1;
+            const int l = (int)(list[i] >> 27);
+            T a[Q], b[Q];
+            chain<T, G, Q, AllPops<S>>(Vx, keep, rpn, jmin, J, bc, cc, m, m, a, b, l);
+            T e[NE];
+            eq_moments<T, S>(d.cf, a, e);
+#pragma unroll
+            for (int x = 0; x < NE; ++x) eqs[x * NJ + m] = e[x];
+        }
+        __syncthreads();
         for (int i = tid; i < n; i += NT) {
             const uint32_t key = list[i];
             const int l = key >> 27, k = key & ((1u << 27) - 1u);
             const int dl = J - l;
+            const int m0 = k << dl;
             T acc[NE];
-            for (int dd = 0; dd < (1 << dl); ++dd) {
-                const int m = (k << dl) + dd;
-                T a[Q], b[Q];
-                chain<T, G, Q, AllPops<S>>(Vx, keep, rpn, jmin, J, bc, cc, m, m, a, b, l);
-                T e[NE];
-                eq_moments<T, S>(d.cf, a, e);
 #pragma unroll
-                for (int x = 0; x < NE; ++x) acc[x] = dd == 0 ? e[x] : acc[x] + e[x];
-            }
+            for (int x = 0; x < NE; ++x) acc[x] = eqs[x * NJ + m0];
+            for (int dd = 1; dd < (1 << dl); ++dd)
+#pragma unroll
+                for (int x = 0; x < NE; ++x) acc[x] = acc[x] + eqs[x * NJ + m0 + dd];
             const T sc = (T)ldexp(1.0, -dl);
 #pragma unroll
             for (int x = 0; x < NE; ++x) acc[x] = acc[x] * sc;
@@ -839,17 +851,9 @@ struct Block {
 #pragma unroll
             for (int h = 0; h < Q; ++h) {
                 bad = bad || (f[h] != f[h]);
-                scr[h * n + i] = f[h];
+                Vx.st(h, s, f[h]);
             }
             if (bad) *nanflag = 1;
-        }
-        __syncthreads();
-        for (int i = tid; i < n; i += NT) {
-            const uint32_t key = list[i];
-            const int l = key >> 27, k = key & ((1u << 27) - 1u);
-            const int s = rank_of(keep, rpn, jmin, l, k);
-#pragma unroll
-            for (int h = 0; h < Q; ++h) Vx.st(h, s, (T)scr[h * n + i]);
         }
         __syncthreads();
     }
@@ -1130,11 +1134,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                     if constexpr (RC && !LRN) {
                         if (recon) {
                             // f^n up the new tree, then the leaves collide on its reconstruction
-                            // (the pairs region is free until the stream)
+                            // (the finest cells' equilibria go to the run's HBM pairs array, free
+                            // until the stream: 2 nm (2^J + 1) values, at least NE 2^J)
                             const bool sy = tvalid ? B.project_table(VN)
                                                    : B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
                             if (!sy) __syncthreads();
-                            B.recon_collide(VN, B.ldsL, where == IN_LDS_A ? B.ldsA : B.ldsB, n, &s_nan);
+                            B.recon_collide(VN, B.ldsL, reinterpret_cast<T*>(d.pairs), n, &s_nan);
                         }
                     }
                     // the stream reads only the moving populations above the leaves, and the
