@@ -557,3 +557,35 @@ def test_reconstructed_collision_refuses_the_predictor():
     run.step(3)
     assert run.stats()["steps"] == 3
     run.close()
+
+
+def test_paper_test_V_through_the_c_abi():
+    """The paper's Test V setup (Burgers, hat datum on [-1, 1], J = 9, mu_bar = 0, clamp,
+    T = 1.3) through the C ABI: with the reconstructed collision the leaf set is bit-exact
+    with the oracle's at every eps, and delta / eps stays below 1.5, while with the leaves
+    collision it grows more than 10x from eps = 1e-2 to 1e-5, as on the oracle."""
+    J, XMIN, XMAX = 9, -3.0, 3.0
+    e = W.edges(J, XMIN, XMAX)
+    dx = e[1] - e[0]
+    xs = e[:-1, None] + (np.arange(256) + 0.5)[None, :] * dx / 256
+    u0 = np.where(np.abs(xs) <= 1.0, 1.0 - np.abs(xs), 0.0).mean(1)
+    n_steps = W.n_steps(1.3, 1.0, J, XMIN, XMAX)
+    base = W.base_params(scheme=W.D1Q2, physics=W.BURGERS, lam=1.0, s=[1.25], jmin=2, jmax=J, mu_bar=0,
+                         bc=W.CLAMP, x_min=XMIN, x_max=XMAX)
+    ref = UniformLBM(scheme_from_params(base), J, W.CLAMP, u0[None, :]).step(n_steps).conserved()
+    ratio = {}
+    for coll in ("leaves", "reconstructed"):
+        for eps in (1e-2, 1e-5):
+            p = dict(base, eps=eps, collision=coll)
+            announce("test V", coll, eps)
+            run = mrlbm.MRLBM(p, u0[None, :])
+            run.step(n_steps)
+            if coll == "reconstructed":
+                ora = make_oracle(p, u0[None, :]).step(n_steps)
+                lv, ix = run.leaves()
+                olv, oix = ora.leaf_list()
+                assert np.array_equal(lv, olv) and np.array_equal(ix, oix), eps
+            ratio[coll, eps] = metrics.delta(ref, run.moments(mrlbm.FINEST), XMIN, XMAX)[0] / eps
+            run.close()
+    assert ratio["leaves", 1e-5] / ratio["leaves", 1e-2] > 10.0, ratio
+    assert max(ratio["reconstructed", 1e-2], ratio["reconstructed", 1e-5]) < 1.5, ratio

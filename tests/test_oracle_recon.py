@@ -105,3 +105,36 @@ def test_reconstructed_differs_from_leaves_on_burgers():
     a = build(p, mc).step(40)
     b = build(p, mc, collision="leaves").step(40)
     assert not np.array_equal(a.finest_populations(), b.finest_populations())
+
+
+def v_delta_over_eps(collision, eps, s=1.25, J=9):
+    """delta / eps of the paper's Test V (Sec. 5.1, Table 1: Burgers, hat datum, T = 1.3,
+    D1Q2, lambda = 1, Omega = [-3, 3], J_min = 2, J = 9, mu_bar = 0) with the given
+    collision. The datum is read as the hat 1 - |x| on [-1, 1] and 0 elsewhere (the printed
+    formula without the indicator of [-1, 1] reaches -2 at x = +-3, beyond |u| <= lambda);
+    clamp boundaries, cell averages, N = round(T / dt)."""
+    xmin, xmax = -3.0, 3.0
+    e = W.edges(J, xmin, xmax)
+    dx = e[1] - e[0]
+    xs = e[:-1, None] + (np.arange(256) + 0.5)[None, :] * dx / 256
+    u0 = np.where(np.abs(xs) <= 1.0, 1.0 - np.abs(xs), 0.0).mean(1)
+    n_steps = W.n_steps(1.3, 1.0, J, xmin, xmax)
+    p = W.base_params(scheme=W.D1Q2, physics=W.BURGERS, lam=1.0, s=[s])
+    sch = scheme_from_params(p)
+    ref = UniformLBM(sch, J, W.CLAMP, u0[None, :]).step(n_steps)
+    a = AdaptiveMRLBM(sch, 2, J, 1, eps, 0, W.CLAMP, u0[None, :], collision=collision).step(n_steps)
+    return metrics.delta(ref.conserved(), a.finest_conserved(), xmin, xmax)[0] / eps
+
+
+
+
+
+def test_paper_test_V_needs_the_reconstructed_collision():
+    """Sec. 5.1, Test V: the example where the leaves collision misses the error estimate and
+    the reconstructed collision keeps it. With the leaves collision delta / eps grows by
+    more than 10x from eps = 1e-2 to 1e-5 (delta is not O(eps)); with the reconstructed
+    collision it stays below 1.5 at both."""
+    leaves = [v_delta_over_eps("leaves", e) for e in (1e-2, 1e-5)]
+    recon = [v_delta_over_eps("reconstructed", e) for e in (1e-2, 1e-5)]
+    assert leaves[1] / leaves[0] > 10.0, leaves
+    assert max(recon) < 1.5 and recon[1] / recon[0] < 3.0, recon
