@@ -805,8 +805,8 @@ struct Block {
 
     // ----------------------------------------------------------- B1': reconstructed collision
     // Reconstructed collision (Sec. 4.3.1, eq. reconstructedCollision). The values of
-    // R(Lambda^{n+1}) hold f^n projected up the tree. First one thread per finest cell m:
-    // the leaf holding m (the last leaf edge at or before m, from the edge bits and their
+    // R(Lambda^{n+1}) hold f^n projected up the tree. First one thread per pair of finest
+    // cells m: the leaf holding m (the last leaf edge at or before m, from the edge bits and their
     // prefix), the reconstruction of m from that leaf's level, and the equilibria of its
     // conserved moments, written to eqs (NE planes of 2^J values). Then one thread per leaf
     // of the spatial list: the sum of its cells' equilibria in cell order, scaled by
@@ -816,16 +816,25 @@ struct Block {
     DEV void recon_collide(const V& Vx, const LP* list, T* eqs, int n, int* nanflag) {
         constexpr int NE = NEq<S>::N;
         const int NJ = 1 << J;
-        for (int m = tid; m < NJ; m += NT) {
+        // cells 2t and 2t+1 (J >= 1) share one chain (its window covers both), started at the
+        // coarser of their leaves' levels
+        auto leaf_level = [&](int m) {
             const uint64_t upto = E[m >> 6] & ((2ull << (m & 63)) - 1ull);  // edges at or before m
             const int i = (int)(scanE[m >> 6] + (uint32_t)__popcll(upto)) - 1;
-            const int l = (int)(list[i] >> 27);
+            return (int)(list[i] >> 27);
+        };
+        for (int t = tid; t < (NJ >> 1); t += NT) {
+            const int ma = 2 * t, mb = 2 * t + 1;
+            const int la = leaf_level(ma), lb = leaf_level(mb);
             T a[Q], b[Q];
-            chain<T, G, Q, AllPops<S>>(Vx, keep, rpn, jmin, J, bc, cc, m, m, a, b, l);
+            chain<T, G, Q, AllPops<S>>(Vx, keep, rpn, jmin, J, bc, cc, ma, mb, a, b, la < lb ? la : lb);
             T e[NE];
             eq_moments<T, S>(d.cf, a, e);
 #pragma unroll
-            for (int x = 0; x < NE; ++x) eqs[x * NJ + m] = e[x];
+            for (int x = 0; x < NE; ++x) eqs[x * NJ + ma] = e[x];
+            eq_moments<T, S>(d.cf, b, e);
+#pragma unroll
+            for (int x = 0; x < NE; ++x) eqs[x * NJ + mb] = e[x];
         }
         __syncthreads();
         for (int i = tid; i < n; i += NT) {
