@@ -45,7 +45,7 @@ def run_pair(p, mc, nsteps, every, label):
         run.close()
 
 
-KINDS = ["advection", "burgers", "burgers_d1q2", "shallow", "euler"]
+KINDS = ["advection", "burgers", "burgers_d1q2", "shallow", "shallow_d1q3", "euler"]
 
 
 @pytest.mark.parametrize("kind", KINDS)

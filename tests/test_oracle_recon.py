@@ -12,7 +12,7 @@ from oracle.adaptive import AdaptiveMRLBM
 from oracle.lattice import BURGERS, D1Q3, VALID_PAIRS, Scheme, scheme_from_params
 from oracle.reference import UniformLBM
 
-KINDS = ["advection", "burgers", "burgers_d1q2", "shallow", "euler"]
+KINDS = ["advection", "burgers", "burgers_d1q2", "shallow", "shallow_d1q3", "euler"]
 
 
 def build(p, mc, eps=None, collision="reconstructed"):

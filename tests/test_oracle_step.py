@@ -17,7 +17,7 @@ from oracle.lattice import scheme_from_params
 from oracle.reference import UniformLBM
 from oracle import metrics, mr
 
-KINDS = ["advection", "burgers", "burgers_d1q2", "shallow", "euler"]
+KINDS = ["advection", "burgers", "burgers_d1q2", "shallow", "shallow_d1q3", "euler"]
 
 
 def build(p, mc, eps=None, cls=AdaptiveMRLBM, **kw):

@@ -16,7 +16,7 @@ Workload families (sizes as used throughout the tests and the benchmark):
                  J 2..14, eps in {1e-2, 1e-3, 1e-4}, T = 0.4 (3277 steps);
                  Riemann data + sine, rescaled to max |u0| <= 0.75 lambda (larger
                  amplitudes blow up for some seeds at s = 1.9, in the uniform scheme too).
-* ``shallow``    D1Q2^2, g = 1, lambda = 2, s = 1.7, clamp [-1, 1], J 2..16, eps = 1e-4,
+* ``shallow``    D1Q2^2 (or D1Q3, ``shallow_d1q3``), g = 1, lambda = 2, s = 1.7, clamp [-1, 1], J 2..16, eps = 1e-4,
                  T = 0.4 (26214 steps); dam break with 1% smooth noise.
 * ``batch``      D1Q2 advection/Burgers instances, J uniform in 8..14, eps in {1e-3, 1e-4}.
 * ``euler``      D1Q2^3, gamma_gas = 1.4, lambda = 3, s = 1.9, clamp [-1, 1], J 2..14,
@@ -118,10 +118,11 @@ def burgers(seed, jmax=14, eps=1e-4, s=1.9, T=0.4, jmin=2, scheme=D1Q3, steps=No
     return p, u[None, :]
 
 
-def shallow(seed, jmax=16, eps=1e-4, s=1.7, T=0.4, jmin=2, steps=None):
+def shallow(seed, jmax=16, eps=1e-4, s=1.7, T=0.4, jmin=2, steps=None, scheme=D1Q2x2):
     """Dam break: h = h_L (x < 0) or h_R, times (1 + 0.01 xi(x)) with xi a normalised sum of
     8 random-phase sines; hu = 0. h_L in U(1.5,3), h_R in U(0.5,1), redrawn until the
-    initial states satisfy |u| + sqrt(g h) <= 0.8 lambda. Clamp boundaries on [-1, 1]."""
+    initial states satisfy |u| + sqrt(g h) <= 0.8 lambda. Clamp boundaries on [-1, 1].
+    scheme: D1Q2x2 (vectorial, the default) or D1Q3 (one relaxation rate s)."""
     rng = np.random.default_rng([2, seed])
     g, lam = 1.0, 2.0
     while True:
@@ -140,7 +141,7 @@ def shallow(seed, jmax=16, eps=1e-4, s=1.7, T=0.4, jmin=2, steps=None):
     hu = np.zeros_like(h)
     if steps is None:
         steps = n_steps(T, lam, jmax)
-    p = base_params(scheme=D1Q2x2, physics=SHALLOW_WATER, lam=lam, s=[s], phys=[0.0, g, 1.4, 0.9],
+    p = base_params(scheme=scheme, physics=SHALLOW_WATER, lam=lam, s=[s], phys=[0.0, g, 1.4, 0.9],
                     jmin=jmin, jmax=jmax, eps=eps, steps=steps, bc=CLAMP)
     return p, np.stack([h, hu])
 
@@ -203,6 +204,8 @@ def small_case(kind="advection", seed=0, jmax=7, **kw):
         return burgers(seed, jmax=jmax, scheme=D1Q2, **kw)
     if kind == "shallow":
         return shallow(seed, jmax=jmax, **kw)
+    if kind == "shallow_d1q3":
+        return shallow(seed, jmax=jmax, scheme=D1Q3, **kw)
     if kind == "euler":
         return euler(seed, jmax=jmax, **kw)
     raise ValueError(kind)
