@@ -16,4 +16,6 @@ brute      literal set-based twin of the tree operators and of the uncompacted
            stream, for tiny J only (Sec. 3.3, 3.4, 4.2, eq. StreamUncompacted).
 reference  the uniform finest-grid scheme L (Sec. 2.1).
 metrics    delta, E-style l1 norms and compression factors (Sec. 5).
+exact      exact Riemann solutions (Burgers, shallow water, Euler) and their cell averages,
+           for the errors E and e against the exact solution (Sec. 5).
 """
