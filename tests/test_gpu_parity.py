@@ -589,3 +589,40 @@ def test_paper_test_V_through_the_c_abi():
             run.close()
     assert ratio["leaves", 1e-5] / ratio["leaves", 1e-2] > 10.0, ratio
     assert max(ratio["reconstructed", 1e-2], ratio["reconstructed", 1e-5]) < 1.5, ratio
+
+
+def test_euler_workload_against_the_exact_solution():
+    """The Euler Riemann workload at full size through the C ABI, checked against the exact
+    solution instead of the oracle: the reference scheme's error E (the library at eps = 0)
+    falls from J = 12 to J = 14 by at least 2^0.8, the adaptive run's error e at eps = 1e-4 is
+    within its perturbation delta of E, and delta stays below a tenth of E."""
+    from oracle import exact
+    GAM = 1.4
+    out = {}
+    for J in (12, 14):
+        p, mc = W.euler(2, jmax=J, eps=1e-4)
+        n = 60 * 2 ** (J - 9)
+        t = n * (p["x_max"] - p["x_min"]) / 2 ** J / p["lam"]
+        rl, rr = mc[0][0], mc[0][-1]
+        ul, ur = mc[1][0] / rl, mc[1][-1] / rr
+        pl = (GAM - 1.0) * (mc[2][0] - 0.5 * rl * ul * ul)
+        pr = (GAM - 1.0) * (mc[2][-1] - 0.5 * rr * ur * ur)
+        ex = exact.cell_averages(lambda xi: exact.euler_riemann(rl, ul, pl, rr, ur, pr, GAM, xi),
+                                 p["x_min"], p["x_max"], J, 0.0, t)
+        announce("euler exact", "J", J, "steps", n)
+        ref = mrlbm.MRLBM(dict(p, eps=0.0), mc)
+        ada = mrlbm.MRLBM(p, mc)
+        ref.step(n)
+        ada.step(n)
+        mr, ma = ref.moments(mrlbm.FINEST), ada.moments(mrlbm.FINEST)
+        E = metrics.delta(ex, mr, p["x_min"], p["x_max"])[0]
+        e = metrics.delta(ex, ma, p["x_min"], p["x_max"])[0]
+        d = metrics.delta(mr, ma, p["x_min"], p["x_max"])[0]
+        out[J] = (E, e, d)
+        print(f"[exact] J={J} steps={n} E={E:.4e} e={e:.4e} delta={d:.4e} E/delta={E / d:.1f} "
+              f"leaves={ada.stats()['leaves']}", flush=True)
+        ref.close()
+        ada.close()
+        assert abs(e - E) <= d * (1 + 1e-9), (J, E, e, d)
+        assert d < 0.1 * E, (J, E, d)
+    assert out[12][0] / out[14][0] > 2 ** 0.8, out
