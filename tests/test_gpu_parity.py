@@ -626,3 +626,24 @@ def test_euler_workload_against_the_exact_solution():
         assert abs(e - E) <= d * (1 + 1e-9), (J, E, e, d)
         assert d < 0.1 * E, (J, E, d)
     assert out[12][0] / out[14][0] > 2 ** 0.8, out
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_seeded_configuration_sweep(seed):
+    """A seeded sweep over the parameters the other cases fix: family, gamma (1..3), J_min
+    (1..3, with at least 2 gamma + 1 coarse cells on a periodic domain), J (6..9), eps
+    (1e-2..1e-4), mu_bar (0..2) and the collision (reconstructed only with gamma = 1); leaf sets
+    bit-exact with the oracle and moments within 1e-12 every 10 steps over 30 steps."""
+    rng = np.random.default_rng([9, seed])
+    kind = KINDS[int(rng.integers(len(KINDS)))]
+    gamma = int(rng.integers(1, 4))
+    jmax = int(rng.integers(6, 10))
+    p, mc = W.small_case(kind, seed=int(rng.integers(1000)), jmax=jmax, eps=float(rng.choice([1e-2, 1e-3, 1e-4])))
+    jmin = int(rng.integers(1, 4))
+    if p["bc"] == W.PERIODIC:
+        while 2 ** jmin < 2 * gamma + 1:
+            jmin += 1
+    coll = "reconstructed" if gamma == 1 and rng.random() < 0.5 else "leaves"
+    p = dict(p, gamma=gamma, jmin=jmin, mu_bar=int(rng.integers(0, 3)), collision=coll)
+    assert mrlbm.validate(p) == mrlbm.OK, p
+    run_pair(p, mc, 30, 10, f"sweep {seed} {kind} gamma {gamma} J {jmin}..{jmax} {coll}")
