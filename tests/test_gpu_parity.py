@@ -647,3 +647,11 @@ def test_seeded_configuration_sweep(seed):
     p = dict(p, gamma=gamma, jmin=jmin, mu_bar=int(rng.integers(0, 3)), collision=coll)
     assert mrlbm.validate(p) == mrlbm.OK, p
     run_pair(p, mc, 30, 10, f"sweep {seed} {kind} gamma {gamma} J {jmin}..{jmax} {coll}")
+
+
+def test_reconstructed_collision_at_full_size():
+    """The reconstructed collision on the benchmark's D1Q3 Burgers workload at its full size
+    (J = 14, leaves down to J_min = 2: up to 4096 finest cells per leaf), 60 steps from t = 0:
+    leaf sets bit-exact and moments within 1e-12 every 20 steps."""
+    p, mc = W.burgers(0, jmax=14, eps=1e-4, s=1.9)
+    run_pair(dict(p, collision="reconstructed"), mc, 60, 20, "recon burgers J14")
