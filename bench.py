@@ -24,10 +24,13 @@ Reported next to the throughput:
   eps = 0 run of the same library (the uniform finest-grid scheme, bit for bit), as delta/eps;
 * the batched ensemble (FP64 and FP32): 4096 independent D1Q2 advection/Burgers instances
   with J uniform in 8..14 in one launch, against one launch per time step and instance;
+* the reconstructed collision (Sec. 4.3.1): the same 510 runs, the first 200 steps with it
+  and with the leaves collision in the same launch shape, and delta/eps of two runs;
 * the learned-refinement form: on D1Q2^3 Euler Riemann problems (J = 14, eps = 1e-4) the
   network is trained on the rule-(b) pairs the method records, then unseen runs advance with
   and without it: leaf-cell updates/s, delta/eps, misses and redos of the judge;
-* the CPU baseline: the FP64 oracle (plain numpy, one thread) on a bounded sample.
+* the CPU baseline: the FP64 oracle (plain numpy, one thread) on two whole runs of the
+  workload (about 14 s).
 """
 
 import argparse
