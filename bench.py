@@ -315,11 +315,14 @@ def profile_summary(path):
     for f in sorted(glob.glob(os.path.join(path, "**", "*_kernel_trace.csv"), recursive=True)):
         with open(f) as fh:
             rows = [r for r in csv.DictReader(fh) if "k_steps" in r["Kernel_Name"]]
-        for r in rows[:4]:
+        for r in rows[:12]:
             dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            name = r["Kernel_Name"]
+            tmpl = name[name.find("k_steps"):name.find(">") + 1] if "<" in name else "k_steps"
             lines.append(f"step kernel dispatch: {dur:.1f} us, grid {r['Grid_Size_X']}, workgroup "
                          f"{r['Workgroup_Size_X']}, LDS {r['LDS_Block_Size']} B, VGPR {r['VGPR_Count']}, "
-                         f"AGPR {r['Accum_VGPR_Count']}, SGPR {r['SGPR_Count']}, scratch {r['Scratch_Size']} B")
+                         f"AGPR {r['Accum_VGPR_Count']}, SGPR {r['SGPR_Count']}, scratch {r['Scratch_Size']} B"
+                         f"  {tmpl}")
     for f in sorted(glob.glob(os.path.join(path, "**", "*_counter_collection.csv"), recursive=True)):
         acc = {}
         with open(f) as fh:
@@ -419,6 +422,8 @@ def main():
     ap.add_argument("--ensemble-runs", type=int, default=4096, help="instances of the batched ensemble")
     ap.add_argument("--ensemble-steps", type=int, default=512)
     ap.add_argument("--recon-steps", type=int, default=200, help="steps of the reconstructed-collision form")
+    ap.add_argument("--recon-only", action="store_true",
+                    help="only the reconstructed-collision form (for profiling its launches)")
     ap.add_argument("--capacity", type=int, default=-1, help="on-chip capacity in cells (-1: tuner or default)")
     ap.add_argument("--schedule", type=int, default=-1, help="workgroup schedule stride (-1: tuner or identity)")
     ap.add_argument("--profile-summary", default="", help="only summarize rocprofv3 CSV output in this folder")
@@ -449,6 +454,9 @@ def main():
 
     from paper_2102_12163_amd import mrlbm
 
+    if args.recon_only:
+        print(json.dumps({"reconstructed_form": reconstructed_form(mrlbm, args.seeds, args.recon_steps)}))
+        return 0
     prec = 0 if args.precision == "fp64" else 1
     cases = instances(args.seeds, prec)
     print(f"[bench] {len(cases)} runs, warmup {args.warmup}, timed {args.steps}", file=sys.stderr, flush=True)
