@@ -655,3 +655,35 @@ def test_reconstructed_collision_at_full_size():
     leaf sets bit-exact and moments within 1e-12 every 20 steps."""
     p, mc = W.burgers(0, jmax=14, eps=1e-4, s=1.9)
     run_pair(dict(p, collision="reconstructed"), mc, 60, 20, "recon burgers J14")
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_seeded_fp32_sweep(seed):
+    """FP32 storage over a seeded sweep of family, gamma, J_min, J, eps and collision: the
+    finest-level moments after 30 steps within 1e-5 relative plus the eps bound of the FP64
+    oracle run (details and thresholds stay FP64, so the trees may differ near thresholds)."""
+    rng = np.random.default_rng([10, seed])
+    kind = KINDS[int(rng.integers(len(KINDS)))]
+    gamma = int(rng.integers(1, 4))
+    jmax = int(rng.integers(6, 10))
+    p, mc = W.small_case(kind, seed=int(rng.integers(1000)), jmax=jmax, eps=float(rng.choice([1e-3, 1e-4])))
+    jmin = int(rng.integers(1, 4))
+    if p["bc"] == W.PERIODIC:
+        while 2 ** jmin < 2 * gamma + 1:
+            jmin += 1
+    coll = "reconstructed" if gamma == 1 and rng.random() < 0.5 else "leaves"
+    p = dict(p, gamma=gamma, jmin=jmin, collision=coll)
+    announce("fp32 sweep", seed, kind, "gamma", gamma, "J", jmin, jmax, coll)
+    n = 30
+    run = mrlbm.MRLBM(dict(p, precision=mrlbm.FP32_STORAGE), mc)
+    run.step(n)
+    ora = make_oracle(p, mc).step(n)
+    ref = UniformLBM(scheme_from_params(p), p["jmax"], p["bc"], mc).step(n)
+    m32 = run.moments(mrlbm.FINEST)
+    m64 = ora.finest_conserved()
+    d64 = metrics.delta(ref.conserved(), m64, p["x_min"], p["x_max"])
+    d3264 = metrics.delta(m64, m32, p["x_min"], p["x_max"])
+    norm = metrics.delta(np.zeros_like(m64), m64, p["x_min"], p["x_max"])
+    for c in range(m64.shape[0]):
+        assert d3264[c] <= 1e-5 * norm[c] + 2.0 * max(d64[c], p["eps"]), (c, d3264, d64)
+    run.close()
