@@ -687,3 +687,34 @@ def test_seeded_fp32_sweep(seed):
     for c in range(m64.shape[0]):
         assert d3264[c] <= 1e-5 * norm[c] + 2.0 * max(d64[c], p["eps"]), (c, d3264, d64)
     run.close()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_seeded_batch_sweep(seed):
+    """Heterogeneous batches: six D1Q2 runs (advection and Burgers) with J in 6..10, eps in
+    1e-2..1e-4 and either collision in one launch, at a random block size and on-chip capacity
+    (all trees in HBM, a small limit that moves trees between LDS and HBM, or the full LDS);
+    every run bit-exact in its leaf set with its own oracle after 25 + 15 steps."""
+    rng = np.random.default_rng([11, seed])
+    ps, ms = [], []
+    for i in range(6):
+        kind = ["advection", "burgers_d1q2"][int(rng.integers(2))]
+        p, mc = W.small_case(kind, seed=int(rng.integers(1000)), jmax=int(rng.integers(6, 11)),
+                             eps=float(rng.choice([1e-2, 1e-3, 1e-4])))
+        ps.append(dict(p, collision="reconstructed" if rng.random() < 0.5 else "leaves"))
+        ms.append(mc)
+    block = int(rng.choice([128, 256, 512]))
+    cap = int(rng.choice([-1, 0, 200]))
+    announce("batch sweep", seed, "block", block, "capacity", cap, [p["jmax"] for p in ps])
+    b = mrlbm.Batch(ps, ms)
+    b.set_block(block)
+    b.set_capacity(cap)
+    b.step(25)
+    b.step(15)
+    for i, (p, mc) in enumerate(zip(ps, ms)):
+        ora = make_oracle(p, mc).step(40)
+        lv, ix = b.leaves(i)
+        olv, oix = ora.leaf_list()
+        assert np.array_equal(lv, olv) and np.array_equal(ix, oix), (seed, i)
+        assert rel_err(b.moments(i), ora.leaf_conserved()) <= 1e-12, (seed, i)
+    b.close()
