@@ -170,24 +170,31 @@ def ensemble_form(mrlbm, n, steps, prec, tune):
             "per_instance_sample": len(sample)}
 
 
-def reconstructed_form(mrlbm, seeds, steps):
+def reconstructed_form(mrlbm, seeds, steps, tune=True, block=0, capacity=-1, schedule=256):
     """The reconstructed collision (Sec. 4.3.1) on the benchmark's workload (the 510-run D1Q3
     Burgers batch, J = 14): the first `steps` steps from t = 0, against the leaves collision
-    on the same steps and launch shape (512 threads, full on-chip capacity, heavy/light
-    schedule), and delta/eps of two runs against the eps = 0 run."""
+    on the same steps, each in the launch shape the built-in tuner picks for it (or the given
+    one), and delta/eps of two runs against the eps = 0 run."""
     out = {"steps": steps}
     for coll in ("leaves", "reconstructed"):
         cases = instances(seeds, 0)
         b = mrlbm.Batch([dict(c[0], collision=coll) for c in cases], [c[1] for c in cases])
-        b.set_block(512)
-        b.set_schedule(256)
         b.checkpoint()
+        if tune:
+            b.tune(steps)
+        else:
+            b.set_block(block or 512)
+            if capacity >= 0:
+                b.set_capacity(capacity)
+            b.set_schedule(schedule)
         b.step(steps)
         b.restore()
         u0 = b.total_updates()
         ms = b.step_timed(steps)
         upd = b.total_updates() - u0
-        out[coll] = {"updates_per_s": upd / (ms / 1e3), "ms_per_step": ms / steps, "leaf_updates": upd}
+        out[coll] = {"updates_per_s": upd / (ms / 1e3), "ms_per_step": ms / steps, "leaf_updates": upd,
+                     "threads_capacity_schedule": [b.get_block(), b.get_capacity(), b.get_schedule()],
+                     "tuned": tune}
         b.close()
     out["reconstructed_over_leaves"] = out["reconstructed"]["updates_per_s"] / out["leaves"]["updates_per_s"]
     sample = [(dict(p, collision="reconstructed"), mc) for p, mc in instances(1, 0)
@@ -455,7 +462,9 @@ def main():
     from paper_2102_12163_amd import mrlbm
 
     if args.recon_only:
-        print(json.dumps({"reconstructed_form": reconstructed_form(mrlbm, args.seeds, args.recon_steps)}))
+        print(json.dumps({"reconstructed_form": reconstructed_form(
+            mrlbm, args.seeds, args.recon_steps, tune=not args.no_tune, block=args.block, capacity=args.capacity,
+            schedule=args.schedule if args.schedule >= 0 else 256)}))
         return 0
     prec = 0 if args.precision == "fp64" else 1
     cases = instances(args.seeds, prec)
@@ -591,7 +600,10 @@ def main():
             "fp32": ensemble_form(mrlbm, args.ensemble_runs, args.ensemble_steps, 1, not args.no_tune)}
     if not args.no_extras and prec == 0:
         print("[bench] reconstructed collision", file=sys.stderr, flush=True)
-        result["reconstructed_form"] = reconstructed_form(mrlbm, args.seeds, args.recon_steps)
+        result["reconstructed_form"] = reconstructed_form(mrlbm, args.seeds, args.recon_steps,
+                                                          tune=not args.no_tune, block=args.block,
+                                                          capacity=args.capacity,
+                                                          schedule=args.schedule if args.schedule >= 0 else 256)
     if not args.no_learned and prec == 0:
         print("[bench] learned-refinement form", file=sys.stderr, flush=True)
         result["learned_form"] = learned_form(mrlbm, 8, 64, args.learned_steps)
