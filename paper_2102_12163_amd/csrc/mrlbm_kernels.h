@@ -642,7 +642,12 @@ struct Block {
             grade_level(a, tid, NT);
             __syncthreads();
         }
-        if (wave == 0 && a > jmin) grade_wave(a);
+        if (wave == 0 && a > jmin) {
+            // the rest of the run waits at the barrier for this wave: issue it first on its SIMD
+            __builtin_amdgcn_s_setprio(3);
+            grade_wave(a);
+            __builtin_amdgcn_s_setprio(0);
+        }
         __syncthreads();
     }
 
