@@ -1076,7 +1076,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
     const bool recon = RC && !LRN && d.recon != 0;
     const bool judge = LRN && scheme && (d.pmode == 2 || (d.pmode == 1 && d.mlp != nullptr));
     long long upd = 0, misses = 0, redos = 0;
-    int last = -1;
+    int last = -1, lastn = -1;  // leaves of the last step's tree (scheme steps / any step)
     bool last_fast = false;
     for (int stp = 0; stp < nsteps; ++stp) {
         // ---- projection of f^n up the old tree (once per step, kept through redos)
@@ -1222,6 +1222,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
         }
         B.rotate();
         where = nwhere;
+        lastn = n;
         if (scheme) {
             upd += n;
             last = n;
@@ -1252,8 +1253,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
         if (mode & MODE_SCHEME) {
             st.steps += nsteps;
             st.leaf_updates += upd;
-            if (last >= 0) st.n_leaves = last;
         }
+        if (lastn >= 0) st.n_leaves = lastn;
         st.n_r = nR;
         st.misses += misses;
         st.redos += redos;

@@ -96,6 +96,7 @@ SIGNATURES = {
     "mrlbm_mlp_logits": (c_int32, [c_void_p, _P(ctypes.c_float), c_int64, _P(ctypes.c_float)]),
     "mrlbm_mlp_destroy": (None, [c_void_p]),
     "mrlbm_mlp_last_error": (ctypes.c_char_p, [c_void_p]),
+    "mrlbm_run_noalloc": (c_int32, [_P(Params), c_void_p, c_int32, c_void_p, c_void_p]),
     "mrlbm_batch_destroy": (None, [c_void_p]),
     "mrlbm_batch_last_error": (ctypes.c_char_p, [c_void_p]),
 }
@@ -151,9 +152,37 @@ def make_params(p):
     return P
 
 
+# Conserved moments per (scheme, physics) pair (the valid pairs of the C ABI).
+_Q_CONS = {(D1Q2, ADVECTION): 1, (D1Q2, BURGERS): 1, (D1Q3, BURGERS): 1, (D1Q3, SHALLOW_WATER): 2,
+           (D1Q2x2, SHALLOW_WATER): 2, (D1Q2x3, EULER): 3}
+
+
+def _initial_moments(P, m_cons0):
+    """m_cons0 as a contiguous float64 array of shape (q_cons, 2^j_max): the C side reads
+    exactly q_cons 2^j_max doubles from it."""
+    m = np.ascontiguousarray(m_cons0, dtype=np.float64)
+    qc = _Q_CONS.get((P.scheme, P.physics))
+    if qc is not None and 0 <= P.j_max <= 30:
+        want = (qc, 1 << P.j_max)
+        if m.shape != want and not (qc == 1 and m.shape == (want[1],)):
+            raise ValueError(f"initial moments have shape {m.shape}, need {want}")
+    return m
+
+
 def validate(p):
     P = p if isinstance(p, Params) else make_params(p)
     return lib().mrlbm_validate(ctypes.byref(P))
+
+
+NOALLOC_SCRATCH_BYTES = 5 << 20
+
+
+def run_noalloc(params, d_m_cons0, nsteps, d_m_out, stream=None):
+    """mrlbm_run_noalloc: device addresses (ints) of the initial finest conserved averages
+    [q_cons][2^J] and of the output [q_cons][2^J]; returns the status code (nothing is
+    allocated; the call is enqueued on ``stream`` and does not synchronize)."""
+    P = params if isinstance(params, Params) else make_params(params)
+    return lib().mrlbm_run_noalloc(ctypes.byref(P), c_void_p(d_m_cons0), int(nsteps), c_void_p(d_m_out), stream)
 
 
 def _check(rc, msgfn):
@@ -241,7 +270,7 @@ class MRLBM:
     def __init__(self, params, m_cons0, stream=None):
         L = lib()
         self.P = params if isinstance(params, Params) else make_params(params)
-        m = np.ascontiguousarray(m_cons0, dtype=np.float64)
+        m = _initial_moments(self.P, m_cons0)
         h = ctypes.c_void_p()
         rc = L.mrlbm_create(ctypes.byref(self.P), _dptr(m), stream, ctypes.byref(h))
         _check(rc, lambda: L.mrlbm_last_error(None).decode())
@@ -328,7 +357,9 @@ class Batch:
         arr = (Params * n)()
         for i, p in enumerate(params_list):
             arr[i] = p if isinstance(p, Params) else make_params(p)
-        self._m = [np.ascontiguousarray(m, dtype=np.float64) for m in m_cons_list]
+        if len(m_cons_list) != n:
+            raise ValueError("need one initial moment array per run")
+        self._m = [_initial_moments(arr[i], m) for i, m in enumerate(m_cons_list)]
         ptrs = (ctypes.POINTER(c_double) * n)(*[_dptr(m) for m in self._m])
         h = ctypes.c_void_p()
         rc = L.mrlbm_batch_create(arr, n, ptrs, stream, ctypes.byref(h))

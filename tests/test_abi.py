@@ -111,6 +111,23 @@ def test_create_rejects_before_touching_the_device():
     assert e.value.code == mrlbm.EINVAL
 
 
+def test_binding_checks_the_initial_moment_shape():
+    """The C side reads q_cons 2^J doubles from the initial-moment pointer: the binding refuses
+    an array of another shape before the call (single runs and batches)."""
+    p = good()
+    n = 2 ** p["jmax"]
+    for bad in (np.zeros((1, n - 1)), np.zeros((2, n)), np.zeros((1, 2 * n))):
+        with pytest.raises(ValueError):
+            mrlbm.MRLBM(p, bad)
+        with pytest.raises(ValueError):
+            mrlbm.Batch([p, p], [np.zeros((1, n)), bad])
+    ps, _ = W.shallow(0, jmax=6)
+    with pytest.raises(ValueError):
+        mrlbm.MRLBM(ps, np.zeros((1, 64)))  # shallow water has two conserved moments
+    with pytest.raises(ValueError):
+        mrlbm.Batch([p], [])
+
+
 def test_batch_rejects_mixed_schemes():
     p1 = good()
     p2, _ = W.advection(0, jmax=8)
@@ -144,8 +161,9 @@ def test_bench_refuses_several_gpus_and_empty_regions():
 
 
 def test_profile_summaries_match_the_kernel_sources():
-    """The committed counter summary names the sha256 of the step-kernel sources it was taken
-    on; bench.py reports its traffic only while they match (this pins the hash function)."""
+    """The committed counter summary of the headline launch names the sha256 of the step-kernel
+    sources and the launch (workload key) it was taken on; bench.py reports its traffic and
+    issue figures only while both match, and the key is the one of the default command."""
     import importlib.util
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
@@ -153,7 +171,15 @@ def test_profile_summaries_match_the_kernel_sources():
     spec.loader.exec_module(bench)
     h = bench.kernel_source_hash()
     assert len(h) == 64
-    t = bench.traffic_for(1.0e6)
-    with open(bench.COUNTER_FILE) as fh:
-        text = fh.read()
-    assert ("kernel_source_sha256: " + h in text) == (t is not None)
+    kv = bench.read_counters()
+    assert kv, "profiles/ holds no counter summary of the headline launch"
+    default_key = bench.workload_key(4096, 20, 5, bench.HEADLINE_SHAPE["block"], bench.HEADLINE_SHAPE["capacity"],
+                                     4096, 0)
+    assert kv["workload_key"] == default_key
+    got = bench.counters_for(default_key)
+    assert (kv["kernel_source_sha256"] == h) == (got is not None)
+    assert bench.counters_for(default_key.replace("steps=20", "steps=21")) is None
+    if got is not None:
+        iss = bench.issue_block(got, 1.0e9)
+        assert iss["valu_per_update"] > 0 and iss["ceiling_updates_per_s"] > 0
+        assert float(got["traffic_bytes_per_launch"]) > 0

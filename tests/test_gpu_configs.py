@@ -1,0 +1,152 @@
+"""GPU parity on the stated workload configurations at their full sizes, in the launch
+shapes the benchmark uses: FP32 storage on the D1Q3 Burgers grid (J = 14, s in {1.5, 1.9}
+x eps in {1e-2, 1e-3, 1e-4}) over 226 steps and over sampled whole runs to T = 0.4;
+the 4096-instance ensemble in FP64 and FP32 over its 512 steps (one sampled instance per
+J); Sod's shock tube (Sec. 5.3) at J = 14 and the shallow-water dam break at J = 16 over
+1000 steps each, leaf sets bit-exact with the oracle.
+
+FP64 runs are held to bit-exact leaf sets and moments within 1e-12; FP32 storage to 1e-5
+relative plus the eps bound (``gpu_helpers.fp32_bound``), whose two parts are printed
+separately for every compared run."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2102_12163_amd import mrlbm
+
+from gpu_helpers import compare_run, first_divergence, fp32_bound, make_oracle, rel_err, same_leaves
+
+pytestmark = pytest.mark.gpu
+
+GRID = [(s, eps) for s in (1.5, 1.9) for eps in (1e-2, 1e-3, 1e-4)]
+
+
+def announce(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def fp32_batch(cases):
+    """FP32-storage batch in the benchmark's FP32 launch shape (512 threads, on-chip capacity
+    1157 cells, heaviest runs first)."""
+    b = mrlbm.Batch([dict(p, precision=mrlbm.FP32_STORAGE) for p, _ in cases], [mc for _, mc in cases])
+    b.set_block(512)
+    b.set_capacity(1157)
+    b.set_schedule(len(cases))
+    return b
+
+
+def check_fp32(label, p, mc, m32, nsteps, leaves32):
+    ora = make_oracle(p, mc).step(nsteps)
+    m64 = ora.finest_conserved()
+    r = fp32_bound(p, mc, m32, m64, nsteps)
+    same = same_leaves(leaves32, ora)
+    print(f"[fp32] {label}: delta32 {r['delta32']} <= rel part {r['rel_part']} + eps part {r['eps_part']}; "
+          f"|fp32 - fp64|_1 {r['fp32_vs_fp64']}, fp64 delta {r['delta64']}, leaf sets equal: {same}", flush=True)
+    assert r["ok"], (label, r)
+    print(f"[fp32] {label}: max relative difference to the FP64 oracle {rel_err(m32, m64):.3e}", flush=True)
+    return r
+
+
+def test_fp32_burgers_j14_grid_226_steps():
+    """FP32 storage on the whole Burgers grid at J = 14 (one seeded run per (s, eps)),
+    226 steps in one launch: every run within 1e-5 relative plus the eps bound of the
+    FP64 oracle."""
+    cases = [W.burgers(0, jmax=14, eps=eps, s=s) for s, eps in GRID]
+    announce("fp32 burgers grid", len(cases))
+    b = fp32_batch(cases)
+    try:
+        n = 226
+        b.step(n)
+        for i, ((p, mc), (s, eps)) in enumerate(zip(cases, GRID)):
+            check_fp32(f"s {s} eps {eps}", p, mc, b.moments(i, mrlbm.FINEST), n, b.leaves(i))
+    finally:
+        b.close()
+
+
+@pytest.mark.parametrize("s,eps", [(1.9, 1e-4), (1.5, 1e-2)])
+def test_fp32_burgers_j14_whole_run(s, eps):
+    """FP32 storage over a whole Burgers run to T = 0.4 (3277 steps, one launch, benchmark
+    launch shape) against the FP64 oracle's whole run."""
+    p, mc = W.burgers(1, jmax=14, eps=eps, s=s)
+    n = p["steps"]
+    announce("fp32 burgers whole run", s, eps, n)
+    b = fp32_batch([(p, mc)])
+    try:
+        b.step(n)
+        check_fp32(f"whole run s {s} eps {eps}", p, mc, b.moments(0, mrlbm.FINEST), n, b.leaves(0))
+    finally:
+        b.close()
+
+
+def ensemble(prec):
+    cases = [W.batch_instance(s, steps=512) for s in range(4096)]
+    ps = [dict(c[0], precision=prec) for c in cases]
+    return cases, ps, mrlbm.Batch(ps, [c[1] for c in cases])
+
+
+def test_fp32_ensemble_at_full_size():
+    """The FP32 ensemble (4096 instances, J uniform in 8..14) over its 512 steps as one launch
+    in the tuner's launch shape; one sampled instance per J against the FP64 oracle."""
+    cases, ps, b = ensemble(mrlbm.FP32_STORAGE)
+    announce("fp32 ensemble", len(cases))
+    try:
+        b.tune(8)
+        n = 512
+        b.step(n)
+        picked = {}
+        for i, p in enumerate(ps):
+            picked.setdefault(p["jmax"], i)
+        assert sorted(picked) == list(range(8, 15))
+        for j, i in sorted(picked.items()):
+            p, mc = cases[i]
+            check_fp32(f"instance {i} J {j}", p, mc, b.moments(i, mrlbm.FINEST), n, b.leaves(i))
+        assert all(b.stats(i)["steps"] == n for i in range(0, len(cases), 97))
+    finally:
+        b.close()
+
+
+def test_sod_j14_bit_exact():
+    """Sod's shock tube (Sec. 5.3: rho, u, p = 1, 0, 1 | 0.125, 0, 0.1), D1Q2^3, lambda = 3,
+    J = 14, eps = 1e-4, over 1000 steps: leaf sets bit-exact and moments within 1e-12 every
+    250 steps."""
+    p, mc = W.euler(0, jmax=14, sod=True)
+    announce("sod J14")
+    run = mrlbm.MRLBM(p, mc)
+    ora = make_oracle(p, mc)
+    done = 0
+    try:
+        while done < 1000:
+            run.step(250)
+            ora.step(250)
+            done += 250
+            upto = done
+            compare_run(run, ora, f"sod step {done}",
+                        locate=lambda: first_divergence(lambda: mrlbm.MRLBM(p, mc), p, mc, upto))
+        assert run.stats()["leaf_updates"] == ora.leaf_updates
+    finally:
+        run.close()
+
+
+def test_shallow_water_j16_1000_steps():
+    """The shallow-water dam break at J = 16 (65536 finest cells), 1000 of its 26214 steps:
+    leaf sets bit-exact and moments within 1e-12 every 250 steps."""
+    p, mc = W.shallow(0, jmax=16)
+    announce("shallow J16 1000 steps")
+    run = mrlbm.MRLBM(p, mc)
+    ora = make_oracle(p, mc)
+    done = 0
+    try:
+        while done < 1000:
+            run.step(250)
+            ora.step(250)
+            done += 250
+            upto = done
+            compare_run(run, ora, f"shallow J16 step {done}",
+                        locate=lambda: first_divergence(lambda: mrlbm.MRLBM(p, mc), p, mc, upto))
+        assert run.stats()["leaf_updates"] == ora.leaf_updates
+    finally:
+        run.close()

@@ -15,7 +15,7 @@ from oracle.lattice import scheme_from_params
 from oracle.reference import UniformLBM
 from paper_2102_12163_amd import mrlbm
 
-from gpu_helpers import compare_run, make_oracle, rel_err
+from gpu_helpers import compare_run, first_divergence, make_oracle, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -26,6 +26,8 @@ def announce(*a):
 
 
 def run_pair(p, mc, nsteps, every, label):
+    """The GPU run and the oracle side by side, compared every ``every`` steps; a leaf-set
+    difference fails, with the step where the trees first diverged located by a re-run."""
     announce(label, "J", p["jmax"], "steps", nsteps)
     run = mrlbm.MRLBM(p, mc)
     ora = make_oracle(p, mc)
@@ -36,8 +38,9 @@ def run_pair(p, mc, nsteps, every, label):
             run.step(k)
             ora.step(k)
             done += k
-            if not compare_run(run, ora, f"{label} step {done}"):
-                break
+            upto = done
+            compare_run(run, ora, f"{label} step {done}",
+                        locate=lambda: first_divergence(lambda: mrlbm.MRLBM(p, mc), p, mc, upto))
         st = run.stats()
         assert st["steps"] == done
         assert st["leaf_updates"] == ora.leaf_updates
@@ -100,6 +103,8 @@ def test_adapt_only_parity(kind):
     for _ in range(2):
         run.adapt()
         ora.adapt()
+        # the handle's statistics follow an adaptation (before any query refreshes them)
+        assert run.stats()["leaves"] == ora.n_leaves()
         lv, ix = run.leaves()
         olv, oix = ora.leaf_list()
         assert np.array_equal(lv, olv) and np.array_equal(ix, oix)
@@ -392,15 +397,16 @@ def test_checkpoint_restore_repeats_the_same_steps():
 
 def test_batched_ensemble_at_full_size():
     """The batched ensemble at its full size (4096 instances, J uniform in 8..14, advection
-    and Burgers, eps in {1e-3, 1e-4}) in the tuner's launch shape, as one launch: one sampled
-    instance per J_max against the oracle (leaves bit for bit, moments to 1e-12)."""
+    and Burgers, eps in {1e-3, 1e-4}) in the tuner's launch shape, its 512 steps as one
+    launch: one sampled instance per J_max against the oracle (leaves bit for bit, moments
+    to 1e-12)."""
     cases = [W.batch_instance(s, steps=0) for s in range(4096)]
     announce("ensemble", len(cases))
     ps, ms = [c[0] for c in cases], [c[1] for c in cases]
     b = mrlbm.Batch(ps, ms)
     try:
         b.tune(8)
-        nsteps = 40
+        nsteps = 512
         b.step(nsteps)
         picked = {}
         for i, p in enumerate(ps):
