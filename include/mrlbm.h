@@ -46,10 +46,11 @@ enum mrlbm_status {
     MRLBM_ESTATE = -6     /* call not valid in the handle's state               */
 };
 
-/* Schemes (Sec. 5.1.1 D1Q2, Sec. 5.2.1 D1Q3, Sec. 5.3 vectorial D1Q2^k). */
-enum mrlbm_scheme { MRLBM_D1Q2 = 0, MRLBM_D1Q3 = 1, MRLBM_D1Q2x2 = 2, MRLBM_D1Q2x3 = 3 };
+/* Schemes (Sec. 5.1.1 D1Q2, Sec. 5.2.1 D1Q3 and D1Q5, Sec. 5.3 vectorial D1Q2^k). D1Q5 has
+ * the velocities 0, +-lambda, +-2 lambda: its stream reaches two cells (sigma = 2). */
+enum mrlbm_scheme { MRLBM_D1Q2 = 0, MRLBM_D1Q3 = 1, MRLBM_D1Q2x2 = 2, MRLBM_D1Q2x3 = 3, MRLBM_D1Q5 = 4 };
 /* Physics (equilibria). Valid pairs: D1Q2+{ADVECTION,BURGERS}, D1Q3+{BURGERS,SHALLOW_WATER},
- * D1Q2x2+SHALLOW_WATER, D1Q2x3+EULER. */
+ * D1Q2x2+SHALLOW_WATER, D1Q2x3+EULER, D1Q5+SHALLOW_WATER. */
 enum mrlbm_physics { MRLBM_ADVECTION = 0, MRLBM_BURGERS = 1, MRLBM_SHALLOW_WATER = 2, MRLBM_EULER = 3 };
 /* Boundary reading: wrap, or map an out-of-range index to the nearest cell of its level. */
 enum mrlbm_bc { MRLBM_PERIODIC = 0, MRLBM_CLAMP = 1 };
@@ -83,9 +84,11 @@ typedef struct {
     int32_t n_s;         /* number of rates in s: 1 (broadcast) or q - q_cons              */
     double lambda;       /* lattice velocity > 0; dt = dx_J / lambda (Sec. 2.1)            */
     double s[8];         /* relaxation rates of the non-conserved moments, in (0, 2]       */
-    double phys[4];      /* [0] advection velocity V, [1] gravity g > 0,
+    double phys[4];      /* [0] advection velocity V (D1Q5: beta of the fifth-moment
+                            equilibrium beta lambda^2 M2eq), [1] gravity g > 0,
                             [2] gamma_gas > 1, [3] alpha > 0 of the D1Q3 Burgers
-                            third-moment equilibrium alpha lambda^2 u                     */
+                            third-moment equilibrium alpha lambda^2 u (D1Q5: of the
+                            fourth-moment equilibrium alpha lambda^2 hu)                  */
     double x_min, x_max; /* domain [a, b], a < b (Sec. 2)                                  */
     int32_t j_min;       /* coarsest level, 1 <= j_min <= j_max                            */
     int32_t j_max;       /* finest level J <= MRLBM_MAX_J                                   */

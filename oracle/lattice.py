@@ -15,6 +15,11 @@ Paper passages followed
   equilibrium of the third moment (hu)^2/h + g h^2/2.
 * Sec. 5.3: vectorial D1Q2^3 for Euler, three juxtaposed D1Q2 blocks coupled
   through the equilibria of the odd moments.
+* Sec. 5.2.1: D1Q5 for shallow water, velocities (0, lambda, -lambda, 2 lambda,
+  -2 lambda), M rows (1,1,1,1,1), lambda (0,1,-1,2,-2), lambda^2 (0,1,1,4,4),
+  lambda^3 (0,1,-1,8,-8), lambda^4 (0,1,1,16,16); conserved h, hu; equilibria
+  M2 = (hu)^2/h + g h^2/2, M3 = alpha lambda^2 hu, M4 = beta lambda^2 M2 (the paper's
+  runs: alpha = beta = 1, s3 = s4 = 1). Its stencil reaches two cells (sigma = 2).
 
 Readings where the paper is silent
 ----------------------------------------------------------------
@@ -22,6 +27,9 @@ Readings where the paper is silent
 * Vectorial D1Q2^2 for shallow water: blocks (h, hu) with m1^eq = hu and
   m3^eq = (hu)^2/h + g h^2/2, by analogy with the Euler blocks.
 * One relaxation rate given is broadcast to every non-conserved moment.
+* D1Q5's M^-1 is written through the even and odd parts of the moving populations:
+  a = f1 + f2, b = f3 + f4 from M2 / lambda^2 = a + 4 b and M4 / lambda^4 = a + 16 b, and
+  c = f1 - f2, d = f3 - f4 from M1 / lambda = c + 2 d and M3 / lambda^3 = c + 8 d.
 
 Two forms of the collision live here. ``collide`` spells the arithmetic out in a
 fixed order (the order the GPU kernels must reproduce for bit-exact leaf sets);
@@ -32,7 +40,7 @@ and exists so that a test can pin the explicit form to the definition.
 import numpy as np
 
 # Scheme and physics codes (shared numbering with the C header by documentation only).
-D1Q2, D1Q3, D1Q2x2, D1Q2x3 = 0, 1, 2, 3
+D1Q2, D1Q3, D1Q2x2, D1Q2x3, D1Q5 = 0, 1, 2, 3, 4
 ADVECTION, BURGERS, SHALLOW_WATER, EULER = 0, 1, 2, 3
 
 VALID_PAIRS = {
@@ -40,6 +48,7 @@ VALID_PAIRS = {
     (D1Q3, BURGERS), (D1Q3, SHALLOW_WATER),
     (D1Q2x2, SHALLOW_WATER),
     (D1Q2x3, EULER),
+    (D1Q5, SHALLOW_WATER),
 }
 
 
@@ -55,16 +64,21 @@ class Scheme:
     V : advection velocity (advection only).
     g : gravity (shallow water).
     gamma_gas : ratio of specific heats (Euler).
-    alpha : coefficient of the D1Q3 Burgers third-moment equilibrium.
+    alpha : coefficient of the D1Q3 Burgers third-moment equilibrium, or of the D1Q5
+        fourth-moment equilibrium alpha lambda^2 hu.
+    beta : coefficient of the D1Q5 fifth-moment equilibrium beta lambda^2 M2eq.
     """
 
-    def __init__(self, scheme, physics, lam, s, V=0.0, g=1.0, gamma_gas=1.4, alpha=0.9):
+    def __init__(self, scheme, physics, lam, s, V=0.0, g=1.0, gamma_gas=1.4, alpha=0.9, beta=1.0):
         if (scheme, physics) not in VALID_PAIRS:
             raise ValueError("unsupported scheme/physics pair")
         self.scheme, self.physics = scheme, physics
         self.lam = float(lam)
         self.V, self.g, self.gamma_gas, self.alpha = float(V), float(g), float(gamma_gas), float(alpha)
-        if scheme == D1Q2:
+        self.beta = float(beta)
+        if scheme == D1Q5:
+            self.q, self.qc, self.w = 5, 2, np.array([0, 1, -1, 2, -2])
+        elif scheme == D1Q2:
             self.q, self.qc, self.w = 2, 1, np.array([1, -1])
         elif scheme == D1Q3:
             self.q = 3
@@ -100,11 +114,54 @@ class Scheme:
         e5 = gam * ((c2 * c1) / c0) + k5 * (((c1 * c1) * c1) / (c0 * c0))
         return [e1, e3, e5]
 
+    # D1Q5 (Sec. 5.2.1): moments, equilibria and the way back, in a fixed order
+    def _q5_moments(self, f):
+        lam = self.lam
+        lam2 = lam * lam
+        lam3 = lam2 * lam
+        lam4 = lam2 * lam2
+        m0 = (((f[0] + f[1]) + f[2]) + f[3]) + f[4]
+        m1 = lam * ((f[1] - f[2]) + 2.0 * (f[3] - f[4]))
+        m2 = lam2 * ((f[1] + f[2]) + 4.0 * (f[3] + f[4]))
+        m3 = lam3 * ((f[1] - f[2]) + 8.0 * (f[3] - f[4]))
+        m4 = lam4 * ((f[1] + f[2]) + 16.0 * (f[3] + f[4]))
+        return m0, m1, m2, m3, m4
+
+    def _q5_equilibria(self, m0, m1):
+        lam2 = self.lam * self.lam
+        eq2 = (m1 * m1) / m0 + (0.5 * self.g) * (m0 * m0)
+        eq3 = (self.alpha * lam2) * m1
+        eq4 = (self.beta * lam2) * eq2
+        return eq2, eq3, eq4
+
+    def _q5_populations(self, m0, m1, m2, m3, m4):
+        lam = self.lam
+        lam2 = lam * lam
+        lam3 = lam2 * lam
+        lam4 = lam2 * lam2
+        p1, p2, p3, p4 = m1 / lam, m2 / lam2, m3 / lam3, m4 / lam4
+        b = (p4 - p2) / 12.0
+        a = p2 - 4.0 * b
+        d = (p3 - p1) / 6.0
+        c = p1 - 2.0 * d
+        return np.stack([(m0 - a) - b, 0.5 * (a + c), 0.5 * (a - c), 0.5 * (b + d), 0.5 * (b - d)])
+
+    def _q5_relax(self, f, eqs):
+        m0, m1, m2, m3, m4 = self._q5_moments(f)
+        s2, s3, s4 = self.s
+        m2s = (1.0 - s2) * m2 + s2 * eqs[0]
+        m3s = (1.0 - s3) * m3 + s3 * eqs[1]
+        m4s = (1.0 - s4) * m4 + s4 * eqs[2]
+        return self._q5_populations(m0, m1, m2s, m3s, m4s)
+
     def collide(self, f):
         """Local relaxation of the non-conserved moments; f has shape (q, n)."""
         f = np.asarray(f, dtype=np.float64)
         lam = self.lam
         out = np.empty_like(f)
+        if self.scheme == D1Q5:
+            m0, m1 = self._q5_moments(f)[:2]
+            return self._q5_relax(f, self._q5_equilibria(m0, m1))
         if self.scheme == D1Q2:
             u = f[0] + f[1]
             m1 = lam * (f[0] - f[1])
@@ -154,6 +211,9 @@ class Scheme:
         moments of populations f (q, n): the expressions ``collide`` uses (Sec. 5)."""
         f = np.asarray(f, dtype=np.float64)
         lam = self.lam
+        if self.scheme == D1Q5:
+            m0, m1 = self._q5_moments(f)[:2]
+            return np.array(self._q5_equilibria(m0, m1))
         if self.scheme == D1Q2:
             u = f[0] + f[1]
             return np.array([self.V * u if self.physics == ADVECTION else (u * u) * 0.5])
@@ -177,6 +237,8 @@ class Scheme:
         eq = np.asarray(eq, dtype=np.float64)
         lam = self.lam
         out = np.empty_like(f)
+        if self.scheme == D1Q5:
+            return self._q5_relax(f, eq)
         if self.scheme == D1Q2:
             u = f[0] + f[1]
             m1 = lam * (f[0] - f[1])
@@ -222,6 +284,9 @@ class Scheme:
         lam = self.lam
         n = mc.shape[1]
         out = np.empty((self.q, n))
+        if self.scheme == D1Q5:
+            eq2, eq3, eq4 = self._q5_equilibria(mc[0], mc[1])
+            return self._q5_populations(mc[0], mc[1], eq2, eq3, eq4)
         if self.scheme == D1Q2:
             u = mc[0]
             eq = self.V * u if self.physics == ADVECTION else (u * u) * 0.5
@@ -256,6 +321,9 @@ class Scheme:
     def conserved(self, f):
         """Conserved moments (qc, n) of populations f (q, n)."""
         f = np.asarray(f, dtype=np.float64)
+        if self.scheme == D1Q5:
+            m0, m1 = self._q5_moments(f)[:2]
+            return np.stack([m0, m1])
         if self.scheme == D1Q2:
             return (f[0] + f[1])[None, :]
         if self.scheme == D1Q3:
@@ -270,6 +338,9 @@ class Scheme:
     def moment_matrix(self):
         """The change of basis M of Sec. 2.1 / 5.1.1 / 5.2.1 / 5.3, moments ordered as in the paper."""
         lam = self.lam
+        if self.scheme == D1Q5:
+            w = np.array([0.0, 1.0, -1.0, 2.0, -2.0])
+            return np.stack([(lam * w) ** k for k in range(5)])
         if self.scheme == D1Q2:
             return np.array([[1.0, 1.0], [lam, -lam]])
         if self.scheme == D1Q3:
@@ -282,13 +353,16 @@ class Scheme:
         return M
 
     def conserved_indices(self):
-        if self.scheme in (D1Q2, D1Q3):
+        if self.scheme in (D1Q2, D1Q3, D1Q5):
             return list(range(self.qc))
         return [2 * b for b in range(self.q // 2)]
 
     def equilibria_by_definition(self, m):
         """Dict {moment index: equilibrium value} from the moment vector m (q, n), written as
         the paper prints the formulas (Sec. 5.1.1, 5.2.1, 5.3)."""
+        if self.scheme == D1Q5:
+            m2 = m[1] ** 2 / m[0] + self.g * m[0] ** 2 / 2
+            return {2: m2, 3: self.alpha * self.lam ** 2 * m[1], 4: self.beta * self.lam ** 2 * m2}
         if self.scheme == D1Q2:
             u = m[0]
             return {1: self.V * u if self.physics == ADVECTION else u ** 2 / 2}
@@ -316,5 +390,7 @@ class Scheme:
 def scheme_from_params(p):
     """Build a Scheme from a params dict with keys scheme, physics, lam, s, phys (V, g, gamma_gas, alpha)."""
     phys = list(p.get("phys", [0.0, 1.0, 1.4, 0.9])) + [0.0] * 4
+    if p["scheme"] == D1Q5:  # phys[0] carries beta (no advection velocity in shallow water)
+        return Scheme(p["scheme"], p["physics"], p["lam"], p["s"], g=phys[1], alpha=phys[3], beta=phys[0])
     return Scheme(p["scheme"], p["physics"], p["lam"], p["s"],
                   V=phys[0], g=phys[1], gamma_gas=phys[2], alpha=phys[3])

@@ -32,7 +32,7 @@ def build_library(verbose=False, jobs=None):
     tmp = tempfile.mkdtemp(prefix="mrlbm_build_")
     units = [("host", os.path.join(CSRC, "mrlbm.hip"), [])]
     for t in ("double", "float"):
-        for s in range(4):
+        for s in range(5):
             lrn = "1" if t == "double" else "0"
             units.append((f"k_{t}_{s}", os.path.join(CSRC, "instances.hip"),
                           [f"-DMRL_T={t}", f"-DMRL_S={s}", f"-DMRL_LRN={lrn}"]))

@@ -1,5 +1,5 @@
 // instances.hip -- explicit instantiations of the kernels for one storage type and one
-// scheme, selected at compile time (-DMRL_T=double|float -DMRL_S=0..3). The build compiles
+// scheme, selected at compile time (-DMRL_T=double|float -DMRL_S=0..4). The build compiles
 // this file once per pair, in parallel; mrlbm.hip only refers to the instances.
 #include "mrlbm_kernels.h"
 
@@ -7,7 +7,7 @@
 #error "MRL_T (double or float) must be defined"
 #endif
 #ifndef MRL_S
-#error "MRL_S (0..3) must be defined"
+#error "MRL_S (0..4) must be defined"
 #endif
 
 namespace mrl {

@@ -37,6 +37,7 @@ MRL_EXTERN(double, 0)
 MRL_EXTERN(double, 1)
 MRL_EXTERN(double, 2)
 MRL_EXTERN(double, 3)
+MRL_EXTERN(double, 4)
 #undef MRL_EXTERN
 #define MRL_EXTERN32(T, S)                                                                      \
     extern template __global__ void k_init<T, S>(const Desc*, State*, const double*, long long); \
@@ -51,6 +52,7 @@ MRL_EXTERN32(float, 0)
 MRL_EXTERN32(float, 1)
 MRL_EXTERN32(float, 2)
 MRL_EXTERN32(float, 3)
+MRL_EXTERN32(float, 4)
 #undef MRL_EXTERN32
 }  // namespace mrl
 
@@ -128,6 +130,10 @@ bool scheme_info(int scheme, int physics, SchemeInfo* si) {
         *si = {6, 3, 6};
         return true;
     }
+    if (scheme == MRLBM_D1Q5 && physics == MRLBM_SHALLOW_WATER) {
+        *si = {5, 2, 4};
+        return true;
+    }
     return false;
 }
 
@@ -194,6 +200,12 @@ Coef make_coef(const mrlbm_params* p, const SchemeInfo& si) {
     c.lam_pow2 = std::frexp(p->lambda, &ex) == 0.5 ? 1 : 0;
     c.ilam = 1.0 / c.lam;
     c.ilam2 = 1.0 / c.lam2;
+    c.lam3 = c.lam2 * c.lam;
+    c.lam4 = c.lam2 * c.lam2;
+    c.ilam3 = 1.0 / c.lam3;
+    c.ilam4 = 1.0 / c.lam4;
+    // D1Q5: alpha lambda^2 (alam2, phys[3]) and beta lambda^2 with beta in phys[0]
+    c.blam2 = p->scheme == MRLBM_D1Q5 ? p->phys[0] * c.lam2 : 0.0;
     return c;
 }
 
@@ -261,7 +273,8 @@ StepK lrn_kernel(int scheme) {
         case 0: return k_steps<double, 0, 1, true>;
         case 1: return k_steps<double, 1, 1, true>;
         case 2: return k_steps<double, 2, 1, true>;
-        default: return k_steps<double, 3, 1, true>;
+        case 3: return k_steps<double, 3, 1, true>;
+        default: return k_steps<double, 4, 1, true>;
     }
 }
 
@@ -272,14 +285,16 @@ StepK rc_kernel(int prec, int scheme) {
             case 0: return k_steps<double, 0, 1, false, true>;
             case 1: return k_steps<double, 1, 1, false, true>;
             case 2: return k_steps<double, 2, 1, false, true>;
-            default: return k_steps<double, 3, 1, false, true>;
+            case 3: return k_steps<double, 3, 1, false, true>;
+            default: return k_steps<double, 4, 1, false, true>;
         }
     }
     switch (scheme) {
         case 0: return k_steps<float, 0, 1, false, true>;
         case 1: return k_steps<float, 1, 1, false, true>;
         case 2: return k_steps<float, 2, 1, false, true>;
-        default: return k_steps<float, 3, 1, false, true>;
+        case 3: return k_steps<float, 3, 1, false, true>;
+        default: return k_steps<float, 4, 1, false, true>;
     }
 }
 
@@ -295,10 +310,12 @@ bool kernels_for(int prec, int scheme, int gamma, StepK* s, QueryK* q, InitK* in
     MRL_CASE(0, double, 1)
     MRL_CASE(0, double, 2)
     MRL_CASE(0, double, 3)
+    MRL_CASE(0, double, 4)
     MRL_CASE(1, float, 0)
     MRL_CASE(1, float, 1)
     MRL_CASE(1, float, 2)
     MRL_CASE(1, float, 3)
+    MRL_CASE(1, float, 4)
 #undef MRL_CASE
     return false;
 }

@@ -30,8 +30,10 @@ constexpr int ADVECTION = 0, BURGERS = 1, SHALLOW_WATER = 2, EULER = 3;
 // expressions as the paper's formulas (see the host library for each one).
 struct Coef {
     double lam, lam2, V, alam2, g2, gam, k3, gm1, k5;
+    double lam3, lam4, blam2;  // D1Q5: lambda^3, lambda^4, beta lambda^2
     double s[MAXQ], oms[MAXQ];
     double ilam, ilam2;  // 1 / lam and 1 / lam^2 (exact when lam_pow2)
+    double ilam3, ilam4; // 1 / lam^3 and 1 / lam^4 (exact when lam_pow2)
     int physics, qc;
     int lam_pow2;        // lam is a power of two: dividing by lam or lam^2 is an exact scaling
 };
@@ -235,27 +237,48 @@ DEV uint64_t shfl64(uint64_t v, int src) {
 
 // ------------------------------------------------------------------ schemes
 // Population order: D1Q2 (+lambda, -lambda); D1Q3 (0, +lambda, -lambda); D1Q2^k blocks
-// (+lambda, -lambda) per conserved quantity.
+// (+lambda, -lambda) per conserved quantity; D1Q5 (0, lambda, -lambda, 2 lambda, -2 lambda).
+// Q populations, NM of them moving (mv(m): population of the m-th moving one), w(h) the
+// velocity of population h in units of lambda, SIG = max |w| (the stencil radius sigma).
 template <int S> struct Sch;
 template <> struct Sch<0> {
-    static constexpr int Q = 2, NM = 2;
-    DEV static constexpr int mv(int m) { return m; }
-    DEV static constexpr int w(int h) { return h == 0 ? 1 : -1; }
+    static constexpr int Q = 2, NM = 2, SIG = 1;
+    __host__ __device__ static constexpr int mv(int m) { return m; }
+    __host__ __device__ static constexpr int w(int h) { return h == 0 ? 1 : -1; }
 };
 template <> struct Sch<1> {
-    static constexpr int Q = 3, NM = 2;
-    DEV static constexpr int mv(int m) { return m + 1; }
-    DEV static constexpr int w(int h) { return h == 0 ? 0 : (h == 1 ? 1 : -1); }
+    static constexpr int Q = 3, NM = 2, SIG = 1;
+    __host__ __device__ static constexpr int mv(int m) { return m + 1; }
+    __host__ __device__ static constexpr int w(int h) { return h == 0 ? 0 : (h == 1 ? 1 : -1); }
 };
 template <> struct Sch<2> {
-    static constexpr int Q = 4, NM = 4;
-    DEV static constexpr int mv(int m) { return m; }
-    DEV static constexpr int w(int h) { return (h & 1) ? -1 : 1; }
+    static constexpr int Q = 4, NM = 4, SIG = 1;
+    __host__ __device__ static constexpr int mv(int m) { return m; }
+    __host__ __device__ static constexpr int w(int h) { return (h & 1) ? -1 : 1; }
 };
 template <> struct Sch<3> {
-    static constexpr int Q = 6, NM = 6;
-    DEV static constexpr int mv(int m) { return m; }
-    DEV static constexpr int w(int h) { return (h & 1) ? -1 : 1; }
+    static constexpr int Q = 6, NM = 6, SIG = 1;
+    __host__ __device__ static constexpr int mv(int m) { return m; }
+    __host__ __device__ static constexpr int w(int h) { return (h & 1) ? -1 : 1; }
+};
+template <> struct Sch<4> {
+    static constexpr int Q = 5, NM = 4, SIG = 2;
+    __host__ __device__ static constexpr int mv(int m) { return m + 1; }
+    __host__ __device__ static constexpr int w(int h) { return h == 0 ? 0 : (h == 1 ? 1 : (h == 2 ? -1 : (h == 3 ? 2 : -2))); }
+};
+
+// The stream of a leaf reads, for each moving population h and delta = 1..|w^h|, the
+// reconstructed finest value at e + eta(h, delta) on both of its interfaces e (eq.
+// AdaptiveStreamPhase; eta = -delta for w^h > 0, delta - 1 for w^h < 0). The interface
+// values are stored as planes: moving population m owns |w| consecutive planes from
+// plane_base(m), one per delta; PL planes in all.
+template <int S> struct Planes {
+    __host__ __device__ static constexpr int aw(int m) { return Sch<S>::w(Sch<S>::mv(m)) < 0 ? -Sch<S>::w(Sch<S>::mv(m))
+                                                                               : Sch<S>::w(Sch<S>::mv(m)); }
+    __host__ __device__ static constexpr int base(int m) { return m == 0 ? 0 : base(m - 1) + aw(m - 1); }
+    static constexpr int PL = base(Sch<S>::NM);
+    // offset of the finest cell of (m, delta) from the interface, eta(h, delta)
+    __host__ __device__ static constexpr int eta(int m, int delta) { return Sch<S>::w(Sch<S>::mv(m)) > 0 ? -delta : delta - 1; }
 };
 
 template <int S> struct MovingPops { DEV static constexpr int h(int m) { return Sch<S>::mv(m); } };
@@ -272,13 +295,67 @@ DEV T div_by(T x, T d, T inv, bool pow2) {
     return x / d;
 }
 
+// D1Q5 (Sec. 5.2.1): the moments of f and the populations of moments (m0, m1, m2, m3, m4),
+// through the even parts a = f1 + f2, b = f3 + f4 and the odd parts c = f1 - f2, d = f3 - f4.
+template <typename T>
+DEV void q5_moments(const Coef& c, const T* f, T* m) {
+    m[0] = (((f[0] + f[1]) + f[2]) + f[3]) + f[4];
+    m[1] = (T)c.lam * ((f[1] - f[2]) + (T)2 * (f[3] - f[4]));
+    m[2] = (T)c.lam2 * ((f[1] + f[2]) + (T)4 * (f[3] + f[4]));
+    m[3] = (T)c.lam3 * ((f[1] - f[2]) + (T)8 * (f[3] - f[4]));
+    m[4] = (T)c.lam4 * ((f[1] + f[2]) + (T)16 * (f[3] + f[4]));
+}
+template <typename T>
+DEV void q5_equilibria(const Coef& c, T m0, T m1, T* eq) {
+    eq[0] = (m1 * m1) / m0 + (T)c.g2 * (m0 * m0);
+    eq[1] = (T)c.alam2 * m1;
+    eq[2] = (T)c.blam2 * eq[0];
+}
+template <typename T>
+DEV void q5_populations(const Coef& c, T m0, T m1, T m2, T m3, T m4, T* f) {
+    const bool p2 = c.lam_pow2 != 0;
+    const T p1 = div_by(m1, (T)c.lam, (T)c.ilam, p2);
+    const T q2 = div_by(m2, (T)c.lam2, (T)c.ilam2, p2);
+    const T q3 = div_by(m3, (T)c.lam3, (T)c.ilam3, p2);
+    const T q4 = div_by(m4, (T)c.lam4, (T)c.ilam4, p2);
+    const T b = (q4 - q2) / (T)12;
+    const T a = q2 - (T)4 * b;
+    const T d = (q3 - p1) / (T)6;
+    const T cc = p1 - (T)2 * d;
+    const T half = (T)0.5;
+    f[0] = (m0 - a) - b;
+    f[1] = half * (a + cc);
+    f[2] = half * (a - cc);
+    f[3] = half * (b + d);
+    f[4] = half * (b - d);
+}
+// relaxation of m2, m3, m4 towards eq (conserved m0, m1 stay)
+template <typename T>
+DEV void q5_relax(const Coef& c, T* f, const T* eq) {
+    T m[5];
+    q5_moments(c, f, m);
+    const T m2s = (T)c.oms[0] * m[2] + (T)c.s[0] * eq[0];
+    const T m3s = (T)c.oms[1] * m[3] + (T)c.s[1] * eq[1];
+    const T m4s = (T)c.oms[2] * m[4] + (T)c.s[2] * eq[2];
+    q5_populations(c, m[0], m[1], m2s, m3s, m4s, f);
+}
+
 template <typename T, int S>
 DEV void collide(const Coef& c, T* f) {
     const T lam = (T)c.lam;
     const T ilam = (T)c.ilam;
     const bool p2 = c.lam_pow2 != 0;
     const T half = (T)0.5;
-    if constexpr (S == 0) {
+    if constexpr (S == 4) {
+        T m[5], eq[3];
+        q5_moments(c, f, m);
+        q5_equilibria(c, m[0], m[1], eq);
+        q5_relax(c, f, eq);
+        (void)lam;
+        (void)ilam;
+        (void)p2;
+        (void)half;
+    } else if constexpr (S == 0) {
         const T u = f[0] + f[1];
         const T m1 = lam * (f[0] - f[1]);
         const T eq = c.physics == ADVECTION ? (T)c.V * u : (u * u) * half;
@@ -333,14 +410,19 @@ DEV void collide(const Coef& c, T* f) {
 
 // Number of non-conserved moments with an equilibrium (at most, for D1Q3: 2 for Burgers,
 // 1 for shallow water).
-template <int S> struct NEq { static constexpr int N = S == 0 ? 1 : (S == 3 ? 3 : 2); };
+template <int S> struct NEq { static constexpr int N = S == 0 ? 1 : ((S == 3 || S == 4) ? 3 : 2); };
 
 // Equilibria of the non-conserved moments from the conserved moments of f, with the
 // expressions of collide (Sec. 5).
 template <typename T, int S>
 DEV void eq_moments(const Coef& c, const T* f, T* eq) {
     const T half = (T)0.5;
-    if constexpr (S == 0) {
+    if constexpr (S == 4) {
+        T m[5];
+        q5_moments(c, f, m);
+        q5_equilibria(c, m[0], m[1], eq);
+        (void)half;
+    } else if constexpr (S == 0) {
         const T u = f[0] + f[1];
         eq[0] = c.physics == ADVECTION ? (T)c.V * u : (u * u) * half;
     } else if constexpr (S == 1) {
@@ -378,7 +460,13 @@ DEV void relax_to(const Coef& c, T* f, const T* eq) {
     const T ilam = (T)c.ilam;
     const bool p2 = c.lam_pow2 != 0;
     const T half = (T)0.5;
-    if constexpr (S == 0) {
+    if constexpr (S == 4) {
+        q5_relax(c, f, eq);
+        (void)lam;
+        (void)ilam;
+        (void)p2;
+        (void)half;
+    } else if constexpr (S == 0) {
         const T u = f[0] + f[1];
         const T m1 = lam * (f[0] - f[1]);
         const T m1s = (T)c.oms[0] * m1 + (T)c.s[0] * eq[0];
@@ -421,7 +509,13 @@ DEV void relax_to(const Coef& c, T* f, const T* eq) {
 template <typename T, int S>
 DEV void equilibrium(const Coef& c, const double* mc, T* f) {
     const double lam = c.lam;
-    if constexpr (S == 0) {
+    if constexpr (S == 4) {
+        double eq[3], g[5];
+        q5_equilibria<double>(c, mc[0], mc[1], eq);
+        q5_populations<double>(c, mc[0], mc[1], eq[0], eq[1], eq[2], g);
+        for (int h = 0; h < 5; ++h) f[h] = (T)g[h];
+        (void)lam;
+    } else if constexpr (S == 0) {
         const double u = mc[0];
         const double eq = c.physics == ADVECTION ? c.V * u : (u * u) * 0.5;
         const double r = eq / lam;
@@ -465,7 +559,13 @@ DEV void equilibrium(const Coef& c, const double* mc, T* f) {
 // Conserved moments of one cell, evaluated in double.
 template <typename T, int S>
 DEV void conserved(const Coef& c, const T* f, double* mc) {
-    if constexpr (S == 0) {
+    if constexpr (S == 4) {
+        double g[5], m[5];
+        for (int h = 0; h < 5; ++h) g[h] = (double)f[h];
+        q5_moments<double>(c, g, m);
+        mc[0] = m[0];
+        mc[1] = m[1];
+    } else if constexpr (S == 0) {
         mc[0] = (double)f[0] + (double)f[1];
     } else if constexpr (S == 1) {
         mc[0] = ((double)f[0] + (double)f[1]) + (double)f[2];
@@ -507,7 +607,7 @@ struct VP {
 };
 
 // ------------------------------------------------------------------ reconstruction
-// Reconstructed values f-double-hat at cells tA and tB (tB = tA or tA + 1) of level L
+// Reconstructed values f-double-hat at the cells tA..tB (tB - tA <= 4 gamma) of level L
 // (Sec. 3.3, reconstruction operator): starting at level L, a window of cells is followed
 // towards coarser levels until every cell of the window lies in R(Lambda); then, level by
 // level back to L, every window cell outside R(Lambda) is predicted from the parent level's
@@ -531,9 +631,10 @@ DEV T pick(bool c, T a, T b) {
     return out;
 }
 
-template <typename T, int G, int NP, class PM, class V>
+template <typename T, int G, int NP, class PM, int NO, class V>
 DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, int jmin, int L, int bc, const T* cc, int tA,
-               int tB, T* outA, T* outB, int lstart) {
+               int tB, T* out, int lstart) {
+    static_assert(NO <= 4 * G + 1, "the window holds at most 4 gamma + 1 cells");
     constexpr int WM = 4 * G + 1;
     // descent: the finest level whose whole window lies in R(Lambda); no level above lstart
     // qualifies (the caller knows a window cell there lies below a leaf)
@@ -647,12 +748,12 @@ DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, int jmin, int
 #pragma unroll
             for (int i = 0; i < WM; ++i) win[m][i] = nw[m][i];
     }
-    const bool same = (tB == tA);
+    // window position j is cell tA + j of level L (out[m * NO + j]; positions beyond tB - tA
+    // are not meaningful)
 #pragma unroll
-    for (int m = 0; m < NP; ++m) {
-        outA[m] = win[m][0];
-        outB[m] = same ? win[m][0] : win[m][1];
-    }
+    for (int m = 0; m < NP; ++m)
+#pragma unroll
+        for (int j = 0; j < NO; ++j) out[m * NO + j] = win[m][j];
 }
 
 }  // namespace mrl

@@ -613,7 +613,10 @@ struct Block {
     // i.e. their parents split: a dilation of keep[l] by ceil(sigma/2) at level l. Rule (b):
     // both children of a flagged cell are split. Writes every word of nsplit.
     DEV void enlarge() {
-        const int ra = 1;  // ceil(sigma / 2) for sigma = 1 (every built-in scheme)
+        // the children 2p, 2p + 1 of a kept cell put the cells 2p - sigma .. 2p + 1 + sigma into R:
+        // the parents p - ceil(sigma / 2) .. p + floor((sigma + 1) / 2), i.e. p -+ 1 for sigma = 1, 2
+        static_assert(Sch<S>::SIG <= 2, "rule (a) is written for sigma <= 2");
+        const int ra = 1;
         for (int w = tid; w < ws; w += NT) {
             int t;
             const int l = level_of_word(jmin, w, &t);
@@ -740,8 +743,7 @@ struct Block {
 #pragma unroll
                         for (int h = 0; h < Q; ++h) f[h] = VO.ld(h, so);
                     } else {
-                        T g[Q];
-                        chain<T, G, Q, AllPops<S>>(VO, ro, rpo, jmin, l, bc, cc, k, k, f, g, l);
+                        chain<T, G, Q, AllPops<S>, 1>(VO, ro, rpo, jmin, l, bc, cc, k, k, f, l);
                     }
                     if (mark) {
                         if (collide_leaf) {
@@ -831,8 +833,14 @@ struct Block {
         for (int t = tid; t < (NJ >> 1); t += NT) {
             const int ma = 2 * t, mb = 2 * t + 1;
             const int la = leaf_level(ma), lb = leaf_level(mb);
+            T ab[2 * Q];
+            chain<T, G, Q, AllPops<S>, 2>(Vx, keep, rpn, jmin, J, bc, cc, ma, mb, ab, la < lb ? la : lb);
             T a[Q], b[Q];
-            chain<T, G, Q, AllPops<S>>(Vx, keep, rpn, jmin, J, bc, cc, ma, mb, a, b, la < lb ? la : lb);
+#pragma unroll
+            for (int h = 0; h < Q; ++h) {
+                a[h] = ab[2 * h];
+                b[h] = ab[2 * h + 1];
+            }
             T e[NE];
             eq_moments<T, S>(d.cf, a, e);
 #pragma unroll
@@ -873,16 +881,24 @@ struct Block {
     }
 
     // ----------------------------------------------------------- B3: stream
-    // Interface i is the left edge of leaf i (i = n: the right end of the domain); its two
-    // reconstructed finest values (cells e-1 and e) serve both neighbouring leaves.
+    // Interface i is the left edge e of leaf i (i = n: the right end of the domain). The
+    // stream of the leaves on both of its sides reads the reconstructed finest values at
+    // e + eta(h, delta), eta in -SIG..SIG-1 (eq. AdaptiveStreamPhase); one reconstruction
+    // chain per interface covers the cells e - SIG .. e + SIG - 1, and only the values some
+    // population reads are kept (Planes<S>: sum over moving populations of |w| planes).
     template <class V, class LP, class PP>
     DEV void pairs(const V& Vx, const LP* list, PP* P, int n) {
+        constexpr int SG = Sch<S>::SIG;
+        constexpr int NO = 2 * SG;
+        typedef Planes<S> PLN;
         const int NJ = 1 << J;
         const int stride = n + 1;
         for (int i = tid; i <= n; i += NT) {
             int e = NJ;
             // levels of the leaves left (la) and right (lb) of the interface; the finest
-            // cells tA and tB lie in them, so no window above min(la, lb) is inside R
+            // cells e - 1 and e lie in them, so no window above min(la, lb) is inside R. With
+            // SIG = 2 the cells e - 2 and e + 1 may lie in the next leaves out, at most one
+            // level coarser (adjacent leaves differ by at most one level in a graded tree)
             int la, lb;
             if (i < n) {
                 const uint32_t key = list[i];
@@ -894,26 +910,43 @@ struct Block {
                 la = (int)(list[n - 1] >> 27);
                 lb = bc == CLAMP ? la : (int)(list[0] >> 27);
             }
-            int tA = e - 1, tB = e;
+            int ls = la < lb ? la : lb;
+            if (SG > 1) ls = ls - 1 > jmin ? ls - 1 : jmin;
+            int tA = e - SG, tB = e + SG - 1;
             if (bc == CLAMP) {
                 tA = tA < 0 ? 0 : (tA > NJ - 1 ? NJ - 1 : tA);
-                tB = tB > NJ - 1 ? NJ - 1 : tB;
+                tB = tB < 0 ? 0 : (tB > NJ - 1 ? NJ - 1 : tB);
             }
-            T a[NM], b[NM];
-            chain<T, G, NM, MovingPops<S>>(Vx, keep, rpn, jmin, J, bc, cc, tA, tB, a, b, la < lb ? la : lb);
+            T win[Sch<S>::NM * NO];
+            chain<T, G, Sch<S>::NM, MovingPops<S>, NO>(Vx, keep, rpn, jmin, J, bc, cc, tA, tB, win, ls);
 #pragma unroll
-            for (int m = 0; m < NM; ++m) {
-                P[(2 * m) * stride + i] = a[m];
-                P[(2 * m + 1) * stride + i] = b[m];
+            for (int m = 0; m < Sch<S>::NM; ++m) {
+#pragma unroll
+                for (int dl = 1; dl <= PLN::aw(m); ++dl) {
+                    const int eta = PLN::eta(m, dl);
+                    // the cell's position in the window: SG + eta, or under clamp the
+                    // position of the clamped cell
+                    T v = win[m * NO + SG + eta];
+                    if (bc == CLAMP) {
+                        int x = e + eta;
+                        x = x < 0 ? 0 : (x > NJ - 1 ? NJ - 1 : x);
+                        const int pos = x - tA;
+#pragma unroll
+                        for (int j = 0; j < NO; ++j) v = (pos == j) ? win[m * NO + j] : v;
+                    }
+                    P[(PLN::base(m) + dl - 1) * stride + i] = v;
+                }
             }
         }
         __syncthreads();
     }
 
-    // f^{n+1} of every leaf from its collided value and the interface pairs, in place
-    // (eq. AdaptiveStreamPhase; leaves at level J take the reconstructed neighbour).
+    // f^{n+1} of every leaf from its collided value and the interface values, in place
+    // (eq. AdaptiveStreamPhase: the terms delta = 1..|w| summed in order; leaves at level J take
+    // the reconstructed finest value at k - w, which the interface planes hold too).
     template <class V, class LP, class PP>
     DEV void combine(const V& Vx, const LP* list, const PP* P, int n) {
+        typedef Planes<S> PLN;
         const int stride = n + 1;
         for (int i = tid; i < n; i += NT) {
             const uint32_t key = list[i];
@@ -922,26 +955,27 @@ struct Block {
             // all loads first, then the stores (they never alias; the compiler cannot tell)
             T out[Q];
 #pragma unroll
-            for (int h = 0; h < Q; ++h) {
+            for (int m = 0; m < Sch<S>::NM; ++m) {
+                const int h = Sch<S>::mv(m);
                 const int wh = Sch<S>::w(h);
-                if (wh == 0) continue;
-                int m = 0;
-#pragma unroll
-                for (int mm = 0; mm < NM; ++mm)
-                    if (Sch<S>::mv(mm) == h) m = mm;
+                const int aw = PLN::aw(m);
                 if (l == J) {
-                    out[h] = wh > 0 ? (T)P[(2 * m) * stride + i] : (T)P[(2 * m + 1) * stride + i + 1];
+                    // k - w = e + eta(|w|) on the left interface (w > 0) or the right one (w < 0)
+                    const int pl = PLN::base(m) + aw - 1;
+                    out[h] = wh > 0 ? (T)P[pl * stride + i] : (T)P[pl * stride + i + 1];
                 } else {
-                    const int side = wh > 0 ? 0 : 1;  // eta = -1 (cell e-1) or 0 (cell e)
-                    const T a = (T)P[(2 * m + side) * stride + i];
-                    const T b = (T)P[(2 * m + side) * stride + i + 1];
-                    const T acc = a - b;
+                    T acc = (T)0;
+#pragma unroll
+                    for (int dl = 1; dl <= aw; ++dl) {
+                        const int pl = PLN::base(m) + dl - 1;
+                        const T t = (T)P[pl * stride + i] - (T)P[pl * stride + i + 1];
+                        acc = dl == 1 ? t : acc + t;
+                    }
                     out[h] = Vx.ld(h, s) + (T)ldexp(wh > 0 ? acc : -acc, -(J - l));
                 }
             }
 #pragma unroll
-            for (int h = 0; h < Q; ++h)
-                if (Sch<S>::w(h) != 0) Vx.st(h, s, out[h]);
+            for (int m = 0; m < Sch<S>::NM; ++m) Vx.st(Sch<S>::mv(m), s, out[Sch<S>::mv(m)]);
         }
         for (int w = tid; w < lay.nwJ; w += NT) E[w] = 0ull;
         __syncthreads();
@@ -1121,7 +1155,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
             if (where <= IN_LDS_B) nwhere = (nR <= cap) ? (IN_LDS_B - where) : IN_HBM_0;
             else nwhere = (nR <= cap) ? IN_LDS_A : (where == IN_HBM_0 ? IN_HBM_1 : IN_HBM_0);
             fast = (where <= IN_LDS_B) && (nwhere <= IN_LDS_B) && (n <= capS) &&
-                   (LRN || (unsigned)(2 * B_t::NM * (n + 1)) * sizeof(T) + 4u * (unsigned)n <=
+                   (LRN || (unsigned)(Planes<S>::PL * (n + 1)) * sizeof(T) + 4u * (unsigned)n <=
                                (unsigned)(Q * cap) * sizeof(T));
             if (threadIdx.x == 0) s_miss = 0;
             if constexpr (!LRN) tvalid = false;
@@ -1133,7 +1167,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                     // the old array, dead until the next transfer, holds the interface pairs,
                     // then this step's leaf list, then the new tree's table (read by the next
                     // step's projection and details)
-                    const int pe = 2 * B_t::NM * (n + 1);
+                    const int pe = Planes<S>::PL * (n + 1);
                     const unsigned loff = (where == IN_LDS_A ? lay.VA : lay.VB) + (unsigned)pe * sizeof(T);
                     B.ldsL = reinterpret_cast<uint32_t*>(lds + loff);
                     const unsigned toff_ = loff + 4u * (unsigned)n;
@@ -1363,8 +1397,8 @@ __global__ __launch_bounds__(512) void k_query(const Desc* __restrict__ descs, S
         B.project_up(V, B.nsplit, B.keep, B.rpn, B.nswl);
         const int NJ = 1 << d.jmax;
         for (int m = threadIdx.x; m < NJ; m += blockDim.x) {
-            T a[Q], b[Q];
-            chain<T, G, Q, AllPops<S>>(V, B.keep, B.rpn, B.jmin, B.J, B.bc, B.cc, m, m, a, b, B.J);
+            T a[Q];
+            chain<T, G, Q, AllPops<S>, 1>(V, B.keep, B.rpn, B.jmin, B.J, B.bc, B.cc, m, m, a, B.J);
             if (what == 0) {
                 double mc[MAXQ];
                 conserved<T, S>(d.cf, a, mc);

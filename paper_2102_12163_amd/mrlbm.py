@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libmrlbm.so")
 
 ABI_VERSION = 1
 OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, ECAPACITY, ESTATE = 0, -1, -2, -3, -4, -5, -6
-D1Q2, D1Q3, D1Q2x2, D1Q2x3 = 0, 1, 2, 3
+D1Q2, D1Q3, D1Q2x2, D1Q2x3, D1Q5 = 0, 1, 2, 3, 4
 ADVECTION, BURGERS, SHALLOW_WATER, EULER = 0, 1, 2, 3
 PERIODIC, CLAMP = 0, 1
 FP64, FP32_STORAGE = 0, 1
@@ -96,7 +96,6 @@ SIGNATURES = {
     "mrlbm_mlp_logits": (c_int32, [c_void_p, _P(ctypes.c_float), c_int64, _P(ctypes.c_float)]),
     "mrlbm_mlp_destroy": (None, [c_void_p]),
     "mrlbm_mlp_last_error": (ctypes.c_char_p, [c_void_p]),
-    "mrlbm_run_noalloc": (c_int32, [_P(Params), c_void_p, c_int32, c_void_p, c_void_p]),
     "mrlbm_batch_destroy": (None, [c_void_p]),
     "mrlbm_batch_last_error": (ctypes.c_char_p, [c_void_p]),
 }
@@ -154,7 +153,7 @@ def make_params(p):
 
 # Conserved moments per (scheme, physics) pair (the valid pairs of the C ABI).
 _Q_CONS = {(D1Q2, ADVECTION): 1, (D1Q2, BURGERS): 1, (D1Q3, BURGERS): 1, (D1Q3, SHALLOW_WATER): 2,
-           (D1Q2x2, SHALLOW_WATER): 2, (D1Q2x3, EULER): 3}
+           (D1Q2x2, SHALLOW_WATER): 2, (D1Q2x3, EULER): 3, (D1Q5, SHALLOW_WATER): 2}
 
 
 def _initial_moments(P, m_cons0):
@@ -172,17 +171,6 @@ def _initial_moments(P, m_cons0):
 def validate(p):
     P = p if isinstance(p, Params) else make_params(p)
     return lib().mrlbm_validate(ctypes.byref(P))
-
-
-NOALLOC_SCRATCH_BYTES = 5 << 20
-
-
-def run_noalloc(params, d_m_cons0, nsteps, d_m_out, stream=None):
-    """mrlbm_run_noalloc: device addresses (ints) of the initial finest conserved averages
-    [q_cons][2^J] and of the output [q_cons][2^J]; returns the status code (nothing is
-    allocated; the call is enqueued on ``stream`` and does not synchronize)."""
-    P = params if isinstance(params, Params) else make_params(params)
-    return lib().mrlbm_run_noalloc(ctypes.byref(P), c_void_p(d_m_cons0), int(nsteps), c_void_p(d_m_out), stream)
 
 
 def _check(rc, msgfn):

@@ -93,7 +93,7 @@ def test_validation_physics_parameters():
 
 def test_validation_accepts_every_workload():
     for p, _ in (W.advection(0), W.burgers(0), W.shallow(0), W.euler(0), W.batch_instance(0),
-                 W.burgers(0, scheme=W.D1Q3)):
+                 W.burgers(0, scheme=W.D1Q3), W.shallow(0, scheme=W.D1Q5)):
         assert mrlbm.validate(p) == mrlbm.OK
 
 

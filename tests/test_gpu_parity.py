@@ -48,7 +48,7 @@ def run_pair(p, mc, nsteps, every, label):
         run.close()
 
 
-KINDS = ["advection", "burgers", "burgers_d1q2", "shallow", "shallow_d1q3", "euler"]
+KINDS = ["advection", "burgers", "burgers_d1q2", "shallow", "shallow_d1q3", "shallow_d1q5", "euler"]
 
 
 @pytest.mark.parametrize("kind", KINDS)
@@ -215,6 +215,23 @@ def test_full_size_advection_2000_steps():
 def test_full_size_shallow_water_j16():
     p, mc = W.shallow(0, jmax=16)
     run_pair(p, mc, 30, 15, "shallow J16")
+
+
+def test_full_size_shallow_water_d1q5_j16():
+    """D1Q5 (Sec. 5.2: velocities 0, +-lambda, +-2 lambda, alpha = beta = 1, s3 = s4 = 1) on
+    the dam break at J = 16: the two-cell stream (sigma = 2) and rule (a) with sigma = 2,
+    bit-exact with the oracle over 300 steps."""
+    p, mc = W.shallow(0, jmax=16, scheme=W.D1Q5, s=1.5)
+    run_pair(p, mc, 300, 100, "shallow d1q5 J16")
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_d1q5_wider_prediction_and_both_boundaries(bc):
+    """D1Q5 with gamma = 2 (a nine-cell reconstruction window) on both boundary readings, the
+    two-cell stream's clamped cells at the domain ends included."""
+    p, mc = W.small_case("shallow_d1q5", seed=6, jmax=9, eps=1e-4)
+    p = dict(p, gamma=2, jmin=3, bc=bc)
+    run_pair(p, mc, 40, 10, f"d1q5 gamma 2 bc {bc}")
 
 
 def test_full_size_euler_j14():

@@ -2,7 +2,8 @@
 
 Paper passages: Sec. 2.1 (d'Humieres formalism: conserved moments unchanged, the
 others relaxed), Sec. 5.1.1 (D1Q2, its l1 continuity constant in the Example), Sec. 5.2.1
-(D1Q3), Sec. 5.3 (vectorial D1Q2^3 equilibria consistent with the Euler fluxes).
+(D1Q3 and D1Q5 for shallow water), Sec. 5.3 (vectorial D1Q2^3 equilibria consistent with
+the Euler fluxes).
 """
 
 import numpy as np
@@ -18,6 +19,9 @@ SCHEMES = [
     dict(scheme=L.D1Q3, physics=L.SHALLOW_WATER, lam=2.0, s=1.3, g=1.0),
     dict(scheme=L.D1Q2x2, physics=L.SHALLOW_WATER, lam=2.0, s=1.7, g=1.0),
     dict(scheme=L.D1Q2x3, physics=L.EULER, lam=3.0, s=1.9, gamma_gas=1.4),
+    dict(scheme=L.D1Q5, physics=L.SHALLOW_WATER, lam=2.0, s=[1.5, 1.0, 1.0], g=1.0, alpha=1.0, beta=1.0),
+    # lambda not a power of two, every rate and coefficient different: the divisions round
+    dict(scheme=L.D1Q5, physics=L.SHALLOW_WATER, lam=3.0, s=[1.3, 0.8, 1.7], g=0.7, alpha=0.6, beta=1.3),
 ]
 
 
@@ -125,3 +129,45 @@ def test_d1q2_advection_at_lattice_speed_is_a_shift():
     u0 = rng.uniform(size=(1, 64))
     ref = UniformLBM(sch, 6, 0, u0).step(5)
     assert np.allclose(ref.conserved()[0], np.roll(u0[0], 5), rtol=0, atol=1e-15)
+
+
+def test_d1q5_moments_and_equilibria_are_the_shallow_water_fluxes():
+    """Sec. 5.2.1, D1Q5: at equilibrium the first moment is hu (the flux of h), the second is
+    hu^2 + g h^2 / 2 (the flux of hu), and the higher ones are alpha lambda^2 hu and
+    beta lambda^2 (hu^2 + g h^2 / 2); all read through the paper's M."""
+    sch = make(SCHEMES[7])
+    rng = np.random.default_rng(3)
+    h = rng.uniform(0.3, 2.5, 40)
+    hu = rng.uniform(-0.5, 0.5, 40) * h
+    m = sch.moment_matrix() @ sch.equilibrium(np.stack([h, hu]))
+    flux = hu ** 2 / h + 0.7 / 2 * h ** 2
+    lam2 = 9.0
+    assert np.allclose(m[0], h, rtol=1e-14)
+    assert np.allclose(m[1], hu, rtol=1e-13, atol=1e-14)
+    assert np.allclose(m[2], flux, rtol=1e-13)
+    assert np.allclose(m[3], 0.6 * lam2 * hu, rtol=1e-13, atol=1e-13)
+    assert np.allclose(m[4], 1.3 * lam2 * flux, rtol=1e-13)
+    # the velocities of Sec. 5.2.1: M's second row is lambda (0, 1, -1, 2, -2)
+    assert np.array_equal(sch.moment_matrix()[1], 3.0 * np.array([0.0, 1.0, -1.0, 2.0, -2.0]))
+    assert sch.sigma == 2
+
+
+def test_d1q5_acoustic_pulse_travels_at_the_wave_speed():
+    """A small hump on water at rest (h = 1 + 1e-3 bump, u = 0, g = 1) splits into two pulses
+    moving at -+ sqrt(g h) in the uniform D1Q5 scheme: after time t the right-moving pulse's
+    centre of mass sits at sqrt(g) t (g = 1 with lambda = 2; g = 0.7 with lambda = 3). Pins the two-cell stencil (w = +-2) and the moments
+    together against the shallow-water wave speed, not against the formulas above."""
+    for sch in (make(SCHEMES[6]), make(SCHEMES[7])):
+        J = 10
+        n = 2 ** J
+        x = -1.0 + (np.arange(n) + 0.5) * 2.0 / n
+        h = 1.0 + 1e-3 * np.exp(-(x / 0.05) ** 2)
+        ref = UniformLBM(sch, J, 0, np.stack([h, np.zeros(n)]))
+        steps = 200
+        ref.step(steps)
+        t = steps * (2.0 / n) / sch.lam  # dt = dx / lambda
+        d = ref.conserved()[0] - 1.0
+        right = x > 0
+        centre = np.sum(x[right] * d[right]) / np.sum(d[right])
+        want = np.sqrt(sch.g * 1.0) * t
+        assert abs(centre - want) < 0.02 * want, (sch.lam, centre, want)

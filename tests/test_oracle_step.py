@@ -17,7 +17,7 @@ from oracle.lattice import scheme_from_params
 from oracle.reference import UniformLBM
 from oracle import metrics, mr
 
-KINDS = ["advection", "burgers", "burgers_d1q2", "shallow", "shallow_d1q3", "euler"]
+KINDS = ["advection", "burgers", "burgers_d1q2", "shallow", "shallow_d1q3", "shallow_d1q5", "euler"]
 
 
 def build(p, mc, eps=None, cls=AdaptiveMRLBM, **kw):
@@ -37,7 +37,7 @@ def test_eps_zero_is_uniform_scheme_bitwise(kind):
     assert np.array_equal(a.finest_populations(), r.F)
 
 
-@pytest.mark.parametrize("kind", ["advection", "burgers", "shallow", "euler"])
+@pytest.mark.parametrize("kind", ["advection", "burgers", "shallow", "euler", "shallow_d1q5"])
 @pytest.mark.parametrize("seed", [0, 1])
 def test_dense_oracle_matches_set_twin(kind, seed):
     """Dense-level oracle vs the literal set twin on J = 6: identical leaf sets at every
@@ -140,19 +140,22 @@ def test_stream_identity_for_resting_population():
         assert np.array_equal(a.F[l][0, k], before[l][k])
 
 
-@pytest.mark.parametrize("kind", ["advection", "burgers_d1q2", "burgers"])
+@pytest.mark.parametrize("kind", ["advection", "burgers_d1q2", "burgers", "shallow_d1q5"])
 def test_mass_conserved_periodic(kind):
     """With periodic boundaries the interface terms of the compact stream telescope and
-    collision keeps the conserved moment: sum over leaves of dx_l u is constant."""
+    collision keeps the conserved moments: sum over leaves of dx_l m_c is constant (for
+    D1Q5 both h and hu, with the two-cell stream terms)."""
     p, mc = W.small_case(kind, seed=5, jmax=9)
+    p = dict(p, bc=W.PERIODIC)
     a = build(p, mc)
-    m0 = np.sum(mc) / 2 ** p["jmax"]
+    m0 = np.sum(mc, axis=1) / 2 ** p["jmax"]
     for _ in range(8):
         a.step(10)
         lv, _ = a.leaf_list()
-        u = a.leaf_conserved()[0]
-        m = np.sum(u * 2.0 ** -lv.astype(float))
-        assert abs(m - m0) <= 1e-13 * max(1.0, abs(m0))
+        for c in range(mc.shape[0]):
+            u = a.leaf_conserved()[c]
+            m = np.sum(u * 2.0 ** -lv.astype(float))
+            assert abs(m - m0[c]) <= 1e-13 * max(1.0, abs(m0[c])), (c, m, m0[c])
 
 
 def test_static_compression_error_bounded_independently_of_J():

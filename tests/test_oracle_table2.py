@@ -6,11 +6,20 @@ Column I (advection of a Gaussian) has a closed-form exact solution and no rule-
 shock sensitivity, so it is the column compared here. The paper leaves the boundary
 treatment, the sampling of the initial datum and the rounding of T / dt unstated; the
 readings below are clamp boundaries (the datum vanishes near x = +-3), cell averages and
-N = round(T / dt); the ratios move by less than 3 % across those choices. What the test
-pins is the dependence on the relaxation rate s (each ratio normalised by the one at
-s = 0.75, within 15 % of the printed column) and the level of the ratios, which sits at
-1.8-2.0 times the printed values at every s (an open discrepancy of the absolute level:
-delta / eps is 1.3-1.6 here, so the printed ratios imply about twice that)."""
+N = round(T / dt).
+
+What the paper fixes, and this test pins:
+* the dependence on the relaxation rate s: each ratio normalised by the one at s = 0.75
+  follows the printed column within 15 % (printed 99.7 -> 8.34, a factor 12 over s);
+* the order of magnitude the text states for test I (the perturbation error 10 to 100
+  times below the reference error): every ratio within a factor 10 of the printed one.
+The absolute level is an open gap, not pinned: the oracle's ratios sit at 1.8-1.95 times
+the printed ones at every s (delta / eps is 1.3-1.6 here where the printed ratios imply
+about twice that). The alternative readings of the setup move the level by less than 5 %
+(mu_bar = infinity as 30 or as "no rule (b)"; an initial compression T_eps then G of the
+datum; one more adaptation at the final time; N rounded up or down; point-sampled data;
+periodic boundaries), and the changes that do move it do so by other factors and are not
+readings of the text (thresholds doubled: 0.66 times printed; rule (a) dropped: 0.13)."""
 
 import math
 import os
@@ -62,8 +71,9 @@ def test_table2_column_I():
         ratio, d_over_eps = got[s]
         # the perturbation error stays of the order of eps (Sec. 4.4 error estimate)
         assert 0.5 < d_over_eps < 3.0, (s, d_over_eps)
-        # absolute level: 1.8-2.0 x the printed ratio (see the module docstring)
-        assert 1.5 < ratio / printed[s] < 2.5, (s, ratio, printed[s])
+        # order of magnitude (the text: delta 10 to 100 times below E for test I); the level
+        # itself is an open gap (module docstring)
+        assert 0.1 < ratio / printed[s] < 10.0, (s, ratio, printed[s])
         # dependence on s: normalised by s = 0.75, within 15 % of the printed column
         ours = ratio / got[ss[0]][0]
         paper = printed[s] / printed[ss[0]]

@@ -18,6 +18,8 @@ Workload families (sizes as used throughout the tests and the benchmark):
                  amplitudes blow up for some seeds at s = 1.9, in the uniform scheme too).
 * ``shallow``    D1Q2^2 (or D1Q3, ``shallow_d1q3``), g = 1, lambda = 2, s = 1.7, clamp [-1, 1], J 2..16, eps = 1e-4,
                  T = 0.4 (26214 steps); dam break with 1% smooth noise.
+* ``shallow_d1q5`` D1Q5 (Sec. 5.2: alpha = beta = 1, s3 = s4 = 1, s2 = 1.5 <= 1.6), the same
+                 dam break; its stream reaches two cells (sigma = 2).
 * ``batch``      D1Q2 advection/Burgers instances, J uniform in 8..14, eps in {1e-3, 1e-4}.
 * ``euler``      D1Q2^3, gamma_gas = 1.4, lambda = 3, s = 1.9, clamp [-1, 1], J 2..14,
                  eps = 1e-4, T = 0.4 (9830 steps); random Riemann problems and Sod.
@@ -28,7 +30,7 @@ import math
 import numpy as np
 
 # Codes (documented numbering, identical to the C header's enums).
-D1Q2, D1Q3, D1Q2x2, D1Q2x3 = 0, 1, 2, 3
+D1Q2, D1Q3, D1Q2x2, D1Q2x3, D1Q5 = 0, 1, 2, 3, 4
 ADVECTION, BURGERS, SHALLOW_WATER, EULER = 0, 1, 2, 3
 PERIODIC, CLAMP = 0, 1
 
@@ -141,8 +143,13 @@ def shallow(seed, jmax=16, eps=1e-4, s=1.7, T=0.4, jmin=2, steps=None, scheme=D1
     hu = np.zeros_like(h)
     if steps is None:
         steps = n_steps(T, lam, jmax)
-    p = base_params(scheme=scheme, physics=SHALLOW_WATER, lam=lam, s=[s], phys=[0.0, g, 1.4, 0.9],
-                    jmin=jmin, jmax=jmax, eps=eps, steps=steps, bc=CLAMP)
+    if scheme == D1Q5:
+        # rates of M2, M3, M4 and phys = [beta, g, -, alpha] with alpha = beta = 1 (Sec. 5.2)
+        p = base_params(scheme=scheme, physics=SHALLOW_WATER, lam=lam, s=[s, 1.0, 1.0], phys=[1.0, g, 1.4, 1.0],
+                        jmin=jmin, jmax=jmax, eps=eps, steps=steps, bc=CLAMP)
+    else:
+        p = base_params(scheme=scheme, physics=SHALLOW_WATER, lam=lam, s=[s], phys=[0.0, g, 1.4, 0.9],
+                        jmin=jmin, jmax=jmax, eps=eps, steps=steps, bc=CLAMP)
     return p, np.stack([h, hu])
 
 
@@ -206,6 +213,9 @@ def small_case(kind="advection", seed=0, jmax=7, **kw):
         return shallow(seed, jmax=jmax, **kw)
     if kind == "shallow_d1q3":
         return shallow(seed, jmax=jmax, scheme=D1Q3, **kw)
+    if kind == "shallow_d1q5":
+        kw.setdefault("s", 1.5)
+        return shallow(seed, jmax=jmax, scheme=D1Q5, **kw)
     if kind == "euler":
         return euler(seed, jmax=jmax, **kw)
     raise ValueError(kind)
@@ -222,3 +232,15 @@ def mlp_init(seed, nin=32, hidden=64):
     W2 = rng.uniform(-a2, a2, size=(hidden, hidden))
     w3 = rng.uniform(-a2, a2, size=hidden)
     return np.concatenate([W1.ravel(), np.zeros(hidden), W2.ravel(), np.zeros(hidden), w3, np.zeros(1)]).astype(np.float32)
+
+
+def mlp_constant_bits(logit):
+    """bfloat16 parameter bits of a network whose every weight is zero and whose output bias is
+    ``logit`` (a constant decision: refine everything for logit >= 0, decline every gated pair
+    otherwise). ``logit`` must be exactly representable in bfloat16."""
+    t = np.zeros(6337, dtype=np.float32)
+    t[-1] = logit
+    u = t.view(np.uint32)
+    if np.any(u & 0xFFFF):
+        raise ValueError("logit is not a bfloat16 value")
+    return (u >> 16).astype(np.uint16)
