@@ -248,8 +248,14 @@ def euler_batch(seeds, jmax, eps, steps):
 
 def test_trained_predictor_against_the_plain_method():
     """Train on the rule-(b) samples of 8 Riemann problems (J = 14, eps = 1e-4), deploy on 8
-    others; report leaf-cell updates, misses, redos and the error against the plain method.
-    The judge bounds the error: it must stay at the plain method's level."""
+    others; report leaf-cell updates, misses, redos and the error against the plain method
+    and against the ideal predictor under this judge. The judge accepts a decline only when
+    the pair's detail after the step stays below the rule-(b) threshold; a network that
+    declines every gated pair is brought by the redos to exactly the accepted declines, so its
+    leaf-update gain bounds what any network can save. Asserted: the judge holds the error at
+    the plain method's level, the trained network saves no more than that bound (up to the
+    spread between trajectories), and the bound itself is small on this workload (the
+    measured reason why the predictor cannot pay for its inference and judge)."""
     J, eps, steps = 14, 1e-4, 2400
     announce("trained predictor J", J, "steps", steps)
     ps, ms = euler_batch(range(100, 108), J, eps, steps)
@@ -271,11 +277,12 @@ def test_trained_predictor_against_the_plain_method():
     print("training loss", loss)
     ps, ms = euler_batch(range(200, 208), J, eps, steps)
     out = {}
-    for name, mode in (("plain", mrlbm.PRED_OFF), ("learned", mrlbm.PRED_LEARNED)):
+    nets = {"learned": bits, "ideal": constant_bits(-1.0)}
+    for name, mode in (("plain", mrlbm.PRED_OFF), ("learned", mrlbm.PRED_LEARNED), ("ideal", mrlbm.PRED_LEARNED)):
         b = mrlbm.Batch(ps, ms)
         try:
             if mode != mrlbm.PRED_OFF:
-                b.set_predictor(bits, mode)
+                b.set_predictor(nets[name], mode)
             ms_run = b.step_timed(steps)
             sts = [b.stats(i) for i in range(len(ps))]
             out[name] = dict(ms=ms_run, upd=sum(s["leaf_updates"] for s in sts), misses=sum(s["misses"] for s in sts),
@@ -291,10 +298,15 @@ def test_trained_predictor_against_the_plain_method():
     for name in out:
         d = [metrics.delta(fin_ref[i], out[name]["fin"][i], -1, 1) for i in range(len(ps))]
         out[name]["delta_over_eps"] = float(np.max(d)) / eps
-    pl, le = out["plain"], out["learned"]
+    pl, le, ib = out["plain"], out["learned"], out["ideal"]
+    gain, bound = 1.0 - le["upd"] / pl["upd"], 1.0 - ib["upd"] / pl["upd"]
     print("plain: updates", pl["upd"], "ms", pl["ms"], "delta/eps", pl["delta_over_eps"])
     print("learned: updates", le["upd"], "ms", le["ms"], "delta/eps", le["delta_over_eps"], "misses", le["misses"],
           "redos", le["redos"])
-    print("leaf-update gain", 1.0 - le["upd"] / pl["upd"], "time ratio", le["ms"] / pl["ms"])
-    assert le["delta_over_eps"] <= 1.5 * pl["delta_over_eps"] + 1e-9
-    assert le["upd"] <= pl["upd"] * 1.01
+    print("ideal: updates", ib["upd"], "ms", ib["ms"], "delta/eps", ib["delta_over_eps"], "misses", ib["misses"],
+          "redos", ib["redos"])
+    print("leaf-update gain", gain, "ideal bound", bound, "time ratio", le["ms"] / pl["ms"])
+    for r in (le, ib):
+        assert r["delta_over_eps"] <= 1.5 * pl["delta_over_eps"] + 1e-9
+    assert gain <= max(bound, 0.0) + 2e-3, (gain, bound)
+    assert bound < 0.02, bound
