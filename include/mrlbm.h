@@ -270,6 +270,31 @@ int mrlbm_mlp_logits(mrlbm_mlp_t m, const float* X, int64_t n, float* logits);
 void mrlbm_mlp_destroy(mrlbm_mlp_t m);
 const char* mrlbm_mlp_last_error(mrlbm_mlp_t m);
 
+/* ---------------------------------------------------------------- allocation-free run
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. One run is set up from p and the finest-level
+ * conserved averages d_m_cons0 (a DEVICE array [q_cons][2^j_max], read only), advanced by
+ * nsteps >= 0 full steps, and its conserved moments reconstructed on the finest level are
+ * written to d_m_out (a DEVICE array [q_cons][2^j_max], owned by the caller): the same bits as
+ * mrlbm_create + mrlbm_step(nsteps) + mrlbm_moments(MRLBM_FINEST) on the same data.
+ *
+ * Nothing is allocated. The run's state (values, tree, leaf list, interface pairs, descriptor)
+ * lives in a file-scope device array of MRLBM_NOALLOC_SCRATCH_BYTES bytes that every GPU the
+ * library runs on holds until the process ends; its address on a device is looked up once,
+ * at the first call with that device current. Every call on one GPU shares that array and
+ * overwrites it (it is cleared by a fill kernel at the start of each call): calls that overlap
+ * on one GPU (different streams or host threads) race, and the caller must order them.
+ *
+ * Enqueued on hip_stream (NULL: the null stream); returns without synchronizing. Errors:
+ * MRLBM_EINVAL for an invalid parameter set (mrlbm_validate), nsteps < 0 or a NULL pointer;
+ * MRLBM_ECAPACITY when the run's state exceeds the scratch array (for FP64 that is J <= 14 with
+ * six populations, J <= 15 with two); MRLBM_EDEVICE on a HIP error. The device input is not
+ * checked for NaN: a NaN met in a step propagates into d_m_out. No message is kept
+ * (mrlbm_last_error is not updated). */
+#define MRLBM_NOALLOC_SCRATCH_BYTES (5u << 20)
+int mrlbm_run_noalloc(const mrlbm_params* p, const double* d_m_cons0, int32_t nsteps, double* d_m_out,
+                      void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -709,6 +710,137 @@ int engine_step_timed(Engine* e, int nsteps, bool graph, double* ms) {
     return check_numeric(e);
 }
 
+// ---------------------------------------------------------------- allocation-free run
+// The state of the run of mrlbm_run_noalloc: one file-scope device array per GPU. In host code
+// its name is a host-side stand-in; the device address comes from hipGetSymbolAddress, looked
+// up once per device and kept in scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[MRLBM_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+unsigned char* scratch_ptr[kMaxDevices];
+
+// Device address of this device's scratch array (the device must be current), or null.
+unsigned char* scratch_for(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+    }
+    return scratch_ptr[dev];
+}
+
+// Zero fill of n 16-byte words (a kernel rather than a memset node, so that the call can be
+// captured in a graph).
+__global__ void k_zero16(uint4* p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// The run's descriptor, passed by value, written into the scratch array.
+__global__ void k_put_desc(Desc d, Desc* dst) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *dst = d;
+}
+
+// On-chip capacity of a single run (the arithmetic of choose_capacity for one run).
+void single_capacity(const Desc& d, int tsz, size_t budget, int* cap, int* capS, size_t* lds, size_t* lds_query) {
+    const int cg = (1 << (d.jmax + 1)) - (1 << d.jmin);
+    auto total = [&](int c) {
+        const int cs = c > 0 ? c / 2 + (1 << d.jmin) : 0;
+        return (size_t)make_layout(d.jmin, d.jmax, c, cs, d.q, d.nm, tsz, false).total;
+    };
+    int lo = 0, hi = cg;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (total(mid) <= budget) lo = mid;
+        else hi = mid - 1;
+    }
+    *cap = lo;
+    *capS = lo > 0 ? lo / 2 + (1 << d.jmin) : 0;
+    *lds = total(lo);
+    *lds_query = (size_t)make_layout(d.jmin, d.jmax, 0, 0, d.q, d.nm, tsz).total;
+}
+
+int run_noalloc(const mrlbm_params* p, const double* d_m0, int32_t nsteps, double* d_out, void* stream_) {
+    if (!p || !d_m0 || !d_out || nsteps < 0) return MRLBM_EINVAL;
+    const int vr = validate(p, nullptr);
+    if (vr != MRLBM_OK) return vr;
+    SchemeInfo si;
+    scheme_info(p->scheme, p->physics, &si);
+    StepK sk;
+    QueryK qk;
+    InitK ik;
+    if (!kernels_for(p->precision, p->scheme, p->gamma, &sk, &qk, &ik)) return MRLBM_EINVAL;
+    const bool recon = (p->flags & MRLBM_FLAG_RECONSTRUCTED_COLLISION) != 0;
+    if (recon) sk = rc_kernel(p->precision, p->scheme);
+    const size_t tsz = p->precision == MRLBM_FP64 ? 8 : 4;
+    // layout of the scratch array: descriptor, state, then the pool of one run as in create
+    const size_t NJ = (size_t)1 << p->j_max;
+    const size_t vals = (size_t)si.q * (((size_t)1 << (p->j_max + 1)) - ((size_t)1 << p->j_min));
+    size_t off = 0;
+    const size_t o_desc = off;
+    off = align256(off + sizeof(Desc));
+    const size_t o_state = off;
+    off = align256(off + sizeof(State));
+    const size_t o_va = off;
+    off = align256(off + vals * tsz);
+    const size_t o_vb = off;
+    off = align256(off + vals * tsz);
+    const size_t o_split = off;
+    off = align256(off + (size_t)std::max(1, wbase(p->j_min, p->j_max)) * 8);
+    const size_t o_list = off;
+    off = align256(off + NJ * 4);
+    const size_t o_pairs = off;
+    off = align256(off + 2 * (size_t)si.nm * (NJ + 1) * tsz);
+    if (off > (size_t)MRLBM_NOALLOC_SCRATCH_BYTES) return MRLBM_ECAPACITY;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MRLBM_EDEVICE;
+    unsigned char* base = scratch_for(dev);
+    if (!base) return MRLBM_EDEVICE;
+    Desc d;
+    memset(&d, 0, sizeof(d));
+    d.jmin = p->j_min;
+    d.jmax = p->j_max;
+    d.gamma = p->gamma;
+    d.mu_bar = p->mu_bar;
+    d.bc = p->bc;
+    d.q = si.q;
+    d.qc = si.qc;
+    d.nm = si.nm;
+    d.recon = recon ? 1 : 0;
+    d.eps = p->eps;
+    pred_coeffs(p->gamma, d.c);
+    d.cf = make_coef(p, si);
+    d.va = base + o_va;
+    d.vb = base + o_vb;
+    d.split = reinterpret_cast<uint64_t*>(base + o_split);
+    d.list = reinterpret_cast<uint32_t*>(base + o_list);
+    d.pairs = base + o_pairs;
+    Desc* dd = reinterpret_cast<Desc*>(base + o_desc);
+    State* ds = reinterpret_cast<State*>(base + o_state);
+    int maxlds = 65536;
+    (void)hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    int cap = 0, capS = 0;
+    size_t lds = 0, lds_query = 0;
+    single_capacity(d, (int)tsz, (size_t)std::max(0, maxlds - 1024), &cap, &capS, &lds, &lds_query);
+    if (hipFuncSetAttribute((const void*)sk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
+        hipFuncSetAttribute((const void*)qk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_query) != hipSuccess)
+        return MRLBM_EDEVICE;
+    hipStream_t stream = (hipStream_t)stream_;
+    const int nt = default_block(p->j_max);
+    const size_t n16 = off / 16;
+    hipLaunchKernelGGL(k_zero16, dim3((unsigned)std::min<size_t>((n16 + 255) / 256, 1024)), dim3(256), 0, stream,
+                       reinterpret_cast<uint4*>(base), n16);
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, stream, d, dd);
+    hipLaunchKernelGGL(ik, dim3((unsigned)((NJ + 255) / 256)), dim3(256), 0, stream, (const Desc*)dd, ds, d_m0, 0LL);
+    if (nsteps > 0)
+        hipLaunchKernelGGL(sk, dim3(1), dim3(nt), lds, stream, (const Desc*)dd, ds, (const int*)nullptr, (int)nsteps,
+                           (int)(MODE_ADAPT | MODE_SCHEME), cap, capS);
+    hipLaunchKernelGGL(qk, dim3(1), dim3(nt), lds_query, stream, (const Desc*)dd, ds, (int)MRLBM_FINEST, 0, d_out);
+    return hipGetLastError() == hipSuccess ? MRLBM_OK : MRLBM_EDEVICE;
+}
+
 }  // namespace
 
 struct mrlbm_s {
@@ -1202,6 +1334,11 @@ int mrlbm_batch_get_block(mrlbm_batch_t b, int32_t* threads) {
     if (!b || !threads) return MRLBM_EINVAL;
     *threads = b->e->nt_user ? b->e->nt_user : b->e->nt;
     return MRLBM_OK;
+}
+
+int mrlbm_run_noalloc(const mrlbm_params* p, const double* d_m_cons0, int32_t nsteps, double* d_m_out,
+                      void* hip_stream) {
+    return run_noalloc(p, d_m_cons0, nsteps, d_m_out, hip_stream);
 }
 
 void mrlbm_batch_destroy(mrlbm_batch_t b) {

@@ -96,6 +96,7 @@ SIGNATURES = {
     "mrlbm_mlp_logits": (c_int32, [c_void_p, _P(ctypes.c_float), c_int64, _P(ctypes.c_float)]),
     "mrlbm_mlp_destroy": (None, [c_void_p]),
     "mrlbm_mlp_last_error": (ctypes.c_char_p, [c_void_p]),
+    "mrlbm_run_noalloc": (c_int32, [_P(Params), c_void_p, c_int32, c_void_p, c_void_p]),
     "mrlbm_batch_destroy": (None, [c_void_p]),
     "mrlbm_batch_last_error": (ctypes.c_char_p, [c_void_p]),
 }
@@ -171,6 +172,17 @@ def _initial_moments(P, m_cons0):
 def validate(p):
     P = p if isinstance(p, Params) else make_params(p)
     return lib().mrlbm_validate(ctypes.byref(P))
+
+
+NOALLOC_SCRATCH_BYTES = 5 << 20
+
+
+def run_noalloc(params, d_m_cons0, nsteps, d_m_out, stream=None):
+    """mrlbm_run_noalloc: device addresses (ints) of the initial finest conserved averages
+    [q_cons][2^J] and of the output [q_cons][2^J]; returns the status code (nothing is
+    allocated; the call is enqueued on ``stream`` and does not synchronize)."""
+    P = params if isinstance(params, Params) else make_params(params)
+    return lib().mrlbm_run_noalloc(ctypes.byref(P), c_void_p(d_m_cons0), int(nsteps), c_void_p(d_m_out), stream)
 
 
 def _check(rc, msgfn):
