@@ -218,6 +218,22 @@ int mrlbm_batch_set_launch_steps(mrlbm_batch_t b, int32_t steps);
 int mrlbm_batch_checkpoint(mrlbm_batch_t b);
 int mrlbm_batch_restore(mrlbm_batch_t b);
 int mrlbm_batch_get_capacity(mrlbm_batch_t b, int32_t* cells);
+/* Launch classes. A launch gives every workgroup the LDS its largest run needs, so in a batch
+ * of uneven J the small runs hold more LDS than they use and fewer of them share a compute unit.
+ * With n classes (1..4) the runs are split by j_max: class c holds the runs with
+ * j_upper[c-1] < j_max <= j_upper[c] (j_upper increasing, the last one >= the largest j_max);
+ * each class is advanced by a grid of its own with threads[c] per workgroup (64..512, a multiple
+ * of 64) and the on-chip capacity that lets runs_per_cu[c] (1..8) of its workgroups share a
+ * compute unit's LDS. The class grids are forked from the handle's stream onto a second stream
+ * of the same priority and joined back (in one captured graph), so they run side by side; within
+ * a class the runs go heaviest first (mrlbm_batch_set_schedule then reorders within each class).
+ * Results do not depend on the classes. n = 0 restores the single launch; mrlbm_batch_tune clears
+ * the classes (it tunes a single launch); not available with the refinement predictor
+ * (MRLBM_EINVAL either way). get_classes returns the number of classes in *n and, for cap_n >= *n,
+ * the runs and the on-chip capacity of each class. */
+int mrlbm_batch_set_classes(mrlbm_batch_t b, int32_t n, const int32_t* j_upper, const int32_t* threads,
+                            const int32_t* runs_per_cu);
+int mrlbm_batch_get_classes(mrlbm_batch_t b, int32_t cap_n, int32_t* n, int32_t* counts, int32_t* cells);
 void mrlbm_batch_destroy(mrlbm_batch_t b);
 const char* mrlbm_batch_last_error(mrlbm_batch_t b);
 
@@ -269,6 +285,50 @@ int mrlbm_mlp_params(mrlbm_mlp_t m, float* theta, uint16_t* bf16);
 int mrlbm_mlp_logits(mrlbm_mlp_t m, const float* X, int64_t n, float* logits);
 void mrlbm_mlp_destroy(mrlbm_mlp_t m);
 const char* mrlbm_mlp_last_error(mrlbm_mlp_t m);
+
+/* ---------------------------------------------------------------- two dimensions
+ * The multi-dimensional extension the paper outlines in its conclusion (dimension d = 2): a
+ * quadtree of dyadic squares J_min..J on [0, 1]^2, projection as the mean over the four children,
+ * the tensor product of the centered prediction (Sec. 3.1) with four details per parent, level
+ * thresholds eps_l = 2^{d (l - J)} eps (Sec. 3.4 as the conclusion modifies it), enlargement rule
+ * (a) on sigma-boxes and rule (b) at 2^{mu_bar + d} eps_l (Sec. 4.2), grading on gamma-boxes
+ * (Sec. 3.3), the leaves collision (Sec. 4.5) and the compact stream (Sec. 4.3.2), for each leaf
+ * and velocity the difference of the strips of reconstructed values entering and leaving it.
+ * The scheme is D2Q4 for u_t + phi_x(u)_x + phi_y(u)_y = 0 (velocities lambda (+-1, 0),
+ * (0, +-1); moments u, m1 = lambda (f0 - f1), m2 = lambda (f2 - f3), m3 = lambda^2 (f0 + f1 - f2 - f3);
+ * equilibria phi_x(u), phi_y(u), 0 with phi = (Vx u, Vy u) for advection, (u^2/2, u^2/2) for
+ * Burgers): the paper leaves multi-D schemes to a companion work. Levels are held densely in
+ * device memory (one kernel per phase and level); J <= 12. Conventions of the 1D handle apply
+ * (status codes, host validation, caller-owned host buffers, calls ordered on the stream). */
+typedef struct {
+    int32_t abi_version; /* MRLBM_ABI_VERSION                                   */
+    int32_t physics;     /* MRLBM_ADVECTION or MRLBM_BURGERS                     */
+    int32_t bc;          /* MRLBM_PERIODIC or MRLBM_CLAMP, in both directions    */
+    int32_t gamma;       /* prediction half-width 1..3                           */
+    double lambda;       /* lattice velocity > 0                                 */
+    double s[3];         /* relaxation rates of m1, m2, m3, in (0, 2]            */
+    double V[2];         /* advection velocity (advection only)                  */
+    int32_t j_min, j_max;/* 1 <= j_min <= j_max <= 12                            */
+    int32_t mu_bar;      /* regularity guess of rule (b), 0..30                  */
+    int32_t reserved;
+    double eps;          /* threshold eps >= 0                                   */
+} mrlbm2d_params;
+typedef struct mrlbm2d_s* mrlbm2d_t;
+int mrlbm2d_validate(const mrlbm2d_params* p);
+/* u0: host array [2^J][2^J] (index i * 2^J + j, i along x) of finest cell averages at t = 0;
+ * populations at equilibrium on the full tree. */
+int mrlbm2d_create(const mrlbm2d_params* p, const double* u0, void* hip_stream, mrlbm2d_t* out);
+/* nsteps time steps (adaptation, leaves collision, compact stream); synchronizes once per step to
+ * count the leaves. */
+int mrlbm2d_step(mrlbm2d_t h, int32_t nsteps);
+/* u reconstructed on every finest cell, out[i * 2^J + j] (cap >= 4^J). */
+int mrlbm2d_moments(mrlbm2d_t h, double* out, int64_t cap);
+/* split flags of level j_min <= level < j_max, out[i * 2^level + j] (cap >= 4^level). */
+int mrlbm2d_split(mrlbm2d_t h, int32_t level, uint8_t* out, int64_t cap);
+/* time steps taken, complete leaves of the current tree, sum over steps of the leaves. */
+int mrlbm2d_stats(mrlbm2d_t h, int64_t* steps, int64_t* leaves, int64_t* leaf_updates);
+void mrlbm2d_destroy(mrlbm2d_t h);
+const char* mrlbm2d_last_error(mrlbm2d_t h);
 
 /* ---------------------------------------------------------------- allocation-free run
  * For callers that cannot allocate device memory: code under HIP graph capture, tight serving

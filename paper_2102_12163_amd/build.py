@@ -1,8 +1,9 @@
 """Build step of the HIP library (hipcc, gfx950).
 
-The kernels are compiled once per (storage type, scheme) from ``csrc/instances.hip`` and
-the host side from ``csrc/mrlbm.hip``, as separate objects compiled in parallel, then
-linked into ``libmrlbm.so`` next to this file.
+The kernels are compiled once per (storage type, scheme) from ``csrc/instances.hip``, the
+host side from ``csrc/mrlbm.hip``, the network's kernels from ``csrc/mlp.hip`` and the
+two-dimensional step from ``csrc/mrlbm2d.hip``, as separate objects compiled in parallel,
+then linked into ``libmrlbm.so`` next to this file.
 """
 
 import os
@@ -37,6 +38,7 @@ def build_library(verbose=False, jobs=None):
             units.append((f"k_{t}_{s}", os.path.join(CSRC, "instances.hip"),
                           [f"-DMRL_T={t}", f"-DMRL_S={s}", f"-DMRL_LRN={lrn}"]))
     units.append(("mlp", os.path.join(CSRC, "mlp.hip"), []))
+    units.append(("md2", os.path.join(CSRC, "mrlbm2d.hip"), []))
     jobs = jobs or min(len(units), os.cpu_count() or 4)
     procs, objs, failed = [], [], []
     pending = list(units)

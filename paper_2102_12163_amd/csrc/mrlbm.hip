@@ -94,6 +94,16 @@ struct Engine {
     hipGraphExec_t gexec = nullptr;
     int gsteps = -1, gnt = -1, gcap = -1;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // launch classes (empty: one launch for the whole batch); class c advances the runs
+    // d_sched[first, first + count) with its own workgroup size and on-chip capacity
+    struct LaunchClass {
+        int first = 0, count = 0, jhi = 0, nt = 512, per_cu = 1, cap = 0, capS = 0;
+        size_t lds = 0;
+    };
+    std::vector<LaunchClass> cls;
+    int cls_gen = 0, gcls = -1;           // generation of the class set (graph cache key)
+    hipStream_t side = nullptr;           // second stream: class launches run side by side
+    hipEvent_t evf = nullptr, evj = nullptr;
     // refinement predictor
     bool lrn = false;             // launch the predictor-capable kernels
     bool any_recon = false;       // some run uses the reconstructed collision
@@ -338,6 +348,9 @@ void engine_free(Engine* e) {
     if (e->graph) (void)hipGraphDestroy(e->graph);
     if (e->ev0) (void)hipEventDestroy(e->ev0);
     if (e->ev1) (void)hipEventDestroy(e->ev1);
+    if (e->evf) (void)hipEventDestroy(e->evf);
+    if (e->evj) (void)hipEventDestroy(e->evj);
+    if (e->side) (void)hipStreamDestroy(e->side);
     if (e->stage) (void)hipFree(e->stage);
     if (e->d_mlp) (void)hipFree(e->d_mlp);
     if (e->d_samples) (void)hipFree(e->d_samples);
@@ -522,6 +535,25 @@ int check_numeric(Engine* e) { return e->numeric ? MRLBM_ENUMERIC : MRLBM_OK; }
 
 static int launch_once(Engine* e, int nsteps, int mode, bool use_graph);
 
+// The class launches of one step call: forked from the handle's stream to the side stream and
+// joined back, so that classes run side by side (also inside a captured graph).
+static int launch_classes(Engine* e, StepK sk, int nsteps, int mode) {
+    hipError_t st;
+    if ((st = hipEventRecord(e->evf, e->stream)) != hipSuccess) return hip_fail(e, st, "hipEventRecord(fork)");
+    if ((st = hipStreamWaitEvent(e->side, e->evf, 0)) != hipSuccess) return hip_fail(e, st, "hipStreamWaitEvent(fork)");
+    int k = 0;
+    for (const auto& c : e->cls) {
+        if (c.count == 0) continue;
+        hipStream_t s = (k++ % 2 == 0) ? e->stream : e->side;
+        hipLaunchKernelGGL(sk, dim3(c.count), dim3(c.nt), c.lds, s, (const Desc*)e->dd, e->ds,
+                           (const int*)(e->d_sched + c.first), nsteps, mode, c.cap, c.capS);
+        if ((st = hipGetLastError()) != hipSuccess) return hip_fail(e, st, "class launch");
+    }
+    if ((st = hipEventRecord(e->evj, e->side)) != hipSuccess) return hip_fail(e, st, "hipEventRecord(join)");
+    if ((st = hipStreamWaitEvent(e->stream, e->evj, 0)) != hipSuccess) return hip_fail(e, st, "hipStreamWaitEvent(join)");
+    return MRLBM_OK;
+}
+
 // Graph of one launch of nsteps full steps in the current launch shape, captured once and
 // kept until the step count, the block size or the capacity changes.
 static int prepare_graph(Engine* e, int nsteps) {
@@ -532,7 +564,8 @@ static int prepare_graph(Engine* e, int nsteps) {
     if (e->lrn) sk = lrn_kernel(e->scheme);
     else if (e->any_recon) sk = rc_kernel(e->prec, e->scheme);
     const int nt = e->nt_user ? e->nt_user : e->nt;
-    if (e->gexec && e->gsteps == nsteps && e->gnt == nt && e->gcap == e->cap) return MRLBM_OK;
+    const int gc = e->cls.empty() ? -1 : e->cls_gen;
+    if (e->gexec && e->gsteps == nsteps && e->gnt == nt && e->gcap == e->cap && e->gcls == gc) return MRLBM_OK;
     if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
     if (e->graph) (void)hipGraphDestroy(e->graph);
     e->gexec = nullptr;
@@ -540,8 +573,18 @@ static int prepare_graph(Engine* e, int nsteps) {
     hipError_t st;
     if ((st = hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
         return hip_fail(e, st, "hipStreamBeginCapture");
-    hipLaunchKernelGGL(sk, dim3(e->n), dim3(nt), e->lds, e->stream, (const Desc*)e->dd, e->ds, (const int*)e->d_sched,
-                       nsteps, MODE_ADAPT | MODE_SCHEME, e->cap, e->capS);
+    if (e->cls.empty()) {
+        hipLaunchKernelGGL(sk, dim3(e->n), dim3(nt), e->lds, e->stream, (const Desc*)e->dd, e->ds,
+                           (const int*)e->d_sched, nsteps, MODE_ADAPT | MODE_SCHEME, e->cap, e->capS);
+    } else {
+        const int rc = launch_classes(e, sk, nsteps, MODE_ADAPT | MODE_SCHEME);
+        if (rc != MRLBM_OK) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(e->stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+    }
     st = hipStreamEndCapture(e->stream, &e->graph);
     if (st != hipSuccess) return hip_fail(e, st, "hipStreamEndCapture");
     if ((st = hipGraphInstantiate(&e->gexec, e->graph, nullptr, nullptr, 0)) != hipSuccess)
@@ -549,6 +592,7 @@ static int prepare_graph(Engine* e, int nsteps) {
     e->gsteps = nsteps;
     e->gnt = nt;
     e->gcap = e->cap;
+    e->gcls = gc;
     return MRLBM_OK;
 }
 
@@ -581,6 +625,7 @@ static int launch_once(Engine* e, int nsteps, int mode, bool use_graph) {
         if ((st = hipGraphLaunch(e->gexec, e->stream)) != hipSuccess) return hip_fail(e, st, "hipGraphLaunch");
         return MRLBM_OK;
     }
+    if (!e->cls.empty()) return launch_classes(e, sk, nsteps, mode);
     hipLaunchKernelGGL(sk, dim3(e->n), dim3(nt), e->lds, e->stream, (const Desc*)e->dd, e->ds, (const int*)e->d_sched,
                        nsteps, mode, e->cap,
                        e->capS);
@@ -1037,7 +1082,32 @@ static int set_schedule(Engine* e, int stride) {
     std::vector<long long> cost(e->n);
     for (int r = 0; r < e->n; ++r) cost[idx[r]] = e->n - r;
     std::vector<int> perm;
-    make_schedule(stride, cost, perm);
+    if (e->cls.empty()) {
+        make_schedule(stride, cost, perm);
+    } else {
+        // each class's segment: its runs, scheduled with the stride among themselves
+        std::vector<int> members, sub;
+        std::vector<long long> subcost;
+        int jlo = -1;
+        for (auto& c : e->cls) {
+            members.clear();
+            subcost.clear();
+            for (int i = 0; i < e->n; ++i)
+                if (e->P[i].j_max > jlo && e->P[i].j_max <= c.jhi) {
+                    members.push_back(i);
+                    subcost.push_back(cost[i]);
+                }
+            c.first = (int)perm.size();
+            c.count = (int)members.size();
+            make_schedule(stride, subcost, sub);
+            for (int v : sub) perm.push_back(members[v]);
+            jlo = c.jhi;
+        }
+        if ((int)perm.size() != e->n) {
+            e->err = "launch classes do not cover every run";
+            return MRLBM_EINVAL;
+        }
+    }
     std::vector<char> seen(e->n, 0);  // the kernel indexes runs through it: must be a permutation
     for (int v : perm) {
         if (v < 0 || v >= e->n || seen[v]) {
@@ -1063,6 +1133,11 @@ int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int
     if (!b || trial_steps <= 0) return MRLBM_EINVAL;
     Engine* e = b->e;
     if (e->numeric) return MRLBM_ENUMERIC;
+    if (!e->cls.empty()) {  // the tuner chooses the shape of a single launch
+        e->cls.clear();
+        ++e->cls_gen;
+        e->gsteps = -1;
+    }
     // snapshot of every run (values, trees, lists, statistics), restored after each trial
     char* snap = nullptr;
     State* ssnap = nullptr;
@@ -1219,6 +1294,111 @@ int mrlbm_batch_get_schedule(mrlbm_batch_t b, int32_t* stride) {
     return MRLBM_OK;
 }
 
+// Launch classes: see the header. Each class's on-chip capacity is the largest that lets
+// runs_per_cu of its workgroups share a compute unit's LDS, for the runs of that class only.
+static int set_classes(Engine* e, int n, const int32_t* jup, const int32_t* threads, const int32_t* per_cu) {
+    if (n < 0 || n > 4 || (n > 0 && (!jup || !threads || !per_cu))) {
+        e->err = "classes: need 0 <= n <= 4 and the three arrays";
+        return MRLBM_EINVAL;
+    }
+    if (e->lrn) {
+        e->err = "classes: not with the refinement predictor";
+        return MRLBM_EINVAL;
+    }
+    int maxj = 0;
+    for (auto& p : e->P) maxj = std::max(maxj, p.j_max);
+    for (int c = 0; c < n; ++c) {
+        if ((c > 0 && jup[c] <= jup[c - 1]) || threads[c] < 64 || threads[c] > 512 || threads[c] % 64 ||
+            per_cu[c] < 1 || per_cu[c] > 8) {
+            e->err = "classes: bounds must increase, threads in 64..512 (multiple of 64), runs per CU in 1..8";
+            return MRLBM_EINVAL;
+        }
+    }
+    if (n > 0 && jup[n - 1] < maxj) {
+        e->err = "classes: the last bound must cover the largest j_max";
+        return MRLBM_EINVAL;
+    }
+    hipError_t st;
+    if (n > 0 && !e->side) {
+        if ((st = hipStreamCreateWithFlags(&e->side, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, st, "hipStreamCreate(side)");
+        if ((st = hipEventCreateWithFlags(&e->evf, hipEventDisableTiming)) != hipSuccess ||
+            (st = hipEventCreateWithFlags(&e->evj, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, st, "hipEventCreate(classes)");
+    }
+    // steps in flight use the old class set
+    if ((st = hipStreamSynchronize(e->stream)) != hipSuccess) return hip_fail(e, st, "classes");
+    const int tsz = e->prec == MRLBM_FP64 ? 8 : 4;
+    e->cls.clear();
+    int jlo = -1;
+    size_t lds_max = e->lds;
+    for (int c = 0; c < n; ++c) {
+        Engine::LaunchClass k;
+        k.jhi = jup[c];
+        k.nt = threads[c];
+        k.per_cu = per_cu[c];
+        const size_t budget = (e->lds_budget + 1024) / (size_t)per_cu[c] - 1024;
+        int cg_max = 0, jmin_min = 30;
+        bool any = false;
+        for (auto& d : e->hd)
+            if (d.jmax > jlo && d.jmax <= k.jhi) {
+                any = true;
+                cg_max = std::max(cg_max, (1 << (d.jmax + 1)) - (1 << d.jmin));
+                jmin_min = std::min(jmin_min, d.jmin);
+            }
+        auto total = [&](int cap) {
+            size_t t = 0;
+            for (auto& d : e->hd)
+                if (d.jmax > jlo && d.jmax <= k.jhi) {
+                    const int cs = cap > 0 ? cap / 2 + (1 << d.jmin) : 0;
+                    t = std::max(t, (size_t)make_layout(d.jmin, d.jmax, cap, cs, d.q, d.nm, tsz, false).total);
+                }
+            return t;
+        };
+        int lo = 0, hi = any ? cg_max : 0;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (total(mid) <= budget) lo = mid;
+            else hi = mid - 1;
+        }
+        k.cap = lo;
+        k.capS = lo > 0 ? lo / 2 + (1 << jmin_min) : 0;
+        k.lds = any ? total(lo) : 0;
+        lds_max = std::max(lds_max, k.lds);
+        e->cls.push_back(k);
+        jlo = k.jhi;
+    }
+    StepK sk;
+    QueryK qk;
+    InitK ik;
+    kernels_for(e->prec, e->scheme, e->gamma, &sk, &qk, &ik);
+    if (e->any_recon) sk = rc_kernel(e->prec, e->scheme);
+    (void)hipFuncSetAttribute((const void*)sk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
+    ++e->cls_gen;
+    e->gsteps = -1;
+    // the schedule array now holds the class segments (heaviest first within each class)
+    return set_schedule(e, e->n);
+}
+
+int mrlbm_batch_set_classes(mrlbm_batch_t b, int32_t n, const int32_t* j_upper, const int32_t* threads,
+                            const int32_t* runs_per_cu) {
+    if (!b) return MRLBM_EINVAL;
+    if (b->e->numeric) return MRLBM_ENUMERIC;
+    return set_classes(b->e, n, j_upper, threads, runs_per_cu);
+}
+
+int mrlbm_batch_get_classes(mrlbm_batch_t b, int32_t cap_n, int32_t* n, int32_t* counts, int32_t* cells) {
+    if (!b || !n) return MRLBM_EINVAL;
+    const Engine* e = b->e;
+    *n = (int32_t)e->cls.size();
+    if (cap_n < *n || ((!counts || !cells) && *n > 0)) return *n > 0 ? MRLBM_ECAPACITY : MRLBM_OK;
+    for (int c = 0; c < *n; ++c) {
+        counts[c] = e->cls[c].count;
+        cells[c] = e->cls[c].cap;
+    }
+    return MRLBM_OK;
+}
+
 int mrlbm_batch_set_schedule(mrlbm_batch_t b, int32_t stride) {
     if (!b || stride < 0) return MRLBM_EINVAL;
     if (b->e->numeric) return MRLBM_ENUMERIC;
@@ -1237,6 +1417,10 @@ static int set_predictor(Engine* e, const uint16_t* params, int32_t mode, double
     }
     if (mode != MRLBM_PRED_OFF && e->any_recon) {
         e->err = "the refinement predictor runs with the leaves collision only";
+        return MRLBM_EINVAL;
+    }
+    if (mode != MRLBM_PRED_OFF && !e->cls.empty()) {
+        e->err = "the refinement predictor runs with a single launch (no launch classes)";
         return MRLBM_EINVAL;
     }
     // steps still in flight on the handle's stream read the weights and samples replaced here

@@ -1,0 +1,623 @@
+// mrlbm2d.hip -- the two-dimensional adaptive MR-LBM step on the GPU (the multi-dimensional
+// extension of the paper's conclusion: projection as the mean over the four children, the
+// tensor product of the centered prediction, eps_l = 2^{d (l - J)} eps, enlargement rule (b)
+// at 2^{mu_bar + d} eps_l), with a D2Q4 scheme for a scalar conservation law.
+//
+// Layout: dense levels in device memory. Level l (J_min <= l <= J) holds q planes of
+// N_l x N_l values (index (h * N_l + i) * N_l + j, i along x) and, below J, one byte per cell
+// for "split" (the cell has four children). A step is a sequence of level-wide kernels:
+// projection up the tree, details and thresholds, the two enlargement rules, the grading
+// sweep from fine to coarse, the data transfer from coarse to fine, the leaves collision, the
+// projection of the collided values, the reconstruction on the finest level and the compact
+// stream (for each leaf and velocity the difference of the strips entering and leaving it).
+// Every expression is written in the order the FP64 checks use, with no contraction into
+// fused multiply-adds (the build passes -ffp-contract=off), so that the threshold decisions
+// and the values agree bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mrlbm.h"
+
+namespace {
+
+constexpr int Q2 = 4;  // D2Q4: (+x, -x, +y, -y)
+
+struct P2 {
+    int jmin, J, gamma, mu_bar, bc, physics;
+    double eps, lam, lam2, s1, s2, s3, oms1, oms2, oms3, Vx, Vy;
+    double c[3];
+};
+
+__device__ __forceinline__ int bci(int i, int n, int bc) {
+    if (bc == MRLBM_PERIODIC) return i & (n - 1);
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// value of plane h at cell (i + di, j + dj) of a level of n x n cells
+__device__ __forceinline__ double at(const double* f, int h, int n, int i, int j, int bc) {
+    return f[((size_t)h * n + bci(i, n, bc)) * n + bci(j, n, bc)];
+}
+
+// Tensor-product prediction of child (2i + a, 2j + b) of (i, j): ((f + sa Qx) + sb Qy) + sa sb Qxy
+__device__ double predict_child(const P2& p, const double* f, int h, int n, int i, int j, int a, int b) {
+    const int bc = p.bc;
+    double qx = 0.0, qy = 0.0, qxy = 0.0;
+    for (int al = 1; al <= p.gamma; ++al) {
+        const double tx = p.c[al - 1] * (at(f, h, n, i + al, j, bc) - at(f, h, n, i - al, j, bc));
+        const double ty = p.c[al - 1] * (at(f, h, n, i, j + al, bc) - at(f, h, n, i, j - al, bc));
+        qx = al == 1 ? tx : qx + tx;
+        qy = al == 1 ? ty : qy + ty;
+    }
+    bool first = true;
+    for (int al = 1; al <= p.gamma; ++al)
+        for (int be = 1; be <= p.gamma; ++be) {
+            const double cc = p.c[al - 1] * p.c[be - 1];
+            const double t = cc * ((at(f, h, n, i + al, j + be, bc) - at(f, h, n, i + al, j - be, bc)) -
+                                   (at(f, h, n, i - al, j + be, bc) - at(f, h, n, i - al, j - be, bc)));
+            qxy = first ? t : qxy + t;
+            first = false;
+        }
+    const double sa = a ? -1.0 : 1.0, sb = b ? -1.0 : 1.0;
+    return ((f[((size_t)h * n + i) * n + j] + sa * qx) + sb * qy) + (sa * sb) * qxy;
+}
+
+// D2Q4 collision (the oracle's fixed order)
+__device__ void collide4(const P2& p, double* f) {
+    const double u = ((f[0] + f[1]) + f[2]) + f[3];
+    const double m1 = p.lam * (f[0] - f[1]);
+    const double m2 = p.lam * (f[2] - f[3]);
+    const double m3 = p.lam2 * ((f[0] + f[1]) - (f[2] + f[3]));
+    double px, py;
+    if (p.physics == MRLBM_ADVECTION) {
+        px = p.Vx * u;
+        py = p.Vy * u;
+    } else {
+        px = (u * u) * 0.5;
+        py = (u * u) * 0.5;
+    }
+    const double m1s = p.oms1 * m1 + p.s1 * px;
+    const double m2s = p.oms2 * m2 + p.s2 * py;
+    const double m3s = p.oms3 * m3;
+    const double a = m1s / p.lam, b = m2s / p.lam, c = m3s / p.lam2;
+    const double e = 0.5 * (u + c), o = 0.5 * (u - c);
+    f[0] = 0.5 * (e + a);
+    f[1] = 0.5 * (e - a);
+    f[2] = 0.5 * (o + b);
+    f[3] = 0.5 * (o - b);
+}
+
+__global__ void k2_init(P2 p, const double* u0, double* FJ) {
+    const int n = 1 << p.J;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)n * n) return;
+    const double u = u0[k];
+    double px, py;
+    if (p.physics == MRLBM_ADVECTION) {
+        px = p.Vx * u;
+        py = p.Vy * u;
+    } else {
+        px = (u * u) * 0.5;
+        py = (u * u) * 0.5;
+    }
+    const double a = px / p.lam, b = py / p.lam, c = 0.0 / p.lam2;
+    const double e = 0.5 * (u + c), o = 0.5 * (u - c);
+    const size_t nn = (size_t)n * n;
+    FJ[k] = 0.5 * (e + a);
+    FJ[nn + k] = 0.5 * (e - a);
+    FJ[2 * nn + k] = 0.5 * (o + b);
+    FJ[3 * nn + k] = 0.5 * (o - b);
+}
+
+__global__ void k2_fill(uint8_t* s, size_t n, uint8_t v) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) s[k] = v;
+}
+
+// projection of the split cells of level l from level l + 1
+__global__ void k2_project(int n, const uint8_t* split, const double* fine, double* coarse) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)n * n || !split[k]) return;
+    const int i = (int)(k / n), j = (int)(k % n);
+    const int m = 2 * n;
+    for (int h = 0; h < Q2; ++h) {
+        const double* g = fine + (size_t)h * m * m;
+        const double a = g[(size_t)(2 * i) * m + 2 * j], b = g[(size_t)(2 * i + 1) * m + 2 * j];
+        const double c = g[(size_t)(2 * i) * m + 2 * j + 1], d = g[(size_t)(2 * i + 1) * m + 2 * j + 1];
+        coarse[((size_t)h * n + i) * n + j] = (((a + b) + c) + d) * 0.25;
+    }
+}
+
+// details of the split cells of level l: keep (T_eps) and rule-(b) flags
+__global__ void k2_details(P2 p, int l, const uint8_t* split, const double* coarse, const double* fine, uint8_t* keep,
+                           uint8_t* ruleb, int* nan_flag) {
+    const int n = 1 << l;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)n * n) return;
+    keep[k] = 0;
+    ruleb[k] = 0;
+    if (!split[k]) return;
+    const int i = (int)(k / n), j = (int)(k % n);
+    const int m = 2 * n;
+    double D = 0.0;
+    bool bad = false;
+    for (int h = 0; h < Q2; ++h)
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                const double pr = predict_child(p, coarse, h, n, i, j, a, b);
+                const double d = fabs(fine[((size_t)h * m + 2 * i + a) * m + 2 * j + b] - pr);
+                bad = bad || (d != d);
+                D = d > D ? d : D;
+            }
+    if (bad) *nan_flag = 1;
+    const double thr = ldexp(p.eps, 2 * (l + 1 - p.J));
+    const double thrb = ldexp(thr, p.mu_bar + 2);
+    const bool kb = bad || D >= thr;
+    keep[k] = kb;
+    ruleb[k] = kb && (l + 1 < p.J) && (bad || D >= thrb);
+}
+
+// rule (a): the kept cells' children put their sigma-box (sigma = 1) into R, i.e. their parents
+// p -+ 1 split; rule (b): the four children of a flagged cell split
+__global__ void k2_enlarge(P2 p, int l, const uint8_t* keep, const uint8_t* ruleb, uint8_t* nsplit_l, uint8_t* nsplit_l1) {
+    const int n = 1 << l;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)n * n || !keep[k]) return;
+    const int i = (int)(k / n), j = (int)(k % n);
+    const int m = 2 * n;
+    // children 2i..2i+1 shifted by -1..1 at level l + 1: parents i - 1 .. i + 1
+    for (int di = -1; di <= 1; ++di)
+        for (int dj = -1; dj <= 1; ++dj) {
+            const int ci = bci(2 * i + (di < 0 ? -1 : (di > 0 ? 2 : 0)), m, p.bc);
+            const int cj = bci(2 * j + (dj < 0 ? -1 : (dj > 0 ? 2 : 0)), m, p.bc);
+            nsplit_l[(size_t)(ci >> 1) * n + (cj >> 1)] = 1;
+        }
+    if (ruleb[k] && nsplit_l1)
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) nsplit_l1[(size_t)(2 * i + a) * m + 2 * j + b] = 1;
+}
+
+// grading at level a: every split (a, p) puts its gamma-box into R (the parents split)
+__global__ void k2_grade(int a, int gamma, int bc, const uint8_t* sa, uint8_t* sa1) {
+    const int n = 1 << a;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)n * n || !sa[k]) return;
+    const int i = (int)(k / n), j = (int)(k % n);
+    const int h = n >> 1;
+    for (int di = -gamma; di <= gamma; ++di)
+        for (int dj = -gamma; dj <= gamma; ++dj) sa1[(size_t)(bci(i + di, n, bc) >> 1) * h + (bci(j + dj, n, bc) >> 1)] = 1;
+}
+
+// transfer at level l + 1: cells of the new tree that the old tree lacked are predicted
+__global__ void k2_transfer(P2 p, int l, const uint8_t* old_split_l, const uint8_t* new_split_l, const double* coarse,
+                            double* fine) {
+    const int n = 1 << l, m = 2 * n;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)m * m) return;
+    const int ci = (int)(k / m), cj = (int)(k % m);
+    const size_t pk = (size_t)(ci >> 1) * n + (cj >> 1);
+    if (!new_split_l[pk] || old_split_l[pk]) return;
+    for (int h = 0; h < Q2; ++h)
+        fine[((size_t)h * m + ci) * m + cj] = predict_child(p, coarse, h, n, ci >> 1, cj >> 1, ci & 1, cj & 1);
+}
+
+// leaves collision at level l (cells of R not split); counts the leaves
+__global__ void k2_collide(P2 p, int l, const uint8_t* split_lm1, const uint8_t* split_l, double* F, unsigned long long* nleaf,
+                           int* nan_flag) {
+    const int n = 1 << l;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)n * n) return;
+    const int i = (int)(k / n), j = (int)(k % n);
+    const bool inR = !split_lm1 || split_lm1[(size_t)(i >> 1) * (n >> 1) + (j >> 1)];
+    const bool leaf = inR && !(split_l && split_l[k]);
+    if (!leaf) return;
+    const size_t nn = (size_t)n * n;
+    double f[Q2];
+    for (int h = 0; h < Q2; ++h) f[h] = F[h * nn + k];
+    collide4(p, f);
+    bool bad = false;
+    for (int h = 0; h < Q2; ++h) {
+        bad = bad || (f[h] != f[h]);
+        F[h * nn + k] = f[h];
+    }
+    if (bad) *nan_flag = 1;
+    atomicAdd(nleaf, 1ull);
+}
+
+// reconstruction from level l to l + 1: G_{l+1} = prediction of G_l, stored values on R
+__global__ void k2_reconstruct(P2 p, int l, const uint8_t* split_l, const double* Gl, const double* Fl1, double* Gl1) {
+    const int n = 1 << l, m = 2 * n;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)m * m) return;
+    const int ci = (int)(k / m), cj = (int)(k % m);
+    const bool inR = split_l[(size_t)(ci >> 1) * n + (cj >> 1)] != 0;
+    for (int h = 0; h < Q2; ++h) {
+        const size_t o = ((size_t)h * m + ci) * m + cj;
+        Gl1[o] = inR ? Fl1[o] : predict_child(p, Gl, h, n, ci >> 1, cj >> 1, ci & 1, cj & 1);
+    }
+}
+
+// compact stream of the leaves of level l from the finest reconstruction G (N_J x N_J)
+__global__ void k2_stream(P2 p, int l, const uint8_t* split_lm1, const uint8_t* split_l, const double* G, double* F) {
+    const int n = 1 << l, NJ = 1 << p.J, L = 1 << (p.J - l);
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)n * n) return;
+    const int i = (int)(k / n), j = (int)(k % n);
+    const bool inR = !split_lm1 || split_lm1[(size_t)(i >> 1) * (n >> 1) + (j >> 1)];
+    if (!inR || (split_l && split_l[k])) return;
+    const size_t nn = (size_t)n * n, NN = (size_t)NJ * NJ;
+    const int x0 = i * L, y0 = j * L, bc = p.bc;
+    const int wx[Q2] = {1, -1, 0, 0}, wy[Q2] = {0, 0, 1, -1};
+    double out[Q2];
+    for (int h = 0; h < Q2; ++h) {
+        const double* g = G + h * NN;
+        if (l == p.J) {
+            out[h] = g[(size_t)bci(x0 - wx[h], NJ, bc) * NJ + bci(y0 - wy[h], NJ, bc)];
+            continue;
+        }
+        double acc = 0.0;
+        for (int t = 0; t < L; ++t) {
+            double a, b;
+            if (wx[h] != 0) {
+                const int y = bci(y0 + t, NJ, bc);
+                a = g[(size_t)bci(wx[h] > 0 ? x0 - 1 : x0, NJ, bc) * NJ + y];
+                b = g[(size_t)bci(wx[h] > 0 ? x0 + L - 1 : x0 + L, NJ, bc) * NJ + y];
+            } else {
+                const int x = bci(x0 + t, NJ, bc);
+                a = g[(size_t)x * NJ + bci(wy[h] > 0 ? y0 - 1 : y0, NJ, bc)];
+                b = g[(size_t)x * NJ + bci(wy[h] > 0 ? y0 + L - 1 : y0 + L, NJ, bc)];
+            }
+            const bool pos = (wx[h] + wy[h]) > 0;
+            const double term = pos ? (a - b) : -(a - b);
+            acc = t == 0 ? term : acc + term;
+        }
+        out[h] = F[h * nn + k] + ldexp(acc, -2 * (p.J - l));
+    }
+    for (int h = 0; h < Q2; ++h) F[h * nn + k] = out[h];
+}
+
+// conserved moment u on the finest level from the reconstruction
+__global__ void k2_moment(int NJ, const double* G, double* out) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t NN = (size_t)NJ * NJ;
+    if (k >= NN) return;
+    out[k] = ((G[k] + G[NN + k]) + G[2 * NN + k]) + G[3 * NN + k];
+}
+
+struct Run2D {
+    P2 p;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<double*> F;      // per level, q x N_l x N_l
+    std::vector<uint8_t*> split; // per level < J
+    std::vector<uint8_t*> nsplit, keep, ruleb;
+    double* G0 = nullptr;        // reconstruction ping-pong (finest size)
+    double* G1 = nullptr;
+    double* out = nullptr;       // finest conserved moment
+    unsigned long long* d_nleaf = nullptr;
+    int* d_nan = nullptr;
+    long long steps = 0, leaf_updates = 0, leaves = 0;
+    bool numeric = false;
+    std::string err;
+    std::vector<void*> allocs;
+};
+
+thread_local std::string g_err2d;
+
+int fail2d(Run2D* r, hipError_t st, const char* what) {
+    r->err = std::string(what) + ": " + hipGetErrorString(st);
+    return st == hipErrorOutOfMemory ? MRLBM_ENOMEM : MRLBM_EDEVICE;
+}
+
+unsigned blocks(size_t n) { return (unsigned)((n + 255) / 256); }
+
+void free2d(Run2D* r) {
+    if (!r) return;
+    for (void* a : r->allocs) (void)hipFree(a);
+    if (r->own_stream && r->stream) (void)hipStreamDestroy(r->stream);
+    delete r;
+}
+
+int validate2d(const mrlbm2d_params* q, std::string* why) {
+    auto bad = [&](const char* m) {
+        if (why) *why = m;
+        return (int)MRLBM_EINVAL;
+    };
+    if (!q) return bad("params is NULL");
+    if (q->abi_version != MRLBM_ABI_VERSION) return bad("abi_version mismatch");
+    if (q->physics != MRLBM_ADVECTION && q->physics != MRLBM_BURGERS) return bad("physics: advection or Burgers");
+    if (q->bc != MRLBM_PERIODIC && q->bc != MRLBM_CLAMP) return bad("bc must be PERIODIC or CLAMP");
+    if (!(q->lambda > 0.0) || !isfinite(q->lambda)) return bad("lambda must be finite and > 0");
+    for (int i = 0; i < 3; ++i)
+        if (!(q->s[i] > 0.0 && q->s[i] <= 2.0)) return bad("relaxation rates must lie in (0, 2]");
+    if (!isfinite(q->V[0]) || !isfinite(q->V[1])) return bad("V must be finite");
+    if (q->gamma < 1 || q->gamma > 3) return bad("gamma must be 1, 2 or 3");
+    if (q->j_min < 1 || q->j_min > q->j_max) return bad("need 1 <= j_min <= j_max");
+    if (q->j_max > 12) {
+        if (why) *why = "j_max beyond 12";
+        return MRLBM_ECAPACITY;
+    }
+    if (q->bc == MRLBM_PERIODIC && (1 << q->j_min) < 2 * q->gamma + 1)
+        return bad("periodic coarsest level needs 2^j_min >= 2 gamma + 1");
+    if (q->mu_bar < 0 || q->mu_bar > 30) return bad("mu_bar must be in 0..30");
+    if (!(q->eps >= 0.0) || !isfinite(q->eps)) return bad("eps must be finite and >= 0");
+    return MRLBM_OK;
+}
+
+int step2d(Run2D* r) {
+    const P2& p = r->p;
+    const int J = p.J, jmin = p.jmin;
+    hipStream_t s = r->stream;
+    auto N = [](int l) { return (size_t)1 << l; };
+    // 1. projection of f^n up the tree
+    for (int l = J - 1; l >= jmin; --l)
+        hipLaunchKernelGGL(k2_project, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, (int)N(l), r->split[l - jmin],
+                           r->F[l + 1 - jmin], r->F[l - jmin]);
+    // 2. details, T_eps and rule-(b) flags
+    for (int l = jmin; l < J; ++l)
+        hipLaunchKernelGGL(k2_details, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l, r->split[l - jmin],
+                           r->F[l - jmin], r->F[l + 1 - jmin], r->keep[l - jmin], r->ruleb[l - jmin], r->d_nan);
+    // 3. enlargement: new = keep, then rules (a) and (b)
+    for (int l = jmin; l < J; ++l)
+        if (hipMemcpyAsync(r->nsplit[l - jmin], r->keep[l - jmin], N(l) * N(l), hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return MRLBM_EDEVICE;
+    for (int l = jmin; l < J; ++l)
+        hipLaunchKernelGGL(k2_enlarge, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l, r->keep[l - jmin],
+                           r->ruleb[l - jmin], r->nsplit[l - jmin], l + 1 < J ? r->nsplit[l + 1 - jmin] : nullptr);
+    // 4. grading, fine to coarse
+    for (int a = J - 1; a > jmin; --a)
+        hipLaunchKernelGGL(k2_grade, dim3(blocks(N(a) * N(a))), dim3(256), 0, s, a, p.gamma, p.bc, r->nsplit[a - jmin],
+                           r->nsplit[a - 1 - jmin]);
+    // 5. transfer, coarse to fine; then the new tree replaces the old one
+    for (int l = jmin; l < J; ++l)
+        hipLaunchKernelGGL(k2_transfer, dim3(blocks(N(l + 1) * N(l + 1))), dim3(256), 0, s, p, l, r->split[l - jmin],
+                           r->nsplit[l - jmin], r->F[l - jmin], r->F[l + 1 - jmin]);
+    std::swap(r->split, r->nsplit);
+    // 6. leaves collision
+    if (hipMemsetAsync(r->d_nleaf, 0, sizeof(unsigned long long), s) != hipSuccess) return MRLBM_EDEVICE;
+    for (int l = jmin; l <= J; ++l)
+        hipLaunchKernelGGL(k2_collide, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l,
+                           l > jmin ? r->split[l - 1 - jmin] : (const uint8_t*)nullptr,
+                           l < J ? r->split[l - jmin] : (const uint8_t*)nullptr, r->F[l - jmin], r->d_nleaf, r->d_nan);
+    // 7. projection of the collided values, reconstruction on the finest level, stream
+    for (int l = J - 1; l >= jmin; --l)
+        hipLaunchKernelGGL(k2_project, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, (int)N(l), r->split[l - jmin],
+                           r->F[l + 1 - jmin], r->F[l - jmin]);
+    double* ga = r->G0;
+    double* gb = r->G1;
+    if (hipMemcpyAsync(ga, r->F[0], sizeof(double) * Q2 * N(jmin) * N(jmin), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return MRLBM_EDEVICE;
+    for (int l = jmin; l < J; ++l) {
+        hipLaunchKernelGGL(k2_reconstruct, dim3(blocks(N(l + 1) * N(l + 1))), dim3(256), 0, s, p, l, r->split[l - jmin],
+                           ga, r->F[l + 1 - jmin], gb);
+        std::swap(ga, gb);
+    }
+    for (int l = jmin; l <= J; ++l)
+        hipLaunchKernelGGL(k2_stream, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l,
+                           l > jmin ? r->split[l - 1 - jmin] : (const uint8_t*)nullptr,
+                           l < J ? r->split[l - jmin] : (const uint8_t*)nullptr, ga, r->F[l - jmin]);
+    hipError_t st = hipGetLastError();
+    if (st != hipSuccess) return fail2d(r, st, "step launch");
+    unsigned long long nl = 0;
+    if ((st = hipMemcpyAsync(&nl, r->d_nleaf, sizeof(nl), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (st = hipStreamSynchronize(s)) != hipSuccess)
+        return fail2d(r, st, "step");
+    r->leaves = (long long)nl;
+    r->leaf_updates += (long long)nl;
+    r->steps += 1;
+    return MRLBM_OK;
+}
+
+}  // namespace
+
+struct mrlbm2d_s {
+    Run2D* r;
+};
+
+extern "C" {
+
+int mrlbm2d_validate(const mrlbm2d_params* p) { return validate2d(p, nullptr); }
+
+int mrlbm2d_create(const mrlbm2d_params* q, const double* u0, void* hip_stream, mrlbm2d_t* out) {
+    if (!out) return MRLBM_EINVAL;
+    *out = nullptr;
+    g_err2d.clear();
+    std::string why;
+    int rc = validate2d(q, &why);
+    if (rc != MRLBM_OK) {
+        g_err2d = why;
+        return rc;
+    }
+    if (!u0) {
+        g_err2d = "initial data pointer is NULL";
+        return MRLBM_EINVAL;
+    }
+    const size_t NJ = (size_t)1 << q->j_max;
+    for (size_t k = 0; k < NJ * NJ; ++k)
+        if (!isfinite(u0[k])) {
+            g_err2d = "initial data must be finite";
+            return MRLBM_EINVAL;
+        }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        g_err2d = "no HIP device";
+        return MRLBM_EDEVICE;
+    }
+    Run2D* r = new (std::nothrow) Run2D();
+    if (!r) return MRLBM_ENOMEM;
+    P2& p = r->p;
+    memset(&p, 0, sizeof(p));
+    p.jmin = q->j_min;
+    p.J = q->j_max;
+    p.gamma = q->gamma;
+    p.mu_bar = q->mu_bar;
+    p.bc = q->bc;
+    p.physics = q->physics;
+    p.eps = q->eps;
+    p.lam = q->lambda;
+    p.lam2 = q->lambda * q->lambda;
+    p.s1 = q->s[0];
+    p.s2 = q->s[1];
+    p.s3 = q->s[2];
+    p.oms1 = 1.0 - q->s[0];
+    p.oms2 = 1.0 - q->s[1];
+    p.oms3 = 1.0 - q->s[2];
+    p.Vx = q->V[0];
+    p.Vy = q->V[1];
+    if (q->gamma == 1) {
+        p.c[0] = -1.0 / 8.0;
+    } else if (q->gamma == 2) {
+        p.c[0] = -22.0 / 128.0;
+        p.c[1] = 3.0 / 128.0;
+    } else {
+        p.c[0] = -201.0 / 1024.0;  // c3 with the sign that makes the stencil exact on degree 5
+        p.c[1] = 11.0 / 256.0;
+        p.c[2] = -5.0 / 1024.0;
+    }
+    hipError_t st;
+    auto dalloc = [&](void** ptr, size_t bytes) {
+        st = hipMalloc(ptr, bytes);
+        if (st == hipSuccess) r->allocs.push_back(*ptr);
+        return st == hipSuccess;
+    };
+    auto fail = [&](const char* what) {
+        const int code = fail2d(r, st, what);
+        g_err2d = r->err;
+        free2d(r);
+        return code;
+    };
+    if (hip_stream) {
+        r->stream = (hipStream_t)hip_stream;
+    } else {
+        if ((st = hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking)) != hipSuccess) return fail("hipStreamCreate");
+        r->own_stream = true;
+    }
+    for (int l = p.jmin; l <= p.J; ++l) {
+        const size_t nn = ((size_t)1 << l) << l;
+        void* f = nullptr;
+        if (!dalloc(&f, sizeof(double) * Q2 * nn)) return fail("hipMalloc(levels)");
+        if ((st = hipMemsetAsync(f, 0, sizeof(double) * Q2 * nn, r->stream)) != hipSuccess) return fail("hipMemset");
+        r->F.push_back(static_cast<double*>(f));
+        if (l < p.J) {
+            void* a[4] = {nullptr, nullptr, nullptr, nullptr};
+            for (int t = 0; t < 4; ++t)
+                if (!dalloc(&a[t], nn)) return fail("hipMalloc(split)");
+            r->split.push_back(static_cast<uint8_t*>(a[0]));
+            r->nsplit.push_back(static_cast<uint8_t*>(a[1]));
+            r->keep.push_back(static_cast<uint8_t*>(a[2]));
+            r->ruleb.push_back(static_cast<uint8_t*>(a[3]));
+            hipLaunchKernelGGL(k2_fill, dim3(blocks(nn)), dim3(256), 0, r->stream, r->split.back(), nn, (uint8_t)1);
+        }
+    }
+    void *g0 = nullptr, *g1 = nullptr, *o = nullptr, *nl = nullptr, *nf = nullptr, *ud = nullptr;
+    if (!dalloc(&g0, sizeof(double) * Q2 * NJ * NJ) || !dalloc(&g1, sizeof(double) * Q2 * NJ * NJ) ||
+        !dalloc(&o, sizeof(double) * NJ * NJ) || !dalloc(&nl, sizeof(unsigned long long)) || !dalloc(&nf, sizeof(int)) ||
+        !dalloc(&ud, sizeof(double) * NJ * NJ))
+        return fail("hipMalloc(work)");
+    r->G0 = static_cast<double*>(g0);
+    r->G1 = static_cast<double*>(g1);
+    r->out = static_cast<double*>(o);
+    r->d_nleaf = static_cast<unsigned long long*>(nl);
+    r->d_nan = static_cast<int*>(nf);
+    if ((st = hipMemsetAsync(r->d_nan, 0, sizeof(int), r->stream)) != hipSuccess ||
+        (st = hipMemcpyAsync(ud, u0, sizeof(double) * NJ * NJ, hipMemcpyHostToDevice, r->stream)) != hipSuccess)
+        return fail("upload");
+    hipLaunchKernelGGL(k2_init, dim3(blocks(NJ * NJ)), dim3(256), 0, r->stream, p, (const double*)ud, r->F.back());
+    if ((st = hipStreamSynchronize(r->stream)) != hipSuccess) return fail("init");
+    r->leaves = (long long)(NJ * NJ);
+    mrlbm2d_t h = new (std::nothrow) mrlbm2d_s{r};
+    if (!h) {
+        free2d(r);
+        return MRLBM_ENOMEM;
+    }
+    *out = h;
+    return MRLBM_OK;
+}
+
+int mrlbm2d_step(mrlbm2d_t h, int32_t nsteps) {
+    if (!h || nsteps < 0) return MRLBM_EINVAL;
+    Run2D* r = h->r;
+    if (r->numeric) return MRLBM_ENUMERIC;
+    for (int t = 0; t < nsteps; ++t) {
+        const int rc = step2d(r);
+        if (rc != MRLBM_OK) return rc;
+    }
+    int nan = 0;
+    hipError_t st = hipMemcpyAsync(&nan, r->d_nan, sizeof(int), hipMemcpyDeviceToHost, r->stream);
+    if (st == hipSuccess) st = hipStreamSynchronize(r->stream);
+    if (st != hipSuccess) return fail2d(r, st, "step");
+    if (nan) {
+        r->numeric = true;
+        return MRLBM_ENUMERIC;
+    }
+    return MRLBM_OK;
+}
+
+int mrlbm2d_moments(mrlbm2d_t h, double* out, int64_t cap) {
+    if (!h || !out) return MRLBM_EINVAL;
+    Run2D* r = h->r;
+    if (r->numeric) return MRLBM_ENUMERIC;
+    const P2& p = r->p;
+    const size_t NJ = (size_t)1 << p.J;
+    if (cap < (int64_t)(NJ * NJ)) return MRLBM_ECAPACITY;
+    hipStream_t s = r->stream;
+    auto N = [](int l) { return (size_t)1 << l; };
+    for (int l = p.J - 1; l >= p.jmin; --l)
+        hipLaunchKernelGGL(k2_project, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, (int)N(l), r->split[l - p.jmin],
+                           r->F[l + 1 - p.jmin], r->F[l - p.jmin]);
+    double* ga = r->G0;
+    double* gb = r->G1;
+    if (hipMemcpyAsync(ga, r->F[0], sizeof(double) * Q2 * N(p.jmin) * N(p.jmin), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return MRLBM_EDEVICE;
+    for (int l = p.jmin; l < p.J; ++l) {
+        hipLaunchKernelGGL(k2_reconstruct, dim3(blocks(N(l + 1) * N(l + 1))), dim3(256), 0, s, p, l,
+                           r->split[l - p.jmin], ga, r->F[l + 1 - p.jmin], gb);
+        std::swap(ga, gb);
+    }
+    hipLaunchKernelGGL(k2_moment, dim3(blocks(NJ * NJ)), dim3(256), 0, s, (int)NJ, (const double*)ga, r->out);
+    hipError_t st = hipMemcpyAsync(out, r->out, sizeof(double) * NJ * NJ, hipMemcpyDeviceToHost, s);
+    if (st == hipSuccess) st = hipStreamSynchronize(s);
+    if (st != hipSuccess) return fail2d(r, st, "moments");
+    return MRLBM_OK;
+}
+
+int mrlbm2d_split(mrlbm2d_t h, int32_t level, uint8_t* out, int64_t cap) {
+    if (!h || !out) return MRLBM_EINVAL;
+    Run2D* r = h->r;
+    if (level < r->p.jmin || level >= r->p.J) return MRLBM_EINVAL;
+    const size_t nn = ((size_t)1 << level) << level;
+    if (cap < (int64_t)nn) return MRLBM_ECAPACITY;
+    hipError_t st = hipMemcpyAsync(out, r->split[level - r->p.jmin], nn, hipMemcpyDeviceToHost, r->stream);
+    if (st == hipSuccess) st = hipStreamSynchronize(r->stream);
+    if (st != hipSuccess) return fail2d(r, st, "split");
+    return MRLBM_OK;
+}
+
+int mrlbm2d_stats(mrlbm2d_t h, int64_t* steps, int64_t* leaves, int64_t* leaf_updates) {
+    if (!h || !steps || !leaves || !leaf_updates) return MRLBM_EINVAL;
+    *steps = h->r->steps;
+    *leaves = h->r->leaves;
+    *leaf_updates = h->r->leaf_updates;
+    return MRLBM_OK;
+}
+
+void mrlbm2d_destroy(mrlbm2d_t h) {
+    if (!h) return;
+    if (h->r && h->r->stream) (void)hipStreamSynchronize(h->r->stream);
+    free2d(h->r);
+    delete h;
+}
+
+const char* mrlbm2d_last_error(mrlbm2d_t h) {
+    if (!h) return g_err2d.c_str();
+    return h->r->err.c_str();
+}
+
+}  // extern "C"

@@ -46,6 +46,12 @@ class Stats(ctypes.Structure):
                 ("tree_cells", c_int64), ("misses", c_int64), ("redos", c_int64)]
 
 
+class Params2D(ctypes.Structure):
+    _fields_ = [("abi_version", c_int32), ("physics", c_int32), ("bc", c_int32), ("gamma", c_int32),
+                ("lam", c_double), ("s", c_double * 3), ("V", c_double * 2), ("j_min", c_int32), ("j_max", c_int32),
+                ("mu_bar", c_int32), ("reserved", c_int32), ("eps", c_double)]
+
+
 class MRLBMError(RuntimeError):
     def __init__(self, code, msg=""):
         super().__init__(f"{_STATUS.get(code, code)}: {msg}")
@@ -81,6 +87,8 @@ SIGNATURES = {
     "mrlbm_batch_set_schedule": (c_int32, [c_void_p, c_int32]),
     "mrlbm_batch_get_schedule": (c_int32, [c_void_p, _P(c_int32)]),
     "mrlbm_batch_set_launch_steps": (c_int32, [c_void_p, c_int32]),
+    "mrlbm_batch_set_classes": (c_int32, [c_void_p, c_int32, _P(c_int32), _P(c_int32), _P(c_int32)]),
+    "mrlbm_batch_get_classes": (c_int32, [c_void_p, c_int32, _P(c_int32), _P(c_int32), _P(c_int32)]),
     "mrlbm_batch_checkpoint": (c_int32, [c_void_p]),
     "mrlbm_batch_restore": (c_int32, [c_void_p]),
     "mrlbm_set_predictor": (c_int32, [c_void_p, _P(ctypes.c_uint16), c_int32, c_double, c_int64]),
@@ -97,6 +105,14 @@ SIGNATURES = {
     "mrlbm_mlp_destroy": (None, [c_void_p]),
     "mrlbm_mlp_last_error": (ctypes.c_char_p, [c_void_p]),
     "mrlbm_run_noalloc": (c_int32, [_P(Params), c_void_p, c_int32, c_void_p, c_void_p]),
+    "mrlbm2d_validate": (c_int32, [_P(Params2D)]),
+    "mrlbm2d_create": (c_int32, [_P(Params2D), _P(c_double), c_void_p, _PP]),
+    "mrlbm2d_step": (c_int32, [c_void_p, c_int32]),
+    "mrlbm2d_moments": (c_int32, [c_void_p, _P(c_double), c_int64]),
+    "mrlbm2d_split": (c_int32, [c_void_p, c_int32, _P(ctypes.c_uint8), c_int64]),
+    "mrlbm2d_stats": (c_int32, [c_void_p, _P(c_int64), _P(c_int64), _P(c_int64)]),
+    "mrlbm2d_destroy": (None, [c_void_p]),
+    "mrlbm2d_last_error": (ctypes.c_char_p, [c_void_p]),
     "mrlbm_batch_destroy": (None, [c_void_p]),
     "mrlbm_batch_last_error": (ctypes.c_char_p, [c_void_p]),
 }
@@ -440,6 +456,20 @@ class Batch:
     def set_launch_steps(self, steps):
         _check(lib().mrlbm_batch_set_launch_steps(self.h, int(steps)), self._err)
 
+    def set_classes(self, j_upper=(), threads=(), runs_per_cu=()):
+        """Launch classes by j_max (see mrlbm_batch_set_classes); empty: one launch."""
+        n = len(j_upper)
+        arr = lambda v: (c_int32 * max(n, 1))(*[int(x) for x in v])  # noqa: E731
+        _check(lib().mrlbm_batch_set_classes(self.h, n, arr(j_upper), arr(threads), arr(runs_per_cu)), self._err)
+
+    def get_classes(self):
+        """[(runs, on-chip capacity)] per class; empty for a single launch."""
+        n = c_int32()
+        counts = (c_int32 * 4)()
+        cells = (c_int32 * 4)()
+        _check(lib().mrlbm_batch_get_classes(self.h, 4, ctypes.byref(n), counts, cells), self._err)
+        return [(counts[i], cells[i]) for i in range(n.value)]
+
     def checkpoint(self):
         """Keep every run's state on the device (one copy, overwritten by the next call)."""
         _check(lib().mrlbm_batch_checkpoint(self.h), self._err)
@@ -466,6 +496,79 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             lib().mrlbm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_params2d(p):
+    """Params2D from a dict with keys physics, bc, gamma, lam, s (three rates or one), V, jmin,
+    jmax, mu_bar, eps."""
+    P = Params2D()
+    P.abi_version = p.get("abi_version", ABI_VERSION)
+    P.physics = p["physics"]
+    P.bc = p.get("bc", PERIODIC)
+    P.gamma = p.get("gamma", 1)
+    P.lam = p["lam"]
+    s = list(np.atleast_1d(np.asarray(p["s"], dtype=np.float64)))
+    s = s * 3 if len(s) == 1 else s
+    for i in range(3):
+        P.s[i] = s[i]
+    V = list(p.get("V", (0.0, 0.0)))
+    P.V[0], P.V[1] = V[0], V[1]
+    P.j_min = p["jmin"]
+    P.j_max = p["jmax"]
+    P.mu_bar = p.get("mu_bar", 0)
+    P.eps = p["eps"]
+    return P
+
+
+class MRLBM2D:
+    """One two-dimensional adaptive run on the GPU (D2Q4, quadtree)."""
+
+    def __init__(self, params, u0, stream=None):
+        L = lib()
+        self.P = params if isinstance(params, Params2D) else make_params2d(params)
+        n = 1 << self.P.j_max if 0 <= self.P.j_max <= 30 else 0
+        u = np.ascontiguousarray(u0, dtype=np.float64)
+        if u.shape != (n, n):
+            raise ValueError(f"initial data have shape {u.shape}, need {(n, n)}")
+        h = ctypes.c_void_p()
+        _check(L.mrlbm2d_create(ctypes.byref(self.P), _dptr(u), stream, ctypes.byref(h)),
+               lambda: L.mrlbm2d_last_error(None).decode())
+        self.h = h
+        self.n = n
+
+    def _err(self):
+        return lib().mrlbm2d_last_error(self.h).decode()
+
+    def step(self, n=1):
+        _check(lib().mrlbm2d_step(self.h, int(n)), self._err)
+
+    def moments(self):
+        out = np.empty((self.n, self.n))
+        _check(lib().mrlbm2d_moments(self.h, _dptr(out), out.size), self._err)
+        return out
+
+    def split(self, level):
+        m = 1 << level
+        out = np.empty((m, m), dtype=np.uint8)
+        _check(lib().mrlbm2d_split(self.h, int(level), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), out.size),
+               self._err)
+        return out.astype(bool)
+
+    def stats(self):
+        a, b, c = c_int64(), c_int64(), c_int64()
+        _check(lib().mrlbm2d_stats(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), self._err)
+        return {"steps": a.value, "leaves": b.value, "leaf_updates": c.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mrlbm2d_destroy(self.h)
             self.h = None
 
     def __del__(self):

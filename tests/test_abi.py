@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     txt = open(os.path.join(ROOT, "include", "mrlbm.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(mrlbm_\w+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(mrlbm(?:2d)?_\w+)\s*\(", txt)))
 
 
 def test_header_and_binding_agree():
@@ -32,11 +32,34 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layout():
+    """The binding's structs against the header compiled by the host C compiler: size and the
+    offset of every field."""
     import ctypes
-    assert ctypes.sizeof(mrlbm.Params) == 176
-    assert mrlbm.Params.lam.offset == 24
-    assert mrlbm.Params.eps.offset == 160
-    assert ctypes.sizeof(mrlbm.Stats) == 64
+    import shutil
+    import subprocess
+    import tempfile
+    structs = {"mrlbm_params": (mrlbm.Params, {"lam": "lambda"}), "mrlbm_stats_t": (mrlbm.Stats, {}),
+               "mrlbm2d_params": (mrlbm.Params2D, {"lam": "lambda"})}
+    cc = shutil.which("gcc") or shutil.which("cc")
+    assert cc, "a host C compiler is needed"
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mrlbm.h"', "int main(void) {"]
+    for name, (cls, ren) in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name} {f} %zu\\n", offsetof({name}, {ren.get(f, f)}));')
+    lines += ["return 0;", "}"]
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "layout.c")
+        with open(src, "w") as fh:
+            fh.write("\n".join(lines))
+        exe = os.path.join(d, "layout")
+        subprocess.run([cc, "-I", os.path.join(ROOT, "include"), "-o", exe, src], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for name, (cls, _) in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)
 
 
 def good():

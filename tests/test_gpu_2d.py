@@ -1,0 +1,123 @@
+"""GPU parity of the two-dimensional step (the multi-D extension: tensor-product prediction,
+eps_l = 2^{d (l - J)} eps, rule (b) at 2^{mu_bar + d} eps_l; D2Q4) against the 2D oracle:
+split flags of every level bit-exact and the reconstructed finest moment within 1e-12 every
+few steps; eps = 0 equal to the uniform 2D scheme; the refusals of the host validation."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import adaptive2d as A
+from paper_2102_12163_amd import mrlbm
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def datum(J, kind, seed=0):
+    """Seeded 2D data on [0, 1]^2 (cell-centre samples): a box or a Gaussian bump."""
+    rng = np.random.default_rng([20, seed])
+    x = (np.arange(2 ** J) + 0.5) / 2 ** J - 0.5
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    cx, cy = rng.uniform(-0.15, 0.15, 2)
+    if kind == "box":
+        a, b = rng.uniform(0.1, 0.25, 2)
+        return 0.2 + 0.5 * ((np.abs(X - cx) < a) & (np.abs(Y - cy) < b))
+    w = rng.uniform(0.01, 0.04)
+    return 0.2 + 0.5 * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / w)
+
+
+def params(physics, J, eps, bc=A.PERIODIC, gamma=1, jmin=2, mu_bar=0):
+    # stable uniform D2Q4 settings on these data (Burgers: lambda = 2)
+    s = [1.5, 1.5, 1.5] if physics == A.ADVECTION else [1.6, 1.6, 1.2]
+    lam = 1.0 if physics == A.ADVECTION else 2.0
+    return dict(physics=physics, bc=bc, gamma=gamma, lam=lam, s=s, V=(0.4, 0.25), jmin=jmin, jmax=J, mu_bar=mu_bar,
+                eps=eps)
+
+
+def oracle(p, u0):
+    sch = A.D2Q4(p["physics"], p["lam"], p["s"], V=p["V"])
+    return A.Adaptive2D(sch, p["jmin"], p["jmax"], p["gamma"], p["eps"], p["mu_bar"], p["bc"], u0)
+
+
+def run_pair(p, u0, nsteps, every, label):
+    announce(label, "J", p["jmax"], "steps", nsteps)
+    run = mrlbm.MRLBM2D(p, u0)
+    ora = oracle(p, u0)
+    done = 0
+    try:
+        while done < nsteps:
+            k = min(every, nsteps - done)
+            run.step(k)
+            ora.step(k)
+            done += k
+            for l in range(p["jmin"], p["jmax"]):
+                assert np.array_equal(run.split(l), ora.split[l]), (label, done, l)
+            got, want = run.moments(), ora.finest_conserved()[0]
+            err = float(np.max(np.abs(got - want))) / max(1.0, float(np.max(np.abs(want))))
+            assert err <= 1e-12, (label, done, err)
+            st = run.stats()
+            assert st["leaves"] == ora.n_leaves() and st["leaf_updates"] == ora.leaf_updates, (label, done)
+        return run.stats()
+    finally:
+        run.close()
+
+
+@pytest.mark.parametrize("physics,bc,gamma,kind", [
+    (A.ADVECTION, A.PERIODIC, 1, "bump"),
+    (A.BURGERS, A.PERIODIC, 1, "box"),
+    (A.BURGERS, A.CLAMP, 1, "box"),
+    (A.ADVECTION, A.CLAMP, 2, "box"),
+    (A.BURGERS, A.PERIODIC, 3, "bump"),
+])
+def test_2d_step_parity(physics, bc, gamma, kind):
+    jmin = 2 if gamma == 1 or bc == A.CLAMP else 3
+    p = params(physics, 6, 1e-3, bc=bc, gamma=gamma, jmin=jmin)
+    st = run_pair(p, datum(6, kind, seed=gamma), 24, 6, f"2d physics {physics} bc {bc} gamma {gamma} {kind}")
+    assert st["leaves"] < 4 ** 6
+
+
+def test_2d_rule_b_and_finer_levels():
+    """mu_bar = 1 and eps = 1e-4 on a steepening Burgers box at J = 7: rule (b) and the
+    grading at many levels."""
+    p = params(A.BURGERS, 7, 1e-4, mu_bar=1)
+    run_pair(p, datum(7, "box", seed=5), 30, 10, "2d rule b J7")
+
+
+def test_2d_eps_zero_is_the_uniform_scheme():
+    p = params(A.BURGERS, 6, 0.0)
+    u0 = datum(6, "box", seed=2)
+    announce("2d eps0")
+    run = mrlbm.MRLBM2D(p, u0)
+    try:
+        run.step(15)
+        sch = A.D2Q4(p["physics"], p["lam"], p["s"], V=p["V"])
+        ref = A.Uniform2D(sch, 6, p["bc"], u0).step(15)
+        assert run.stats()["leaves"] == 4 ** 6
+        assert np.array_equal(run.moments(), ref.conserved()[0])
+    finally:
+        run.close()
+
+
+def test_2d_larger_run():
+    """J = 8 (65536 finest cells), Burgers box, 24 steps: trees bit-exact, moments to 1e-12."""
+    p = params(A.BURGERS, 8, 1e-3)
+    run_pair(p, datum(8, "box", seed=7), 24, 12, "2d J8")
+
+
+def test_2d_validation():
+    """Refused on the host: a bad parameter set, J beyond 12, a wrongly shaped datum."""
+    p = params(A.ADVECTION, 6, 1e-3)
+    L = mrlbm.lib()
+    for key, val in (("gamma", 4), ("jmin", 0), ("eps", -1.0), ("lam", 0.0), ("s", [2.5, 1.0, 1.0])):
+        assert L.mrlbm2d_validate(mrlbm.make_params2d(dict(p, **{key: val}))) == mrlbm.EINVAL, key
+    assert L.mrlbm2d_validate(mrlbm.make_params2d(dict(p, jmax=13))) == mrlbm.ECAPACITY
+    with pytest.raises(ValueError):
+        mrlbm.MRLBM2D(p, np.zeros((32, 32)))
+    with pytest.raises(mrlbm.MRLBMError):
+        mrlbm.MRLBM2D(dict(p, eps=-1.0), np.zeros((64, 64)))

@@ -382,6 +382,58 @@ def test_bench_workload_in_bench_launch_configuration():
         ref.close()
 
 
+def test_launch_classes_do_not_change_results():
+    """Runs split into launch classes by j_max (each class its own grid, workgroup size and
+    on-chip capacity, the class grids side by side) give the bits of the single launch: graph
+    and direct launches, chunked launches, the oracle on one run per class; the tuner clears
+    the classes; bad class sets are refused."""
+    cases = [W.batch_instance(s, steps=0) for s in range(40)]
+    ps, ms = [c[0] for c in cases], [c[1] for c in cases]
+    announce("launch classes", sorted(p["jmax"] for p in ps))
+    a = mrlbm.Batch(ps, ms)
+    b = mrlbm.Batch(ps, ms)
+    try:
+        b.set_classes([10, 12, 14], [256, 512, 512], [8, 4, 2])
+        cl = b.get_classes()
+        assert len(cl) == 3 and sum(c[0] for c in cl) == len(cases)
+        assert sum(c[0] for c in cl[:1]) == sum(p["jmax"] <= 10 for p in ps)
+        a.step(30)
+        b.step(30)                       # graph launch
+        b.set_launch_steps(7)            # 20 steps as launches of 7, 7, 6
+        a.step(20)
+        b.step(20)
+        for i in range(len(cases)):
+            la, ia = a.leaves(i)
+            lb, ib = b.leaves(i)
+            assert np.array_equal(la, lb) and np.array_equal(ia, ib), i
+            assert np.array_equal(a.moments(i), b.moments(i)), i
+        assert a.total_updates() == b.total_updates()
+        b.set_launch_steps(0)
+        ms_ = b.step_timed(5)
+        a.step(5)
+        assert ms_ > 0 and a.total_updates() == b.total_updates()
+        for j_lo, j_hi in ((8, 10), (11, 12), (13, 14)):
+            i = next(k for k, p in enumerate(ps) if j_lo <= p["jmax"] <= j_hi)
+            ora = make_oracle(ps[i], ms[i]).step(55)
+            lv, ix = b.leaves(i)
+            olv, oix = ora.leaf_list()
+            assert np.array_equal(lv, olv) and np.array_equal(ix, oix), i
+            assert rel_err(b.moments(i), ora.leaf_conserved()) <= 1e-12, i
+        for bad in (([14, 12], [512, 512], [2, 4]), ([12], [512], [2]), ([14], [100], [2]), ([14], [512], [0])):
+            with pytest.raises(mrlbm.MRLBMError):
+                b.set_classes(*bad)
+        b.tune(3)
+        assert b.get_classes() == []
+        b.set_classes([14], [512], [2])
+        with pytest.raises(mrlbm.MRLBMError):
+            b.set_predictor(None, mrlbm.PRED_RECORD, sample_capacity=10)
+        b.set_classes()
+        assert b.get_classes() == []
+    finally:
+        a.close()
+        b.close()
+
+
 def test_checkpoint_restore_repeats_the_same_steps():
     """Steps taken after a restore give what the same steps gave after the checkpoint (bit
     for bit, statistics included); restore without a checkpoint is an error."""
