@@ -12,9 +12,12 @@ Protocol: the instances start at t = 0 on the full tree (Sec. 4.4); ``--warmup``
 advance them (the first of them, whose adaptation walks the full trees, is timed alone and
 reported as ``t0_step_ms``); the timed region is the ``--steps`` K steps that follow, as one
 launch (no restore: the timed steps continue the warmed-up runs). The launch shape is fixed
-(512 threads per workgroup, on-chip capacity 1722 cells = two instances per compute unit,
-heaviest instances first) so that the committed rocprofv3 counters describe the launch that
-is timed; the built-in tuner's choice is reported beside it.
+so that the committed rocprofv3 counters describe the launch that
+is timed: two launch classes, the runs with J <= 12 in workgroups of 128 threads sized for eight
+per compute unit and the J = 13, 14 runs in workgroups of 256 threads sized for four, the
+heaviest class first and both grids side by side, heaviest instances first within each (the
+step is latency bound: more, smaller workgroups per CU hide more of it); the built-in tuner's
+single-launch choice is reported beside it.
 
 Reported next to the throughput:
 * ``roofline``: algorithmic bytes (2 q s_b + 8 = 40 per leaf-cell update for D1Q2 FP64:
@@ -63,8 +66,10 @@ SALU_ISSUE_PER_S = CUS * CLOCK_HZ
 LDS_BYTES_PER_S = CUS * 128 * CLOCK_HZ
 
 ENSEMBLE_STEPS = 512
-HEADLINE_SHAPE = {"block": 512, "capacity": 1722}  # schedule: heaviest first (stride = runs)
-FP32_SHAPE = {"block": 512, "capacity": 3444}
+# launch classes of the headline: runs with J <= 12 in workgroups of 128 threads sized for 8 per
+# CU, the J = 13, 14 runs in workgroups of 256 threads sized for 4 per CU (heaviest class first)
+HEADLINE_CLASSES = ([12, 14], [128, 256], [8, 4])
+HEADLINE_SHAPE = {"block": 256, "capacity": 442}  # --no-classes: one launch, heaviest first
 KERNEL_SOURCES = ("mrlbm_device.h", "mrlbm_kernels.h", "instances.hip")
 COUNTER_FILE = os.path.join(ROOT, "profiles", "k_steps_ensemble4096_counters.txt")
 
@@ -211,9 +216,26 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def workload_key(runs, steps, warmup, block, capacity, schedule, prec):
-    return (f"ensemble runs={runs} steps={steps} warmup={warmup} block={block} capacity={capacity} "
+def workload_key(runs, steps, warmup, shape, schedule, prec):
+    """shape: 'block=B capacity=C' of a single launch, or the launch classes."""
+    return (f"ensemble runs={runs} steps={steps} warmup={warmup} {shape} "
             f"schedule={schedule} precision={'fp64' if prec == 0 else 'fp32'}")
+
+
+def launch_shape(b, classes):
+    """The launch shape of a batch as text (workload key) and as a config entry."""
+    if not classes:
+        return f"block={b.get_block()} capacity={b.get_capacity()}", None
+    got = b.get_classes()
+    rows = [{"j_max_upper": j, "threads": t, "runs_per_cu": r, "runs": n, "onchip_capacity_cells": c}
+            for (j, t, r), (n, c) in zip(zip(*classes), got)]
+    return classes_text(classes), rows
+
+
+def classes_text(classes):
+    """Launch classes as requested (j_max bound: threads x runs per CU); the capacities they
+    give follow from the device's LDS and are reported beside the key."""
+    return "classes=" + ";".join(f"j<={j}:{t}x{r}" for j, t, r in zip(*classes))
 
 
 def read_counters(path=COUNTER_FILE):
@@ -255,7 +277,8 @@ def counters_summary(spec):
     bench.py reads back. spec: comma-separated key=folder items: fetch, write (the bench
     command with FETCH_SIZE / WRITE_SIZE), cfetch, cwrite (the copy probe), sq (any number of
     folders with SQ_* counters), json (the bench line of the profiled run). The timed launch is
-    the last step-kernel dispatch of the run."""
+    the last step-kernel launch of the run: its last ``grids`` dispatches (one per launch
+    class, summed)."""
     items = [kv.split("=", 1) for kv in spec.split(",")]
     ks = "k_steps"
     line = None
@@ -273,7 +296,13 @@ def counters_summary(spec):
     w = _rows(d["write"], "WRITE_SIZE", ks)
     cf = _rows(d["cfetch"], "FETCH_SIZE", "copyBuffer")
     cw = _rows(d["cwrite"], "WRITE_SIZE", "copyBuffer")
-    fk, wk = f[max(f)], w[max(w)]
+    grids = int(line.get("roofline", {}).get("grids", 1))
+
+    def last(per):
+        ids = sorted(per)[-grids:]
+        return sum(per[i] for i in ids)
+
+    fk, wk = last(f), last(w)
     cfk = sum(cf.values()) / len(cf)
     cwk = sum(cw.values()) / len(cw)
     kib = (1 << 30) / 1024.0
@@ -282,7 +311,7 @@ def counters_summary(spec):
     upd = line["timed_updates"]
     print(f"kernel_source_sha256: {kernel_source_hash()}")
     print(f"workload_key: {line['workload_key']}")
-    print(f"dispatches_seen: {len(f)} (the timed launch is the last)")
+    print(f"dispatches_seen: {len(f)} (the timed launch is the last {grids}, summed)")
     print(f"fetch_kib: {fk:.1f}")
     print(f"write_kib: {wk:.1f}")
     print(f"copy_probe: 1 GiB per copy, fetch_kib {cfk:.1f} -> scale {sf:.4f}, write_kib {cwk:.1f} -> scale {sw:.4f}")
@@ -298,7 +327,7 @@ def counters_summary(spec):
                 names |= {r["Counter_Name"] for r in csv.DictReader(fh)}
         for n in sorted(names):
             rows = _rows(folder, n, ks)
-            print(f"{n}: {rows[max(rows)]:.1f}")
+            print(f"{n}: {last(rows):.1f}")
 
 
 def issue_block(kv, value):
@@ -398,6 +427,18 @@ def profile_summary(path):
         with open(f) as fh:
             rows = [r for r in csv.DictReader(fh) if "k_steps" in r["Kernel_Name"]]
         rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+        # launches: dispatches whose intervals overlap (the grids of one launch's classes run
+        # side by side) form one launch; its span is the last end minus the first start
+        spans = []
+        for r in rows:
+            a, e = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            if spans and a < spans[-1][1]:
+                spans[-1] = [spans[-1][0], max(spans[-1][1], e), spans[-1][2] + 1]
+            else:
+                spans.append([a, e, 1])
+        lines.append(f"step-kernel launches ({len(spans)}; overlapping dispatches are one launch; the first 12):")
+        for i, (a, e, k) in enumerate(spans[:12]):
+            lines.append(f"  L{i}: span {(e - a) / 1e6:10.4f} ms, {k} dispatch(es)")
         lines.append(f"step-kernel dispatches in launch order ({len(rows)} in all; the first 12):")
         for i, r in enumerate(rows[:12]):
             dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
@@ -556,12 +597,13 @@ def shallow_form(mrlbm, runs, steps=0):
 
 def ensemble_fp32(mrlbm, runs, warmup, steps):
     cases = ensemble_cases(runs, 1)
-    b = make_batch(mrlbm, cases, FP32_SHAPE["block"], FP32_SHAPE["capacity"], runs)
+    b = make_batch(mrlbm, cases)
+    b.set_classes(*HEADLINE_CLASSES)
+    _, class_rows = launch_shape(b, HEADLINE_CLASSES)
     ms, upd, t0 = timed_region(b, warmup, steps)
     b.close()
     return {"updates_per_s": upd / (ms / 1e3), "ms_per_step": ms / steps, "t0_step_ms": t0,
-            "threads_capacity_schedule": [FP32_SHAPE["block"], FP32_SHAPE["capacity"], runs],
-            "bytes_per_update": b_alg(2, 1)}
+            "launch_classes": class_rows, "bytes_per_update": b_alg(2, 1)}
 
 
 def main():
@@ -570,8 +612,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20, help="timed steps K (one launch)")
     ap.add_argument("--warmup", type=int, default=5, help="steps W from t = 0 before the timed region")
     ap.add_argument("--runs", type=int, default=4096, help="instances of the ensemble")
-    ap.add_argument("--block", type=int, default=HEADLINE_SHAPE["block"], help="threads per workgroup")
-    ap.add_argument("--capacity", type=int, default=HEADLINE_SHAPE["capacity"], help="on-chip capacity in cells")
+    ap.add_argument("--no-classes", action="store_true", help="one launch for all runs (--block, --capacity)")
+    ap.add_argument("--block", type=int, default=HEADLINE_SHAPE["block"], help="threads per workgroup (--no-classes)")
+    ap.add_argument("--capacity", type=int, default=HEADLINE_SHAPE["capacity"],
+                    help="on-chip capacity in cells (--no-classes)")
     ap.add_argument("--schedule", type=int, default=-1, help="schedule stride (-1: heaviest first)")
     ap.add_argument("--headline-only", action="store_true", help="only the headline (for profiling its launch)")
     ap.add_argument("--no-extras", action="store_true", help="skip every extra form")
@@ -630,7 +674,12 @@ def main():
     cases = ensemble_cases(args.runs, prec)
     print(f"[bench] ensemble of {len(cases)} instances, warmup {args.warmup}, timed {args.steps}", file=sys.stderr,
           flush=True)
-    b = make_batch(mrlbm, cases, args.block, args.capacity, schedule)
+    classes = None if args.no_classes else HEADLINE_CLASSES
+    if classes:
+        b = make_batch(mrlbm, cases)
+        b.set_classes(*classes)
+    else:
+        b = make_batch(mrlbm, cases, args.block, args.capacity, schedule)
     if extras:
         b.checkpoint()  # t = 0, for the whole-run leg
     ms, upd, t0 = timed_region(b, args.warmup, args.steps)
@@ -638,7 +687,9 @@ def main():
     leaves_now = np.array([b.stats(i)["leaves"] for i in range(len(cases))])
     js = np.array([c[0]["jmax"] for c in cases])
     print(f"[bench] timed launch {ms:.3f} ms, {upd} leaf-cell updates", file=sys.stderr, flush=True)
-    key = workload_key(args.runs, args.steps, args.warmup, b.get_block(), b.get_capacity(), b.get_schedule(), prec)
+    shape_text, class_rows = launch_shape(b, classes)
+    key = workload_key(args.runs, args.steps, args.warmup, shape_text, b.get_schedule(), prec)
+    grids = len(class_rows) if class_rows else 1
     kv = counters_for(key)
     bpu = b_alg(2, prec)
     achieved = upd * bpu / (ms / 1e3) / 1e9
@@ -660,9 +711,12 @@ def main():
                         "s in {1.5,1.9}), J_max uniform in 8..14, J_min=2, eps in {1e-3,1e-4}, gamma=1, periodic "
                         "[-1,1], seeded step+bump data, 512 steps each, one persistent launch",
             "runs": len(cases), "j_max_range": [int(js.min()), int(js.max())],
-            "threads_per_workgroup": b.get_block(), "onchip_capacity_cells": b.get_capacity(),
+            "launch_classes": class_rows,
+            "threads_per_workgroup": None if class_rows else b.get_block(),
+            "onchip_capacity_cells": None if class_rows else b.get_capacity(),
             "schedule_stride": b.get_schedule(),
-            "form": "timed steps continue the warmed-up runs (no restore), one launch replayed from a HIP graph",
+            "form": "timed steps continue the warmed-up runs (no restore), one launch replayed from a HIP graph"
+                    + (f" (its {grids} class grids side by side)" if class_rows else ""),
             "mean_leaves_per_instance": float(leaves_now.mean()),
         },
         "t0_step_ms": t0,
@@ -673,7 +727,8 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": float(kv["traffic_bytes_per_launch"]) if kv else None,
             "traffic_unit": "HBM bytes of the timed launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-probe scaled)",
-            "kernel": "k_steps<double,0,1>", "bytes_per_update": bpu, "launches": 1, "avg_launch_ms": ms,
+            "kernel": "k_steps<double,0,1>", "bytes_per_update": bpu, "launches": 1, "grids": grids,
+            "avg_launch_ms": ms,
             "issue": issue_block(kv, value),
         },
     }

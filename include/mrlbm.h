@@ -188,8 +188,8 @@ int mrlbm_batch_get_block(mrlbm_batch_t b, int32_t* threads);
  * get_capacity returns the capacity in use. */
 int mrlbm_batch_set_capacity(mrlbm_batch_t b, int32_t cells);
 /* Built-in tuner: times trial_steps steps of the batch for every candidate launch shape
- * (threads per workgroup 128/256/384/512 x LDS capacity for 1, 2 or 3 runs per compute
- * unit), then for every candidate schedule (see mrlbm_batch_set_schedule: identity, the
+ * (threads per workgroup 128/256/384/512 x LDS capacity for 1, 2, 3, 4 or 8 runs per compute
+ * unit, at most 32 waves per compute unit), then for every candidate schedule (see mrlbm_batch_set_schedule: identity, the
  * device's CU count, 8, heaviest first), restoring the runs' state after each trial, and
  * keeps the fastest (leaf-cell updates/s). The runs end in the state they had before the call. Allocates a
  * temporary snapshot of the handle's device memory. Chosen values are returned when the
@@ -223,7 +223,7 @@ int mrlbm_batch_get_capacity(mrlbm_batch_t b, int32_t* cells);
  * With n classes (1..4) the runs are split by j_max: class c holds the runs with
  * j_upper[c-1] < j_max <= j_upper[c] (j_upper increasing, the last one >= the largest j_max);
  * each class is advanced by a grid of its own with threads[c] per workgroup (64..512, a multiple
- * of 64) and the on-chip capacity that lets runs_per_cu[c] (1..8) of its workgroups share a
+ * of 64) and the on-chip capacity that lets runs_per_cu[c] (1..16) of its workgroups share a
  * compute unit's LDS. The class grids are forked from the handle's stream onto a second stream
  * of the same priority and joined back (in one captured graph), so they run side by side; within
  * a class the runs go heaviest first (mrlbm_batch_set_schedule then reorders within each class).

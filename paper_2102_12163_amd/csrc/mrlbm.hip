@@ -541,8 +541,11 @@ static int launch_classes(Engine* e, StepK sk, int nsteps, int mode) {
     hipError_t st;
     if ((st = hipEventRecord(e->evf, e->stream)) != hipSuccess) return hip_fail(e, st, "hipEventRecord(fork)");
     if ((st = hipStreamWaitEvent(e->side, e->evf, 0)) != hipSuccess) return hip_fail(e, st, "hipStreamWaitEvent(fork)");
+    // heaviest class first (on the handle's stream): its runs hold the most LDS, and the
+    // lighter classes fill what is left on each compute unit around them
     int k = 0;
-    for (const auto& c : e->cls) {
+    for (auto it = e->cls.rbegin(); it != e->cls.rend(); ++it) {
+        const auto& c = *it;
         if (c.count == 0) continue;
         hipStream_t s = (k++ % 2 == 0) ? e->stream : e->side;
         hipLaunchKernelGGL(sk, dim3(c.count), dim3(c.nt), c.lds, s, (const Desc*)e->dd, e->ds,
@@ -1183,8 +1186,11 @@ int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int
     if ((st = copy_all(true)) != hipSuccess) rc = hip_fail(e, st, "tune snapshot");
     // launch shape: threads per workgroup x runs per CU (which sets the on-chip capacity)
     const int nts[4] = {128, 256, 384, 512};
+    const int pcs[5] = {1, 2, 3, 4, 8};
     for (int ti = 0; ti < 4 && rc == MRLBM_OK; ++ti) {
-        for (int per_cu = 1; per_cu <= 3 && rc == MRLBM_OK; ++per_cu) {
+        for (int pi = 0; pi < 5 && rc == MRLBM_OK; ++pi) {
+            const int per_cu = pcs[pi];
+            if (per_cu * nts[ti] > 2048) continue;  // beyond 32 waves per CU
             e->nt_user = nts[ti];
             e->lds_budget = (full_budget + 1024) / per_cu - 1024;
             choose_capacity(e);
@@ -1309,8 +1315,8 @@ static int set_classes(Engine* e, int n, const int32_t* jup, const int32_t* thre
     for (auto& p : e->P) maxj = std::max(maxj, p.j_max);
     for (int c = 0; c < n; ++c) {
         if ((c > 0 && jup[c] <= jup[c - 1]) || threads[c] < 64 || threads[c] > 512 || threads[c] % 64 ||
-            per_cu[c] < 1 || per_cu[c] > 8) {
-            e->err = "classes: bounds must increase, threads in 64..512 (multiple of 64), runs per CU in 1..8";
+            per_cu[c] < 1 || per_cu[c] > 16) {
+            e->err = "classes: bounds must increase, threads in 64..512 (multiple of 64), runs per CU in 1..16";
             return MRLBM_EINVAL;
         }
     }

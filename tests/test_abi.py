@@ -196,8 +196,7 @@ def test_profile_summaries_match_the_kernel_sources():
     assert len(h) == 64
     kv = bench.read_counters()
     assert kv, "profiles/ holds no counter summary of the headline launch"
-    default_key = bench.workload_key(4096, 20, 5, bench.HEADLINE_SHAPE["block"], bench.HEADLINE_SHAPE["capacity"],
-                                     4096, 0)
+    default_key = bench.workload_key(4096, 20, 5, bench.classes_text(bench.HEADLINE_CLASSES), 4096, 0)
     assert kv["workload_key"] == default_key
     got = bench.counters_for(default_key)
     assert (kv["kernel_source_sha256"] == h) == (got is not None)
