@@ -426,6 +426,8 @@ def profile_summary(path):
     for f in sorted(glob.glob(os.path.join(path, "**", "*_kernel_trace.csv"), recursive=True)):
         with open(f) as fh:
             rows = [r for r in csv.DictReader(fh) if "k_steps" in r["Kernel_Name"]]
+        if not rows:
+            continue
         rows.sort(key=lambda r: int(r["Start_Timestamp"]))
         # launches: dispatches whose intervals overlap (the grids of one launch's classes run
         # side by side) form one launch; its span is the last end minus the first start
@@ -578,21 +580,49 @@ def learned_form(mrlbm, n_train, n_test, steps, jmax=14, eps=1e-4, pos_weight=16
 
 
 def shallow_form(mrlbm, runs, steps=0):
-    """The D1Q2^2 shallow-water dam break at its full size (J = 16, 65536 finest cells, clamp,
-    eps = 1e-4, s = 1.7, lambda = 2): ``runs`` seeded runs advanced together, ``steps`` steps
-    from t = 0 as one launch (0: the whole run to T = 0.4, 26214 steps)."""
-    cases = [W.shallow(seed, jmax=16) for seed in range(runs)]
-    n = steps or cases[0][0]["steps"]
-    b = make_batch(mrlbm, cases, 512)
-    ms = b.step_timed(n)
-    upd = b.total_updates()
-    st = [b.stats(i) for i in range(len(cases))]
-    out = {"runs": runs, "j_max": 16, "steps": n, "updates_per_s": upd / (ms / 1e3), "ms_per_step": ms / n,
-           "leaf_updates": upd, "threads_capacity": [b.get_block(), b.get_capacity()],
-           "mean_leaves_at_end": float(np.mean([x["leaves"] for x in st])),
-           "bytes_per_update": b_alg(4, 0)}
-    b.close()
+    """The shallow-water dam break at its full size (J = 16, 65536 finest cells, clamp,
+    eps = 1e-4, lambda = 2) with the D1Q2^2 scheme (s = 1.7) and with D1Q5 (Sec. 5.2.1:
+    alpha = beta = 1, s3 = s4 = 1, s2 = 1.5; its stream reaches two cells): ``runs`` seeded
+    runs of each advanced together, ``steps`` steps from t = 0 as one launch (0: the whole run
+    to T = 0.4, 26214 steps)."""
+    out = {}
+    for name, scheme, s, q in (("d1q2x2", W.D1Q2x2, 1.7, 4), ("d1q5", W.D1Q5, 1.5, 5)):
+        cases = [W.shallow(seed, jmax=16, scheme=scheme, s=s) for seed in range(runs)]
+        n = steps or cases[0][0]["steps"]
+        b = make_batch(mrlbm, cases, 512)
+        ms = b.step_timed(n)
+        upd = b.total_updates()
+        st = [b.stats(i) for i in range(len(cases))]
+        bpu = b_alg(q, 0)
+        out[name] = {"runs": runs, "j_max": 16, "steps": n, "updates_per_s": upd / (ms / 1e3), "ms_per_step": ms / n,
+                     "leaf_updates": upd, "threads_capacity": [b.get_block(), b.get_capacity()],
+                     "mean_leaves_at_end": float(np.mean([x["leaves"] for x in st])),
+                     "bytes_per_update": bpu, "algorithmic_gbs": upd * bpu / (ms / 1e3) / 1e9}
+        b.close()
     return out
+
+
+def two_d_form(mrlbm, jmax=12, warmup=5, steps=50):
+    """The two-dimensional step (D2Q4 Burgers, a seeded box on [0, 1]^2, J = 12: 2^24 finest
+    cells, eps = 1e-3): W steps from t = 0, then K steps timed with HIP events on the run's
+    stream. Algorithmic bytes per leaf-cell update as for the 1D step: the four populations
+    read and written once, a 4-byte key (72 B)."""
+    p, u0 = W.two_d(0, jmax=jmax)
+    run = mrlbm.MRLBM2D(p, u0)
+    try:
+        run.step(warmup)
+        u_before = run.stats()["leaf_updates"]
+        ms = run.step_timed(steps)
+        st = run.stats()
+    finally:
+        run.close()
+    upd = st["leaf_updates"] - u_before
+    bpu = b_alg(4, 0)
+    return {"j_max": jmax, "finest_cells": 4 ** jmax, "warmup": warmup, "steps": steps,
+            "updates_per_s": upd / (ms / 1e3), "ms_per_step": ms / steps, "leaves_at_end": st["leaves"],
+            "compression_pct": 100.0 * (1.0 - st["leaves"] / 4.0 ** jmax), "bytes_per_update": bpu,
+            "algorithmic_gbs": upd * bpu / (ms / 1e3) / 1e9,
+            "note": "dense levels in HBM, one kernel per phase and level: O(4^J) work per step"}
 
 
 def ensemble_fp32(mrlbm, runs, warmup, steps):
@@ -627,7 +657,7 @@ def main():
     ap.add_argument("--learned-steps", type=int, default=2400)
     ap.add_argument("--recon-steps", type=int, default=200)
     ap.add_argument("--shallow-runs", type=int, default=64, help="seeded J = 16 shallow-water runs")
-    ap.add_argument("--only", default="", choices=["", "fp32", "burgers", "shallow", "recon", "learned"],
+    ap.add_argument("--only", default="", choices=["", "fp32", "burgers", "shallow", "recon", "learned", "twod"],
                     help="only this extra form (for profiling its launches)")
     ap.add_argument("--profile-summary", default="", help="only summarize rocprofv3 CSV output in this folder")
     ap.add_argument("--counters-summary", default="", help="only print the counter block (see counters_summary)")
@@ -666,7 +696,8 @@ def main():
                 "burgers": lambda: burgers_form(mrlbm, args.burgers_seeds, args.warmup, args.steps, 0),
                 "shallow": lambda: shallow_form(mrlbm, args.shallow_runs),
                 "recon": lambda: reconstructed_form(mrlbm, args.burgers_seeds, args.recon_steps),
-                "learned": lambda: learned_form(mrlbm, 8, 64, args.learned_steps)}
+                "learned": lambda: learned_form(mrlbm, 8, 64, args.learned_steps),
+                "twod": lambda: two_d_form(mrlbm)}
         print(json.dumps({args.only: legs[args.only]()}))
         return 0
     prec = 0
@@ -777,6 +808,8 @@ def main():
         result["burgers_form"] = burgers_form(mrlbm, args.burgers_seeds, args.warmup, args.steps, 0)
         print("[bench] shallow water J=16", file=sys.stderr, flush=True)
         result["shallow_form"] = shallow_form(mrlbm, args.shallow_runs)
+        print("[bench] two dimensions J=12", file=sys.stderr, flush=True)
+        result["two_d_form"] = two_d_form(mrlbm)
         print("[bench] reconstructed collision", file=sys.stderr, flush=True)
         result["reconstructed_form"] = reconstructed_form(mrlbm, args.burgers_seeds, args.recon_steps)
         if not args.no_learned:

@@ -318,9 +318,13 @@ int mrlbm2d_validate(const mrlbm2d_params* p);
 /* u0: host array [2^J][2^J] (index i * 2^J + j, i along x) of finest cell averages at t = 0;
  * populations at equilibrium on the full tree. */
 int mrlbm2d_create(const mrlbm2d_params* p, const double* u0, void* hip_stream, mrlbm2d_t* out);
-/* nsteps time steps (adaptation, leaves collision, compact stream); synchronizes once per step to
- * count the leaves. */
+/* nsteps time steps (adaptation, leaves collision, compact stream), enqueued on the handle's
+ * stream; the leaf counts stay on the device and are read back once, at the end of the call
+ * (which synchronizes the stream). MRLBM_ENUMERIC when a value became NaN. */
 int mrlbm2d_step(mrlbm2d_t h, int32_t nsteps);
+/* mrlbm2d_step with the time between HIP events recorded on the handle's stream before the
+ * first and after the last step, in *ms. */
+int mrlbm2d_step_timed(mrlbm2d_t h, int32_t nsteps, float* ms);
 /* u reconstructed on every finest cell, out[i * 2^J + j] (cap >= 4^J). */
 int mrlbm2d_moments(mrlbm2d_t h, double* out, int64_t cap);
 /* split flags of level j_min <= level < j_max, out[i * 2^level + j] (cap >= 4^level). */

@@ -208,17 +208,21 @@ __global__ void k2_transfer(P2 p, int l, const uint8_t* old_split_l, const uint8
         fine[((size_t)h * m + ci) * m + cj] = predict_child(p, coarse, h, n, ci >> 1, cj >> 1, ci & 1, cj & 1);
 }
 
-// leaves collision at level l (cells of R not split); counts the leaves
+// leaves collision at level l (cells of R not split); counts the leaves (one atomic per wave)
 __global__ void k2_collide(P2 p, int l, const uint8_t* split_lm1, const uint8_t* split_l, double* F, unsigned long long* nleaf,
                            int* nan_flag) {
     const int n = 1 << l;
-    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= (size_t)n * n) return;
-    const int i = (int)(k / n), j = (int)(k % n);
-    const bool inR = !split_lm1 || split_lm1[(size_t)(i >> 1) * (n >> 1) + (j >> 1)];
-    const bool leaf = inR && !(split_l && split_l[k]);
-    if (!leaf) return;
     const size_t nn = (size_t)n * n;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool leaf = false;
+    if (k < nn) {
+        const int i = (int)(k / n), j = (int)(k % n);
+        const bool inR = !split_lm1 || split_lm1[(size_t)(i >> 1) * (n >> 1) + (j >> 1)];
+        leaf = inR && !(split_l && split_l[k]);
+    }
+    const unsigned long long wl = __ballot(leaf);
+    if ((threadIdx.x & 63) == 0 && wl) atomicAdd(nleaf, (unsigned long long)__popcll(wl));
+    if (!leaf) return;
     double f[Q2];
     for (int h = 0; h < Q2; ++h) f[h] = F[h * nn + k];
     collide4(p, f);
@@ -228,7 +232,11 @@ __global__ void k2_collide(P2 p, int l, const uint8_t* split_lm1, const uint8_t*
         F[h * nn + k] = f[h];
     }
     if (bad) *nan_flag = 1;
-    atomicAdd(nleaf, 1ull);
+}
+
+// leaf count of the step into the running total (cnt[0]: this step, cnt[1]: all steps)
+__global__ void k2_tally(unsigned long long* cnt) {
+    if (threadIdx.x == 0) cnt[1] += cnt[0];
 }
 
 // reconstruction from level l to l + 1: G_{l+1} = prediction of G_l, stored values on R
@@ -380,12 +388,13 @@ int step2d(Run2D* r) {
         hipLaunchKernelGGL(k2_transfer, dim3(blocks(N(l + 1) * N(l + 1))), dim3(256), 0, s, p, l, r->split[l - jmin],
                            r->nsplit[l - jmin], r->F[l - jmin], r->F[l + 1 - jmin]);
     std::swap(r->split, r->nsplit);
-    // 6. leaves collision
+    // 6. leaves collision (d_nleaf[0] counts this step's leaves)
     if (hipMemsetAsync(r->d_nleaf, 0, sizeof(unsigned long long), s) != hipSuccess) return MRLBM_EDEVICE;
     for (int l = jmin; l <= J; ++l)
         hipLaunchKernelGGL(k2_collide, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l,
                            l > jmin ? r->split[l - 1 - jmin] : (const uint8_t*)nullptr,
                            l < J ? r->split[l - jmin] : (const uint8_t*)nullptr, r->F[l - jmin], r->d_nleaf, r->d_nan);
+    hipLaunchKernelGGL(k2_tally, dim3(1), dim3(64), 0, s, r->d_nleaf);
     // 7. projection of the collided values, reconstruction on the finest level, stream
     for (int l = J - 1; l >= jmin; --l)
         hipLaunchKernelGGL(k2_project, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, (int)N(l), r->split[l - jmin],
@@ -405,13 +414,24 @@ int step2d(Run2D* r) {
                            l < J ? r->split[l - jmin] : (const uint8_t*)nullptr, ga, r->F[l - jmin]);
     hipError_t st = hipGetLastError();
     if (st != hipSuccess) return fail2d(r, st, "step launch");
-    unsigned long long nl = 0;
-    if ((st = hipMemcpyAsync(&nl, r->d_nleaf, sizeof(nl), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (st = hipStreamSynchronize(s)) != hipSuccess)
-        return fail2d(r, st, "step");
-    r->leaves = (long long)nl;
-    r->leaf_updates += (long long)nl;
     r->steps += 1;
+    return MRLBM_OK;
+}
+
+// After the steps of a call: this step's leaves, the running total and the NaN flag.
+int finish2d(Run2D* r) {
+    unsigned long long cnt[2] = {0, 0};
+    int nan = 0;
+    hipError_t st = hipMemcpyAsync(cnt, r->d_nleaf, sizeof(cnt), hipMemcpyDeviceToHost, r->stream);
+    if (st == hipSuccess) st = hipMemcpyAsync(&nan, r->d_nan, sizeof(int), hipMemcpyDeviceToHost, r->stream);
+    if (st == hipSuccess) st = hipStreamSynchronize(r->stream);
+    if (st != hipSuccess) return fail2d(r, st, "step");
+    if (r->steps > 0) r->leaves = (long long)cnt[0];
+    r->leaf_updates = (long long)cnt[1];
+    if (nan) {
+        r->numeric = true;
+        return MRLBM_ENUMERIC;
+    }
     return MRLBM_OK;
 }
 
@@ -518,7 +538,7 @@ int mrlbm2d_create(const mrlbm2d_params* q, const double* u0, void* hip_stream, 
     }
     void *g0 = nullptr, *g1 = nullptr, *o = nullptr, *nl = nullptr, *nf = nullptr, *ud = nullptr;
     if (!dalloc(&g0, sizeof(double) * Q2 * NJ * NJ) || !dalloc(&g1, sizeof(double) * Q2 * NJ * NJ) ||
-        !dalloc(&o, sizeof(double) * NJ * NJ) || !dalloc(&nl, sizeof(unsigned long long)) || !dalloc(&nf, sizeof(int)) ||
+        !dalloc(&o, sizeof(double) * NJ * NJ) || !dalloc(&nl, 2 * sizeof(unsigned long long)) || !dalloc(&nf, sizeof(int)) ||
         !dalloc(&ud, sizeof(double) * NJ * NJ))
         return fail("hipMalloc(work)");
     r->G0 = static_cast<double*>(g0);
@@ -527,6 +547,7 @@ int mrlbm2d_create(const mrlbm2d_params* q, const double* u0, void* hip_stream, 
     r->d_nleaf = static_cast<unsigned long long*>(nl);
     r->d_nan = static_cast<int*>(nf);
     if ((st = hipMemsetAsync(r->d_nan, 0, sizeof(int), r->stream)) != hipSuccess ||
+        (st = hipMemsetAsync(r->d_nleaf, 0, 2 * sizeof(unsigned long long), r->stream)) != hipSuccess ||
         (st = hipMemcpyAsync(ud, u0, sizeof(double) * NJ * NJ, hipMemcpyHostToDevice, r->stream)) != hipSuccess)
         return fail("upload");
     hipLaunchKernelGGL(k2_init, dim3(blocks(NJ * NJ)), dim3(256), 0, r->stream, p, (const double*)ud, r->F.back());
@@ -549,15 +570,25 @@ int mrlbm2d_step(mrlbm2d_t h, int32_t nsteps) {
         const int rc = step2d(r);
         if (rc != MRLBM_OK) return rc;
     }
-    int nan = 0;
-    hipError_t st = hipMemcpyAsync(&nan, r->d_nan, sizeof(int), hipMemcpyDeviceToHost, r->stream);
-    if (st == hipSuccess) st = hipStreamSynchronize(r->stream);
-    if (st != hipSuccess) return fail2d(r, st, "step");
-    if (nan) {
-        r->numeric = true;
-        return MRLBM_ENUMERIC;
-    }
-    return MRLBM_OK;
+    return finish2d(r);
+}
+
+int mrlbm2d_step_timed(mrlbm2d_t h, int32_t nsteps, float* ms) {
+    if (!h || nsteps < 0 || !ms) return MRLBM_EINVAL;
+    Run2D* r = h->r;
+    if (r->numeric) return MRLBM_ENUMERIC;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t st = hipEventCreate(&a);
+    if (st == hipSuccess) st = hipEventCreate(&b);
+    if (st == hipSuccess) st = hipEventRecord(a, r->stream);
+    int rc = st == hipSuccess ? MRLBM_OK : fail2d(r, st, "timing events");
+    for (int t = 0; t < nsteps && rc == MRLBM_OK; ++t) rc = step2d(r);
+    if (rc == MRLBM_OK && (st = hipEventRecord(b, r->stream)) != hipSuccess) rc = fail2d(r, st, "timing events");
+    if (rc == MRLBM_OK) rc = finish2d(r);
+    if ((rc == MRLBM_OK || rc == MRLBM_ENUMERIC) && hipEventElapsedTime(ms, a, b) != hipSuccess) *ms = 0.f;
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    return rc;
 }
 
 int mrlbm2d_moments(mrlbm2d_t h, double* out, int64_t cap) {

@@ -108,6 +108,7 @@ SIGNATURES = {
     "mrlbm2d_validate": (c_int32, [_P(Params2D)]),
     "mrlbm2d_create": (c_int32, [_P(Params2D), _P(c_double), c_void_p, _PP]),
     "mrlbm2d_step": (c_int32, [c_void_p, c_int32]),
+    "mrlbm2d_step_timed": (c_int32, [c_void_p, c_int32, _P(ctypes.c_float)]),
     "mrlbm2d_moments": (c_int32, [c_void_p, _P(c_double), c_int64]),
     "mrlbm2d_split": (c_int32, [c_void_p, c_int32, _P(ctypes.c_uint8), c_int64]),
     "mrlbm2d_stats": (c_int32, [c_void_p, _P(c_int64), _P(c_int64), _P(c_int64)]),
@@ -548,6 +549,12 @@ class MRLBM2D:
 
     def step(self, n=1):
         _check(lib().mrlbm2d_step(self.h, int(n)), self._err)
+
+    def step_timed(self, n=1):
+        """n steps; returns the milliseconds between HIP events around them."""
+        ms = ctypes.c_float()
+        _check(lib().mrlbm2d_step_timed(self.h, int(n), ctypes.byref(ms)), self._err)
+        return ms.value
 
     def moments(self):
         out = np.empty((self.n, self.n))

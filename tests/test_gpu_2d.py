@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import adaptive2d as A
+import workloads as W
 from paper_2102_12163_amd import mrlbm
 
 pytestmark = pytest.mark.gpu
@@ -121,3 +122,25 @@ def test_2d_validation():
         mrlbm.MRLBM2D(p, np.zeros((32, 32)))
     with pytest.raises(mrlbm.MRLBMError):
         mrlbm.MRLBM2D(dict(p, eps=-1.0), np.zeros((64, 64)))
+
+
+def test_2d_timed_steps_and_the_seeded_workload():
+    """The timed call takes the same steps as the plain one (trees, moments and leaf counts
+    equal) and reports a positive time; the seeded 2D workload of the benchmark at J = 7
+    matches the oracle."""
+    p, u0 = W.two_d(3, jmax=7)
+    announce("2d timed", p["jmax"])
+    a = mrlbm.MRLBM2D(p, u0)
+    b = mrlbm.MRLBM2D(p, u0)
+    try:
+        a.step(4)
+        ms = b.step_timed(4)
+        assert ms > 0.0
+        assert a.stats() == b.stats()
+        assert np.array_equal(a.moments(), b.moments())
+        for l in range(p["jmin"], p["jmax"]):
+            assert np.array_equal(a.split(l), b.split(l))
+    finally:
+        a.close()
+        b.close()
+    run_pair(p, u0, 12, 6, "2d seeded workload J7")

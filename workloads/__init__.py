@@ -23,6 +23,10 @@ Workload families (sizes as used throughout the tests and the benchmark):
 * ``batch``      D1Q2 advection/Burgers instances, J uniform in 8..14, eps in {1e-3, 1e-4}.
 * ``euler``      D1Q2^3, gamma_gas = 1.4, lambda = 3, s = 1.9, clamp [-1, 1], J 2..14,
                  eps = 1e-4, T = 0.4 (9830 steps); random Riemann problems and Sod.
+* ``two_d``      D2Q4 on [0, 1]^2 (the multi-D extension): Burgers (lambda = 2, s = 1.6, 1.6,
+                 1.2) or advection (V = (0.4, 0.25), lambda = 1, s = 1.5), periodic, J up to
+                 12, J_min = 2, eps = 1e-3; a seeded box or Gaussian bump (cell-centre
+                 samples).
 """
 
 import math
@@ -244,3 +248,22 @@ def mlp_constant_bits(logit):
     if np.any(u & 0xFFFF):
         raise ValueError("logit is not a bfloat16 value")
     return (u >> 16).astype(np.uint16)
+
+
+def two_d(seed, jmax=12, kind="box", physics=BURGERS, eps=1e-3, jmin=2, bc=PERIODIC):
+    """Parameters (the dict ``mrlbm.make_params2d`` takes) and the 2^J x 2^J datum of a seeded
+    2D run: 0.2 plus 0.5 times a box or a Gaussian bump, sampled at cell centres."""
+    rng = np.random.default_rng([20, seed])
+    x = (np.arange(2 ** jmax) + 0.5) / 2 ** jmax - 0.5
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    cx, cy = rng.uniform(-0.15, 0.15, 2)
+    if kind == "box":
+        a, b = rng.uniform(0.1, 0.25, 2)
+        u0 = 0.2 + 0.5 * ((np.abs(X - cx) < a) & (np.abs(Y - cy) < b))
+    else:
+        w = rng.uniform(0.01, 0.04)
+        u0 = 0.2 + 0.5 * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / w)
+    adv = physics == ADVECTION
+    p = dict(physics=physics, bc=bc, gamma=1, lam=1.0 if adv else 2.0, s=[1.5] * 3 if adv else [1.6, 1.6, 1.2],
+             V=(0.4, 0.25), jmin=jmin, jmax=jmax, mu_bar=0, eps=eps)
+    return p, u0
