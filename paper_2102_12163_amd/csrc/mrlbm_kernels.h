@@ -317,17 +317,18 @@ struct Block {
     }
 
     // Slot table of a tree (split bits sp, R bits, slot prefix RP, split-word list wl) written
-    // to dst (room for maxe words, in a dead part of a value array): NOFF words of per-level
-    // offsets (toff), then the split cells in level order, each as (own slot << 16) | slot of
-    // its even child, then their keys (level << 27) | p in the same order. The tree must fit
-    // on chip (slots < 2^16) and its split words must number at most NT and nwJ (pre uses
-    // scanE, free at this point); returns false otherwise, or when the table outgrows maxe
-    // (no table). Ends with a barrier when it returns true.
+    // to dst (room for maxe words, in a dead part of the LDS value arrays): NOFF words of
+    // per-level offsets (toff), then the split cells in level order, each as (own slot << 16) |
+    // slot of its even child, then their keys (level << 27) | p in the same order. Slots are
+    // ranks in R(Lambda), the same whether the values sit on chip or in HBM; they must fit 16
+    // bits (#R <= 2^16), and the split words must number at most NT and nwJ (pre uses scanE,
+    // free at this point); returns false otherwise, or when the table outgrows maxe (no
+    // table). Ends with a barrier when it returns true.
     DEV bool build_table(const uint64_t* sp, const uint64_t* R, const uint32_t* RP, WordList wl, LU* dst,
                          int maxe) {
         int first;
         const int ntask = list_tasks(wl, &first);
-        if (ntask > NT || ntask > lay.nwJ || (int)RP[wt] > lay.cap || lay.cap > 65535) return false;
+        if (ntask > NT || ntask > lay.nwJ || (int)RP[wt] > 65536 || lay.cap > 65535) return false;
         const int nlev = J - jmin + 1;
         int li = 0, fl = 0;  // level of task tid (waves that hold tasks)
         if (wave * 64 < ntask) {
@@ -1100,10 +1101,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
     // per-cell slot lookups
     // (the table sits in the free array B)
     bool tvalid = false;
-    if constexpr (!LRN)
+    const unsigned arrb = (unsigned)Q * (unsigned)cap * (unsigned)sizeof(T);  // one LDS value array
+    if constexpr (!LRN) {
         if (where == IN_LDS_A)
-            tvalid = B.build_table(B.split, B.ro, B.rpo, B.swl, (typename B_t::LU*)(lds + lay.VB),
-                                   (int)(((unsigned)Q * (unsigned)cap * sizeof(T)) / 4u));
+            tvalid = B.build_table(B.split, B.ro, B.rpo, B.swl, (typename B_t::LU*)(lds + lay.VB), (int)(arrb / 4u));
+        else if (cap > 0)  // values in HBM: both value arrays are free
+            tvalid = B.build_table(B.split, B.ro, B.rpo, B.swl, (typename B_t::LU*)(lds + lay.VA),
+                                   (int)((lay.VB + arrb - lay.VA) / 4u));
+    }
     const bool scheme = (mode & MODE_SCHEME) != 0;
     // reconstructed collision: only the RC instances carry its code (it would raise the
     // register count of every other kernel)
@@ -1111,7 +1116,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
     const bool judge = LRN && scheme && (d.pmode == 2 || (d.pmode == 1 && d.mlp != nullptr));
     long long upd = 0, misses = 0, redos = 0;
     int last = -1, lastn = -1;  // leaves of the last step's tree (scheme steps / any step)
-    bool last_fast = false;
+    bool last_lds_list = false;  // the last scheme step's leaf list is in LDS (B.ldsL)
     for (int stp = 0; stp < nsteps; ++stp) {
         // ---- projection of f^n up the old tree (once per step, kept through redos)
         if constexpr (LRN)
@@ -1122,7 +1127,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
             else B.project_up(VO, B.split, B.ro, B.rpo, B.swl);
         } else {
             VP<T, T> VO{hbm_vals<T>(d, where - IN_HBM_0), Cg};
-            B.project_up(VO, B.split, B.ro, B.rpo, B.swl);
+            if (tvalid) B.project_table(VO);
+            else B.project_up(VO, B.split, B.ro, B.rpo, B.swl);
         }
         int nwhere = where, n = 0;
         bool fast = false;
@@ -1143,7 +1149,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                 else B.details(VO, &s_nan);
             } else {
                 VP<T, T> VO{hbm_vals<T>(d, where - IN_HBM_0), Cg};
-                B.details(VO, &s_nan);
+                if (!LRN && tvalid) B.details_table(VO, &s_nan);
+                else B.details(VO, &s_nan);
             }
             __syncthreads();
             B.enlarge();
@@ -1220,20 +1227,75 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                 VP<T, T> VO{po, so};
                 VP<T, T> VN{pn, sn};
                 B.transfer(VO, VN, scheme && !recon, scheme, &s_nan);
-                if (scheme) {
+                // From here to the next transfer the LDS value arrays that do not hold the new
+                // values are free (the old array too, once the transfer has read it): the
+                // interface planes and the leaf list go there when they fit, as on chip, then
+                // the new tree's slot table; otherwise planes and list go to the run's HBM arrays
+                bool lds_lists = false;
+                if constexpr (!LRN) {
+                    unsigned f0 = 0, f1 = 0;
+                    if (cap > 0) {
+                        if (nwhere == IN_LDS_A) {
+                            f0 = lay.VB;
+                            f1 = lay.VB + arrb;
+                        } else if (nwhere == IN_LDS_B) {
+                            f0 = lay.VA;
+                            f1 = lay.VA + arrb;
+                        } else {
+                            f0 = lay.VA;
+                            f1 = lay.VB + arrb;
+                        }
+                    }
+                    const unsigned pe = (unsigned)(Planes<S>::PL * (n + 1)) * (unsigned)sizeof(T);
+                    unsigned toff_ = f0;
+                    if (scheme && f0 + pe + 4u * (unsigned)n <= f1) {
+                        lds_lists = true;
+                        B.ldsL = reinterpret_cast<uint32_t*>(lds + f0 + pe);
+                        toff_ = f0 + pe + 4u * (unsigned)n;
+                    }
+                    if (f1 > toff_)
+                        tvalid = B.build_table(B.nsplit, B.keep, B.rpn, B.nswl, (typename B_t::LU*)(lds + toff_),
+                                               (int)((f1 - toff_) / 4u));
+                    if (scheme && lds_lists) {
+                        B.scan_edges();
+                        B.write_list(B.ldsL, false);
+                        if constexpr (RC) {
+                            if (recon) {
+                                const bool sy = tvalid ? B.project_table(VN)
+                                                       : B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
+                                if (!sy) __syncthreads();
+                                B.recon_collide(VN, B.ldsL, reinterpret_cast<T*>(d.pairs), n, &s_nan);
+                            }
+                        }
+                        const bool synced =
+                            tvalid ? B.template project_table<MovingPops<S>, B_t::NM>(VN)
+                                   : B.template project_up<MovingPops<S>, B_t::NM>(VN, B.nsplit, B.keep, B.rpn, B.nswl);
+                        if (!synced) __syncthreads();
+                        LT* PB = (LT*)(T*)(lds + f0);
+                        B.pairs(VN, B.ldsL, PB, n);
+                        B.combine(VN, B.ldsL, PB, n);
+                    }
+                }
+                if (scheme && !lds_lists) {
                     B.scan_edges();
                     B.write_list(d.list);
                     T* P = reinterpret_cast<T*>(d.pairs);
                     if constexpr (RC && !LRN) {
                         if (recon) {
-                            if (!B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl)) __syncthreads();
+                            const bool sy = tvalid ? B.project_table(VN)
+                                                   : B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
+                            if (!sy) __syncthreads();
                             B.recon_collide(VN, d.list, P, n, &s_nan);
                         }
                     }
-                    B.template project_up<MovingPops<S>, B_t::NM>(VN, B.nsplit, B.keep, B.rpn, B.nswl);
+                    const bool synced =
+                        tvalid ? B.template project_table<MovingPops<S>, B_t::NM>(VN)
+                               : B.template project_up<MovingPops<S>, B_t::NM>(VN, B.nsplit, B.keep, B.rpn, B.nswl);
+                    if (!synced) __syncthreads();
                     B.pairs(VN, d.list, P, n);
                     B.combine(VN, d.list, P, n);
                 }
+                last_lds_list = lds_lists;
                 if constexpr (LRN) {
                     if (judge && (d.pmode == 2 || s_dec)) {
                         B.project_up(VN, B.nsplit, B.keep, B.rpn, B.nswl);
@@ -1260,7 +1322,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
         if (scheme) {
             upd += n;
             last = n;
-            last_fast = fast;
+            if (fast) last_lds_list = true;
         }
         if (threadIdx.x == 0) B.red[0] = 0;
         __syncthreads();
@@ -1276,11 +1338,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
             const int h = i / nR, s = i - h * nR;
             dst[(size_t)h * Cg + s] = src[h * cap + s];
         }
-        if (last >= 0 && last_fast)
-            for (int i = threadIdx.x; i < last; i += blockDim.x) d.list[i] = B.ldsL[i];
     } else {
         home = where - IN_HBM_0;
     }
+    if (last >= 0 && last_lds_list)
+        for (int i = threadIdx.x; i < last; i += blockDim.x) d.list[i] = B.ldsL[i];
     for (int w = threadIdx.x; w < wsplit; w += blockDim.x) d.split[w] = B.split[w];
     if (threadIdx.x == 0) {
         st.cur = home;
