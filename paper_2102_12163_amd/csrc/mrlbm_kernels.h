@@ -321,42 +321,26 @@ struct Block {
     // per-level offsets (toff), then the split cells in level order, each as (own slot << 16) |
     // slot of its even child, then their keys (level << 27) | p in the same order. Slots are
     // ranks in R(Lambda), the same whether the values sit on chip or in HBM; they must fit 16
-    // bits (#R <= 2^16), and the split words must number at most NT and nwJ (pre uses scanE,
-    // free at this point); returns false otherwise, or when the table outgrows maxe (no
-    // table). Ends with a barrier when it returns true.
+    // bits (#R <= 2^16). The cells of R above level jmin come in sibling pairs, in the order of
+    // their parents, so a split cell's place in the table is (slot of its even child - #R at
+    // level jmin) / 2 and the level offsets follow from the slot prefix: no scan. Returns false
+    // when the slots do not fit or the table outgrows maxe (no table); ends with a barrier when
+    // it returns true.
     DEV bool build_table(const uint64_t* sp, const uint64_t* R, const uint32_t* RP, WordList wl, LU* dst,
                          int maxe) {
-        int first;
-        const int ntask = list_tasks(wl, &first);
-        if (ntask > NT || ntask > lay.nwJ || (int)RP[wt] > 65536 || lay.cap > 65535) return false;
+        if ((int)RP[wt] > 65536 || lay.cap > 65535) return false;
         const int nlev = J - jmin + 1;
-        int li = 0, fl = 0;  // level of task tid (waves that hold tasks)
-        if (wave * 64 < ntask) {
-            for (int i = 0; i < nlev; ++i) {
-                const int fi = __builtin_amdgcn_readlane(first, i);
-                if (fi <= tid) {
-                    li = i;
-                    fl = fi;
-                }
-            }
-        }
-        uint32_t cnt = 0;
-        if (tid < ntask) {
-            const int l = jmin + li;
-            cnt = (uint32_t)__popcll(sp[WB(l) + wl.w[WB(l) + (tid - fl)]]);
-        }
-        uint32_t tot;
-        const uint32_t base = block_scan(cnt, &tot);  // tasks are in level order
-        if (2 * tot + NOFF > (uint32_t)maxe) return false;  // uniform: tot is the block total
+        const uint32_t base = RP[WB(jmin + 1)];  // the cells of level jmin
+        const uint32_t tot = (RP[wt] - base) >> 1;
+        if (2 * tot + NOFF > (uint32_t)maxe) return false;  // uniform
         toff = dst;
         tab = dst + NOFF;
         tabp = tab + tot;
-        uint32_t* pre = scanE;
-        if (tid < ntask) pre[tid] = base;
-        __syncthreads();
-        // level jmin + i starts at its first task's base; an empty level starts where the next
-        // task's level does (its range is empty); lane nlev holds the total
-        if (wave == 0 && lane <= nlev) toff[lane] = first < ntask ? pre[first] : tot;
+        // level jmin + i starts after the split cells of the levels below it, i.e. after half
+        // the cells of R at levels jmin + 1 .. jmin + i; lane nlev holds the total
+        if (wave == 0 && lane <= nlev) toff[lane] = lane < nlev ? (RP[WB(jmin + lane + 1)] - base) >> 1 : tot;
+        int first;
+        const int ntask = list_tasks(wl, &first);
         for (int task = wave; task < ntask; task += nwaves) {
             int t;
             const int l = task_level(task, first, &t);
@@ -366,7 +350,7 @@ struct Block {
                 const int p = (w << 6) + lane;
                 const uint32_t so = (uint32_t)rank_lane(R, RP, jmin, l, w);
                 const uint32_t sc = (uint32_t)rank_of(R, RP, jmin, l + 1, 2 * p);
-                const uint32_t e = pre[task] + popc_below_lane(b);
+                const uint32_t e = (sc - base) >> 1;
                 tab[e] = (so << 16) | sc;
                 tabp[e] = ((uint32_t)l << 27) | (uint32_t)p;
             }
