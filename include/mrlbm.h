@@ -179,13 +179,15 @@ int mrlbm_batch_stats(mrlbm_batch_t b, int32_t inst, mrlbm_stats_t* st);
 /* Sum of leaf_updates over all runs of the batch. Synchronizes. */
 int mrlbm_batch_total_updates(mrlbm_batch_t b, int64_t* total);
 /* Launch shape used by the batch: threads per workgroup (64..512, multiple of 64), 0 =
- * let the built-in tuner choose. Takes effect at the next step call. */
+ * let the built-in tuner choose. Takes effect at the next step call. MRLBM_ESTATE while
+ * launch classes are set (mrlbm_batch_set_classes: each class has its own shape). */
 int mrlbm_batch_set_block(mrlbm_batch_t b, int32_t threads);
 int mrlbm_batch_get_block(mrlbm_batch_t b, int32_t* threads);
 /* On-chip capacity: a run keeps the values of its tree in the workgroup's LDS while the tree
  * has at most this many cells of R(Lambda), and in its HBM arrays otherwise (same results).
  * cells = -1: the largest capacity the device's LDS allows (default); 0: always HBM.
- * get_capacity returns the capacity in use. */
+ * get_capacity returns the capacity of the single launch (the classes' own capacities come
+ * from mrlbm_batch_get_classes). MRLBM_ESTATE while launch classes are set. */
 int mrlbm_batch_set_capacity(mrlbm_batch_t b, int32_t cells);
 /* Built-in tuner: times trial_steps steps of the batch for every candidate launch shape
  * (threads per workgroup 128/256/384/512 x LDS capacity for 1, 2, 3, 4 or 8 runs per compute

@@ -1023,6 +1023,10 @@ int mrlbm_batch_total_updates(mrlbm_batch_t b, int64_t* total) {
 
 int mrlbm_batch_set_block(mrlbm_batch_t b, int32_t threads) {
     if (!b) return MRLBM_EINVAL;
+    if (!b->e->cls.empty()) {
+        b->e->err = "launch classes are set (each has its own block size): clear them first";
+        return MRLBM_ESTATE;
+    }
     if (threads != 0 && (threads < 64 || threads > 512 || threads % 64 != 0)) {
         b->e->err = "threads must be 0 or a multiple of 64 in 64..512";
         return MRLBM_EINVAL;
@@ -1033,6 +1037,10 @@ int mrlbm_batch_set_block(mrlbm_batch_t b, int32_t threads) {
 
 int mrlbm_batch_set_capacity(mrlbm_batch_t b, int32_t cells) {
     if (!b || cells < -1) return MRLBM_EINVAL;
+    if (!b->e->cls.empty()) {
+        b->e->err = "launch classes are set (each has its own capacity): clear them first";
+        return MRLBM_ESTATE;
+    }
     b->e->cap_user = cells;
     choose_capacity(b->e);
     return MRLBM_OK;

@@ -205,3 +205,76 @@ def test_profile_summaries_match_the_kernel_sources():
         iss = bench.issue_block(got, 1.0e9)
         assert iss["valu_per_update"] > 0 and iss["ceiling_updates_per_s"] > 0
         assert float(got["traffic_bytes_per_launch"]) > 0
+
+
+def _bench_module():
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod2", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    return bench
+
+
+def test_counter_block_sums_the_timed_launchs_class_dispatches(tmp_path, capsys):
+    """bench.py --counters-summary on synthetic rocprofv3 output: the timed launch is the last
+    `grids` step-kernel dispatches, summed; FETCH_SIZE and WRITE_SIZE are scaled by what the
+    copy probe reads for 1 GiB (here half and all of it: scales 2 and 1)."""
+    import csv
+    import json as _json
+    bench = _bench_module()
+
+    def write(folder, counter, kernel, per_dispatch):
+        os.makedirs(folder, exist_ok=True)
+        with open(os.path.join(folder, "run_counter_collection.csv"), "w", newline="") as fh:
+            w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+            w.writeheader()
+            for did, val in per_dispatch.items():
+                # two rows per dispatch (two XCD-level entries) that must be summed
+                for half in (0.25, 0.75):
+                    w.writerow({"Dispatch_Id": did, "Kernel_Name": kernel, "Counter_Name": counter,
+                                "Counter_Value": val * half})
+
+    ks = "void mrl::k_steps<double, 0, 1, false, false>(...)"
+    # six dispatches: three launches of two class grids; the last two are the timed launch
+    write(str(tmp_path / "f"), "FETCH_SIZE", ks, {1: 5.0, 2: 6.0, 3: 7.0, 4: 8.0, 5: 100.0, 6: 300.0})
+    write(str(tmp_path / "w"), "WRITE_SIZE", ks, {1: 1.0, 2: 1.0, 3: 1.0, 4: 1.0, 5: 1000.0, 6: 24.0})
+    kib = (1 << 30) / 1024.0
+    write(str(tmp_path / "cf"), "FETCH_SIZE", "__amd_rocclr_copyBuffer", {1: kib / 2, 2: kib / 2})
+    write(str(tmp_path / "cw"), "WRITE_SIZE", "__amd_rocclr_copyBuffer", {1: kib, 2: kib})
+    write(str(tmp_path / "sq"), "SQ_INSTS_VALU", ks, {1: 1.0, 2: 2.0, 3: 3.0, 4: 4.0, 5: 50.0, 6: 70.0})
+    line = {"timed_updates": 1000, "workload_key": "k", "roofline": {"grids": 2}}
+    with open(tmp_path / "line.json", "w") as fh:
+        fh.write("[bench] noise\n" + _json.dumps(line) + "\n")
+    spec = ",".join([f"fetch={tmp_path / 'f'}", f"write={tmp_path / 'w'}", f"cfetch={tmp_path / 'cf'}",
+                     f"cwrite={tmp_path / 'cw'}", f"sq={tmp_path / 'sq'}", f"json={tmp_path / 'line.json'}"])
+    bench.counters_summary(spec)
+    out = dict(l.split(":", 1) for l in capsys.readouterr().out.splitlines() if ":" in l)
+    assert float(out["fetch_kib"]) == 400.0 and float(out["write_kib"]) == 1024.0
+    want = (400.0 * 2.0 + 1024.0 * 1.0) * 1024.0
+    assert abs(float(out["traffic_bytes_per_launch"]) - want) <= 1e-6 * want
+    assert abs(float(out["traffic_bytes_per_update"]) - want / 1000) <= 1e-6 * want
+    assert float(out["SQ_INSTS_VALU"]) == 120.0
+
+
+def test_profile_summary_groups_overlapping_dispatches(tmp_path, capsys):
+    """The kernel-trace summary counts dispatches whose intervals overlap as one launch and
+    gives its span (last end minus first start)."""
+    import csv
+    bench = _bench_module()
+    fields = ["Kernel_Name", "Start_Timestamp", "End_Timestamp", "Grid_Size_X", "Workgroup_Size_X", "LDS_Block_Size",
+              "VGPR_Count", "Accum_VGPR_Count", "SGPR_Count", "Scratch_Size"]
+    ks = "void mrl::k_steps<double, 0, 1, false, false>(...)"
+    spans = [(0, 400), (100, 500), (1000, 1200), (1100, 1300), (2000, 4000), (2100, 5000)]
+    with open(tmp_path / "run_kernel_trace.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=fields)
+        w.writeheader()
+        for a, e in spans + [(6000, 6001)]:
+            w.writerow({"Kernel_Name": ks if a < 6000 else "other", "Start_Timestamp": a * 1000, "End_Timestamp": e * 1000,
+                        "Grid_Size_X": 256, "Workgroup_Size_X": 128, "LDS_Block_Size": 512, "VGPR_Count": 52,
+                        "Accum_VGPR_Count": 0, "SGPR_Count": 112, "Scratch_Size": 0})
+    bench.profile_summary(str(tmp_path))
+    text = capsys.readouterr().out
+    assert "step-kernel launches (3;" in text
+    assert "L0: span     0.5000 ms, 2 dispatch(es)" in text
+    assert "L2: span     3.0000 ms, 2 dispatch(es)" in text

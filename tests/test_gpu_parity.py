@@ -422,6 +422,10 @@ def test_launch_classes_do_not_change_results():
         for bad in (([14, 12], [512, 512], [2, 4]), ([12], [512], [2]), ([14], [100], [2]), ([14], [512], [0])):
             with pytest.raises(mrlbm.MRLBMError):
                 b.set_classes(*bad)
+        with pytest.raises(mrlbm.MRLBMError):
+            b.set_block(256)  # each class has its own shape
+        with pytest.raises(mrlbm.MRLBMError):
+            b.set_capacity(100)
         b.tune(3)
         assert b.get_classes() == []
         b.set_classes([14], [512], [2])
