@@ -186,14 +186,18 @@ struct Block {
     // ----------------------------------------------------------- tree structures
     // From split bits sp: R bits (R), slot prefix (RP, RP[wt] = #R), the list of nonzero
     // split words (sl) and, when LW is given, leaf bits LW = R & ~split, their word list and
-    // the leaf count in red[0]. Ends with a barrier.
-    DEV void build_tree(const uint64_t* sp, uint64_t* R, uint32_t* RP, WordList sl, uint64_t* LW, WordList ll) {
-        if (tid < 32) {
-            sl.c[tid] = 0;
-            if (LW) ll.c[tid] = 0;
+    // the leaf count in red[0]. Ends with a barrier. cleared: the caller has zeroed the word
+    // counts of sl and ll and red[0] before a barrier of its own.
+    DEV void build_tree(const uint64_t* sp, uint64_t* R, uint32_t* RP, WordList sl, uint64_t* LW, WordList ll,
+                        bool cleared = false) {
+        if (!cleared) {
+            if (tid < 32) {
+                sl.c[tid] = 0;
+                if (LW) ll.c[tid] = 0;
+            }
+            if (tid == 0 && LW) red[0] = 0;
+            __syncthreads();
         }
-        if (tid == 0 && LW) red[0] = 0;
-        __syncthreads();
         const int per = (wt + NT - 1) / NT;
         const int w0 = tid * per;
         uint32_t s = 0;
@@ -1126,6 +1130,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                     if (w < lay.ws) B.declined[w] = 0ull;
             }
             if (threadIdx.x == 0) s_dec = 0;
+            // the new tree's word counts and leaf count (dead since the last step's lists)
+            if (threadIdx.x < 32) {
+                B.nswl.c[threadIdx.x] = 0;
+                B.lwl.c[threadIdx.x] = 0;
+            }
+            if (threadIdx.x == 0) B.red[0] = 0;
             __syncthreads();
             if (where <= IN_LDS_B) {
                 VP<T, LT> VO{where == IN_LDS_A ? B.ldsA : B.ldsB, cap};
@@ -1139,7 +1149,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
             __syncthreads();
             B.enlarge();
             B.grade();
-            B.build_tree(B.nsplit, B.keep, B.rpn, B.nswl, B.ruleb, B.lwl);
+            B.build_tree(B.nsplit, B.keep, B.rpn, B.nswl, B.ruleb, B.lwl, true);
             const int nR = (int)B.rpn[lay.wt];
             n = (int)B.red[0];
             // ---- new values: on chip when the new tree fits
@@ -1308,8 +1318,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
             last = n;
             if (fast) last_lds_list = true;
         }
-        if (threadIdx.x == 0) B.red[0] = 0;
-        __syncthreads();
+        // no barrier here: every path above ends with one, and nothing until the next step's
+        // first barrier writes what another wave may still read
     }
     // ---- epilogue: home copy, tree, leaf list of the last step, statistics
     const int nR = (int)B.rpo[lay.wt];
