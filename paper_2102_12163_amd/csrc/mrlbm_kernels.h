@@ -328,10 +328,10 @@ struct Block {
     // bits (#R <= 2^16). The cells of R above level jmin come in sibling pairs, in the order of
     // their parents, so a split cell's place in the table is (slot of its even child - #R at
     // level jmin) / 2 and the level offsets follow from the slot prefix: no scan. Returns false
-    // when the slots do not fit or the table outgrows maxe (no table); ends with a barrier when
-    // it returns true.
+    // when the slots do not fit or the table outgrows maxe (no table); when it returns true it
+    // ends with a barrier, unless sync is false (the caller's next barrier orders the writes).
     DEV bool build_table(const uint64_t* sp, const uint64_t* R, const uint32_t* RP, WordList wl, LU* dst,
-                         int maxe) {
+                         int maxe, bool sync = true) {
         if ((int)RP[wt] > 65536 || lay.cap > 65535) return false;
         const int nlev = J - jmin + 1;
         const uint32_t base = RP[WB(jmin + 1)];  // the cells of level jmin
@@ -359,7 +359,7 @@ struct Block {
                 tabp[e] = ((uint32_t)l << 27) | (uint32_t)p;
             }
         }
-        __syncthreads();
+        if (sync) __syncthreads();
         return true;
     }
 
@@ -1105,38 +1105,47 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
     long long upd = 0, misses = 0, redos = 0;
     int last = -1, lastn = -1;  // leaves of the last step's tree (scheme steps / any step)
     bool last_lds_list = false;  // the last scheme step's leaf list is in LDS (B.ldsL)
+    // the adaptation's decision bits, the new tree's word counts and leaf count start cleared
+    // (all of them dead since the last step's lists were used)
+    auto clear_decisions = [&]() {
+        for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) {
+            B.keep[w] = 0ull;
+            B.ruleb[w] = 0ull;
+            if constexpr (LRN)
+                if (w < lay.ws) B.declined[w] = 0ull;
+        }
+        if (threadIdx.x == 0) s_dec = 0;
+        if (threadIdx.x < 32) {
+            B.nswl.c[threadIdx.x] = 0;
+            B.lwl.c[threadIdx.x] = 0;
+        }
+        if (threadIdx.x == 0) B.red[0] = 0;
+    };
     for (int stp = 0; stp < nsteps; ++stp) {
-        // ---- projection of f^n up the old tree (once per step, kept through redos)
+        // ---- projection of f^n up the old tree (once per step, kept through redos); the
+        // clearing touches none of its data, and its barriers order the clearing before the
+        // details
         if constexpr (LRN)
             for (int w = threadIdx.x; w < lay.ws; w += blockDim.x) B.forced[w] = 0ull;
+        clear_decisions();
+        bool psync;
         if (where <= IN_LDS_B) {
             VP<T, LT> VO{where == IN_LDS_A ? B.ldsA : B.ldsB, cap};
-            if (tvalid) B.project_table(VO);
-            else B.project_up(VO, B.split, B.ro, B.rpo, B.swl);
+            psync = tvalid ? B.project_table(VO) : B.project_up(VO, B.split, B.ro, B.rpo, B.swl);
         } else {
             VP<T, T> VO{hbm_vals<T>(d, where - IN_HBM_0), Cg};
-            if (tvalid) B.project_table(VO);
-            else B.project_up(VO, B.split, B.ro, B.rpo, B.swl);
+            psync = tvalid ? B.project_table(VO) : B.project_up(VO, B.split, B.ro, B.rpo, B.swl);
         }
+        if (!psync) __syncthreads();
         int nwhere = where, n = 0;
         bool fast = false;
         int attempt = 0;
         for (;;) {
-            // ---- adaptation on the old tree
-            for (int w = threadIdx.x; w < lay.wt; w += blockDim.x) {
-                B.keep[w] = 0ull;
-                B.ruleb[w] = 0ull;
-                if constexpr (LRN)
-                    if (w < lay.ws) B.declined[w] = 0ull;
+            // ---- adaptation on the old tree (a redo starts from cleared decisions again)
+            if (attempt > 0) {
+                clear_decisions();
+                __syncthreads();
             }
-            if (threadIdx.x == 0) s_dec = 0;
-            // the new tree's word counts and leaf count (dead since the last step's lists)
-            if (threadIdx.x < 32) {
-                B.nswl.c[threadIdx.x] = 0;
-                B.lwl.c[threadIdx.x] = 0;
-            }
-            if (threadIdx.x == 0) B.red[0] = 0;
-            __syncthreads();
             if (where <= IN_LDS_B) {
                 VP<T, LT> VO{where == IN_LDS_A ? B.ldsA : B.ldsB, cap};
                 if (!LRN && tvalid) B.details_table(VO, &s_nan);
@@ -1172,8 +1181,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                     const unsigned loff = (where == IN_LDS_A ? lay.VA : lay.VB) + (unsigned)pe * sizeof(T);
                     B.ldsL = reinterpret_cast<uint32_t*>(lds + loff);
                     const unsigned toff_ = loff + 4u * (unsigned)n;
+                    // a scheme step's edge scan follows: its barriers order the table writes
                     tvalid = B.build_table(B.nsplit, B.keep, B.rpn, B.nswl, (typename B_t::LU*)(lds + toff_),
-                                           (int)(((unsigned)(Q * cap - pe) * sizeof(T) - 4u * (unsigned)n) / 4u));
+                                           (int)(((unsigned)(Q * cap - pe) * sizeof(T) - 4u * (unsigned)n) / 4u),
+                                           !scheme);
                 }
                 if (scheme) {
                     B.scan_edges();
@@ -1249,7 +1260,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
                     }
                     if (f1 > toff_)
                         tvalid = B.build_table(B.nsplit, B.keep, B.rpn, B.nswl, (typename B_t::LU*)(lds + toff_),
-                                               (int)((f1 - toff_) / 4u));
+                                               (int)((f1 - toff_) / 4u), !scheme);
                     if (scheme && lds_lists) {
                         B.scan_edges();
                         B.write_list(B.ldsL, false);
