@@ -1333,12 +1333,21 @@ static int set_classes(Engine* e, int n, const int32_t* jup, const int32_t* thre
         return MRLBM_EINVAL;
     }
     hipError_t st;
-    if (n > 0 && !e->side) {
-        if ((st = hipStreamCreateWithFlags(&e->side, hipStreamNonBlocking)) != hipSuccess)
+    // the side stream and the fork/join events, each created once (a failed call leaves the
+    // ones it made, and the next call makes the rest)
+    if (n > 0) {
+        if (!e->side && (st = hipStreamCreateWithFlags(&e->side, hipStreamNonBlocking)) != hipSuccess) {
+            e->side = nullptr;
             return hip_fail(e, st, "hipStreamCreate(side)");
-        if ((st = hipEventCreateWithFlags(&e->evf, hipEventDisableTiming)) != hipSuccess ||
-            (st = hipEventCreateWithFlags(&e->evj, hipEventDisableTiming)) != hipSuccess)
+        }
+        if (!e->evf && (st = hipEventCreateWithFlags(&e->evf, hipEventDisableTiming)) != hipSuccess) {
+            e->evf = nullptr;
             return hip_fail(e, st, "hipEventCreate(classes)");
+        }
+        if (!e->evj && (st = hipEventCreateWithFlags(&e->evj, hipEventDisableTiming)) != hipSuccess) {
+            e->evj = nullptr;
+            return hip_fail(e, st, "hipEventCreate(classes)");
+        }
     }
     // steps in flight use the old class set
     if ((st = hipStreamSynchronize(e->stream)) != hipSuccess) return hip_fail(e, st, "classes");
