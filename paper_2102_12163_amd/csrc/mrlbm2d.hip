@@ -46,8 +46,13 @@ __device__ __forceinline__ double at(const double* f, int h, int n, int i, int j
     return f[((size_t)h * n + bci(i, n, bc)) * n + bci(j, n, bc)];
 }
 
-// Tensor-product prediction of child (2i + a, 2j + b) of (i, j): ((f + sa Qx) + sb Qy) + sa sb Qxy
-__device__ double predict_child(const P2& p, const double* f, int h, int n, int i, int j, int a, int b) {
+// The terms of the tensor-product prediction of the four children of (i, j) on plane h:
+// child (2i + a, 2j + b) is ((f + sa Qx) + sb Qy) + sa sb Qxy with sa = (-1)^a, sb = (-1)^b
+struct Terms {
+    double f, qx, qy, qxy;
+};
+
+__device__ Terms predict_terms(const P2& p, const double* f, int h, int n, int i, int j) {
     const int bc = p.bc;
     double qx = 0.0, qy = 0.0, qxy = 0.0;
     for (int al = 1; al <= p.gamma; ++al) {
@@ -65,8 +70,12 @@ __device__ double predict_child(const P2& p, const double* f, int h, int n, int 
             qxy = first ? t : qxy + t;
             first = false;
         }
+    return Terms{f[((size_t)h * n + i) * n + j], qx, qy, qxy};
+}
+
+__device__ __forceinline__ double child_value(const Terms& q, int a, int b) {
     const double sa = a ? -1.0 : 1.0, sb = b ? -1.0 : 1.0;
-    return ((f[((size_t)h * n + i) * n + j] + sa * qx) + sb * qy) + (sa * sb) * qxy;
+    return ((q.f + sa * q.qx) + sb * q.qy) + (sa * sb) * q.qxy;
 }
 
 // D2Q4 collision (the oracle's fixed order)
@@ -148,14 +157,16 @@ __global__ void k2_details(P2 p, int l, const uint8_t* split, const double* coar
     const int m = 2 * n;
     double D = 0.0;
     bool bad = false;
-    for (int h = 0; h < Q2; ++h)
+    for (int h = 0; h < Q2; ++h) {
+        const Terms q = predict_terms(p, coarse, h, n, i, j);
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b) {
-                const double pr = predict_child(p, coarse, h, n, i, j, a, b);
+                const double pr = child_value(q, a, b);
                 const double d = fabs(fine[((size_t)h * m + 2 * i + a) * m + 2 * j + b] - pr);
                 bad = bad || (d != d);
                 D = d > D ? d : D;
             }
+    }
     if (bad) *nan_flag = 1;
     const double thr = ldexp(p.eps, 2 * (l + 1 - p.J));
     const double thrb = ldexp(thr, p.mu_bar + 2);
@@ -195,17 +206,19 @@ __global__ void k2_grade(int a, int gamma, int bc, const uint8_t* sa, uint8_t* s
         for (int dj = -gamma; dj <= gamma; ++dj) sa1[(size_t)(bci(i + di, n, bc) >> 1) * h + (bci(j + dj, n, bc) >> 1)] = 1;
 }
 
-// transfer at level l + 1: cells of the new tree that the old tree lacked are predicted
+// transfer at level l + 1: the children of cells split in the new tree and not in the old one
+// are predicted (one thread per parent of level l)
 __global__ void k2_transfer(P2 p, int l, const uint8_t* old_split_l, const uint8_t* new_split_l, const double* coarse,
                             double* fine) {
     const int n = 1 << l, m = 2 * n;
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= (size_t)m * m) return;
-    const int ci = (int)(k / m), cj = (int)(k % m);
-    const size_t pk = (size_t)(ci >> 1) * n + (cj >> 1);
-    if (!new_split_l[pk] || old_split_l[pk]) return;
-    for (int h = 0; h < Q2; ++h)
-        fine[((size_t)h * m + ci) * m + cj] = predict_child(p, coarse, h, n, ci >> 1, cj >> 1, ci & 1, cj & 1);
+    if (k >= (size_t)n * n || !new_split_l[k] || old_split_l[k]) return;
+    const int i = (int)(k / n), j = (int)(k % n);
+    for (int h = 0; h < Q2; ++h) {
+        const Terms q = predict_terms(p, coarse, h, n, i, j);
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) fine[((size_t)h * m + 2 * i + a) * m + 2 * j + b] = child_value(q, a, b);
+    }
 }
 
 // leaves collision at level l (cells of R not split); counts the leaves (one atomic per wave)
@@ -239,38 +252,50 @@ __global__ void k2_tally(unsigned long long* cnt) {
     if (threadIdx.x == 0) cnt[1] += cnt[0];
 }
 
-// reconstruction from level l to l + 1: G_{l+1} = prediction of G_l, stored values on R
+// reconstruction from level l to l + 1: G_{l+1} = prediction of G_l, stored values on R (one
+// thread per parent of level l: the children of a split cell are in R, the others predicted)
 __global__ void k2_reconstruct(P2 p, int l, const uint8_t* split_l, const double* Gl, const double* Fl1, double* Gl1) {
     const int n = 1 << l, m = 2 * n;
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= (size_t)m * m) return;
-    const int ci = (int)(k / m), cj = (int)(k % m);
-    const bool inR = split_l[(size_t)(ci >> 1) * n + (cj >> 1)] != 0;
+    if (k >= (size_t)n * n) return;
+    const int i = (int)(k / n), j = (int)(k % n);
+    const bool inR = split_l[k] != 0;
     for (int h = 0; h < Q2; ++h) {
-        const size_t o = ((size_t)h * m + ci) * m + cj;
-        Gl1[o] = inR ? Fl1[o] : predict_child(p, Gl, h, n, ci >> 1, cj >> 1, ci & 1, cj & 1);
+        const size_t o0 = ((size_t)h * m + 2 * i) * m + 2 * j, o1 = o0 + m;
+        if (inR) {
+            Gl1[o0] = Fl1[o0];
+            Gl1[o0 + 1] = Fl1[o0 + 1];
+            Gl1[o1] = Fl1[o1];
+            Gl1[o1 + 1] = Fl1[o1 + 1];
+        } else {
+            const Terms q = predict_terms(p, Gl, h, n, i, j);
+            Gl1[o0] = child_value(q, 0, 0);
+            Gl1[o0 + 1] = child_value(q, 0, 1);
+            Gl1[o1] = child_value(q, 1, 0);
+            Gl1[o1 + 1] = child_value(q, 1, 1);
+        }
     }
 }
 
-// compact stream of the leaves of level l from the finest reconstruction G (N_J x N_J)
-__global__ void k2_stream(P2 p, int l, const uint8_t* split_lm1, const uint8_t* split_l, const double* G, double* F) {
+// compact stream of the leaf (l, i, j) from the finest reconstruction G (N_J x N_J): per
+// velocity h0 <= h < h1 the strip of finest values entering the leaf minus the strip leaving
+// it (each velocity reads and writes its own plane only)
+__device__ void stream_leaf(const P2& p, int l, int i, int j, const double* G, double* F, int h0 = 0, int h1 = Q2) {
     const int n = 1 << l, NJ = 1 << p.J, L = 1 << (p.J - l);
-    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= (size_t)n * n) return;
-    const int i = (int)(k / n), j = (int)(k % n);
-    const bool inR = !split_lm1 || split_lm1[(size_t)(i >> 1) * (n >> 1) + (j >> 1)];
-    if (!inR || (split_l && split_l[k])) return;
+    const size_t k = (size_t)i * n + j;
     const size_t nn = (size_t)n * n, NN = (size_t)NJ * NJ;
     const int x0 = i * L, y0 = j * L, bc = p.bc;
     const int wx[Q2] = {1, -1, 0, 0}, wy[Q2] = {0, 0, 1, -1};
     double out[Q2];
-    for (int h = 0; h < Q2; ++h) {
+    for (int h = h0; h < h1; ++h) {
         const double* g = G + h * NN;
         if (l == p.J) {
             out[h] = g[(size_t)bci(x0 - wx[h], NJ, bc) * NJ + bci(y0 - wy[h], NJ, bc)];
             continue;
         }
         double acc = 0.0;
+        // the terms are summed in strip order; the loads of the unrolled iterations go ahead
+#pragma unroll 8
         for (int t = 0; t < L; ++t) {
             double a, b;
             if (wx[h] != 0) {
@@ -288,7 +313,37 @@ __global__ void k2_stream(P2 p, int l, const uint8_t* split_lm1, const uint8_t* 
         }
         out[h] = F[h * nn + k] + ldexp(acc, -2 * (p.J - l));
     }
-    for (int h = 0; h < Q2; ++h) F[h * nn + k] = out[h];
+    for (int h = h0; h < h1; ++h) F[h * nn + k] = out[h];
+}
+
+// the leaves of level l < J, or of a J with no coarser level: one thread per cell, or with
+// per_velocity one per cell and velocity (long strips: the four sums side by side)
+__global__ void k2_stream_cells(P2 p, int l, const uint8_t* split_lm1, const uint8_t* split_l, const double* G,
+                                double* F, int per_velocity) {
+    const int n = 1 << l;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t k = per_velocity ? t / Q2 : t;
+    if (k >= (size_t)n * n) return;
+    const int i = (int)(k / n), j = (int)(k % n);
+    if (split_lm1 && !split_lm1[(size_t)(i >> 1) * (n >> 1) + (j >> 1)]) return;  // not in R
+    if (split_l && split_l[k]) return;                                              // not a leaf
+    if (per_velocity) {
+        const int h = (int)(t % Q2);
+        stream_leaf(p, l, i, j, G, F, h, h + 1);
+    } else {
+        stream_leaf(p, l, i, j, G, F);
+    }
+}
+
+// the leaves of the finest level J > jmin (strips of one cell): one thread per parent of level
+// J - 1, which streams its four children when it is split
+__global__ void k2_stream_finest(P2 p, const uint8_t* split_jm1, const double* G, double* F) {
+    const int n = 1 << p.J, np = n >> 1;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)np * np || !split_jm1[k]) return;
+    const int pi = (int)(k / np), pj = (int)(k % np);
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) stream_leaf(p, p.J, 2 * pi + a, 2 * pj + b, G, F);
 }
 
 // conserved moment u on the finest level from the reconstruction
@@ -385,7 +440,7 @@ int step2d(Run2D* r) {
                            r->nsplit[a - 1 - jmin]);
     // 5. transfer, coarse to fine; then the new tree replaces the old one
     for (int l = jmin; l < J; ++l)
-        hipLaunchKernelGGL(k2_transfer, dim3(blocks(N(l + 1) * N(l + 1))), dim3(256), 0, s, p, l, r->split[l - jmin],
+        hipLaunchKernelGGL(k2_transfer, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l, r->split[l - jmin],
                            r->nsplit[l - jmin], r->F[l - jmin], r->F[l + 1 - jmin]);
     std::swap(r->split, r->nsplit);
     // 6. leaves collision (d_nleaf[0] counts this step's leaves)
@@ -404,14 +459,22 @@ int step2d(Run2D* r) {
     if (hipMemcpyAsync(ga, r->F[0], sizeof(double) * Q2 * N(jmin) * N(jmin), hipMemcpyDeviceToDevice, s) != hipSuccess)
         return MRLBM_EDEVICE;
     for (int l = jmin; l < J; ++l) {
-        hipLaunchKernelGGL(k2_reconstruct, dim3(blocks(N(l + 1) * N(l + 1))), dim3(256), 0, s, p, l, r->split[l - jmin],
+        hipLaunchKernelGGL(k2_reconstruct, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l, r->split[l - jmin],
                            ga, r->F[l + 1 - jmin], gb);
         std::swap(ga, gb);
     }
-    for (int l = jmin; l <= J; ++l)
-        hipLaunchKernelGGL(k2_stream, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l,
-                           l > jmin ? r->split[l - 1 - jmin] : (const uint8_t*)nullptr,
-                           l < J ? r->split[l - jmin] : (const uint8_t*)nullptr, ga, r->F[l - jmin]);
+    for (int l = jmin; l < J; ++l) {
+        const int pv = J - l >= 4 ? 1 : 0;  // strips of 16 cells or more: a thread per velocity
+        hipLaunchKernelGGL(k2_stream_cells, dim3(blocks(N(l) * N(l) * (pv ? Q2 : 1))), dim3(256), 0, s, p, l,
+                           l > jmin ? r->split[l - 1 - jmin] : (const uint8_t*)nullptr, r->split[l - jmin], ga,
+                           r->F[l - jmin], pv);
+    }
+    if (J > jmin)
+        hipLaunchKernelGGL(k2_stream_finest, dim3(blocks(N(J - 1) * N(J - 1))), dim3(256), 0, s, p, r->split[J - 1 - jmin],
+                           ga, r->F[J - jmin]);
+    else
+        hipLaunchKernelGGL(k2_stream_cells, dim3(blocks(N(J) * N(J))), dim3(256), 0, s, p, J, (const uint8_t*)nullptr,
+                           (const uint8_t*)nullptr, ga, r->F[0], 0);
     hipError_t st = hipGetLastError();
     if (st != hipSuccess) return fail2d(r, st, "step launch");
     r->steps += 1;
@@ -608,7 +671,7 @@ int mrlbm2d_moments(mrlbm2d_t h, double* out, int64_t cap) {
     if (hipMemcpyAsync(ga, r->F[0], sizeof(double) * Q2 * N(p.jmin) * N(p.jmin), hipMemcpyDeviceToDevice, s) != hipSuccess)
         return MRLBM_EDEVICE;
     for (int l = p.jmin; l < p.J; ++l) {
-        hipLaunchKernelGGL(k2_reconstruct, dim3(blocks(N(l + 1) * N(l + 1))), dim3(256), 0, s, p, l,
+        hipLaunchKernelGGL(k2_reconstruct, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l,
                            r->split[l - p.jmin], ga, r->F[l + 1 - p.jmin], gb);
         std::swap(ga, gb);
     }
