@@ -675,9 +675,11 @@ DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, int jmin, int
         }
     }
     // ascent; once a window level holds no cell of R(Lambda), no finer window level does
-    // (their parents lie inside it), and the rest is prediction only
+    // (their parents lie inside it), and the rest is prediction only. The levels below L carry
+    // the whole window; level L, taken after the loop by every lane at once, only the NO
+    // output cells (tA .. tB, in range under clamp).
     bool anyr = true;
-    for (int l = l0 + 1; l <= L; ++l) {
+    for (int l = l0 + 1; l < L; ++l) {
         const int sh = L - l;
         const int u = (tA + 2 * G) >> sh;
         const int lo = u - 2 * G;
@@ -748,12 +750,59 @@ DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, int jmin, int
 #pragma unroll
             for (int i = 0; i < WM; ++i) win[m][i] = nw[m][i];
     }
-    // window position j is cell tA + j of level L (out[m * NO + j]; positions beyond tB - tA
-    // are not meaningful)
+    if (l0 < L) {
+        // level L: window position i is cell tA + i (lo = tA); its children come from the
+        // parents at window positions G .. G + NO / 2 of level L - 1, the same arithmetic
+        const int u = tA + 2 * G;
+        const bool par = (u & 1) != 0;
+        constexpr int NPAR = NO / 2 + 1;  // parents whose children reach positions 0 .. NO
+        static_assert(NPAR <= 2 * G + 1, "the outputs lie inside the window");
+        T kid[NP][2 * NPAR];
 #pragma unroll
-    for (int m = 0; m < NP; ++m)
+        for (int m = 0; m < NP; ++m)
 #pragma unroll
-        for (int j = 0; j < NO; ++j) out[m * NO + j] = win[m][j];
+            for (int j = 0; j < NPAR; ++j) {
+                T acc = (T)0;
+#pragma unroll
+                for (int a = 1; a <= G; ++a) {
+                    const T t = cc[a - 1] * (win[m][G + j + a] - win[m][G + j - a]);
+                    acc = (a == 1) ? t : acc + t;
+                }
+                kid[m][2 * j] = win[m][G + j] + acc;
+                kid[m][2 * j + 1] = win[m][G + j] - acc;
+            }
+        T nw[NP][NO];
+#pragma unroll
+        for (int i = 0; i < NO; ++i)
+#pragma unroll
+            for (int m = 0; m < NP; ++m) nw[m][i] = pick(par, kid[m][i + 1], kid[m][i]);
+        if (anyr) {
+            const int N = 1 << L;
+            const int wbl = wbase(jmin, L);
+#pragma unroll
+            for (int i = 0; i < NO; ++i) {
+                const int xx = bcx(tA + i, N, bc);
+                const int w = wbl + (xx >> 6);
+                const uint64_t rw = R[w];
+                if ((rw >> (xx & 63)) & 1ull) {
+                    const int s = (int)RP[w] + __popcll(rw & ((1ull << (xx & 63)) - 1ull));
+#pragma unroll
+                    for (int m = 0; m < NP; ++m) nw[m][i] = Vx.ld(PM::h(m), s);
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NP; ++m)
+#pragma unroll
+            for (int j = 0; j < NO; ++j) out[m * NO + j] = nw[m][j];
+    } else {
+        // window position j is cell tA + j of level L (positions beyond tB - tA are not
+        // meaningful)
+#pragma unroll
+        for (int m = 0; m < NP; ++m)
+#pragma unroll
+            for (int j = 0; j < NO; ++j) out[m * NO + j] = win[m][j];
+    }
 }
 
 }  // namespace mrl
