@@ -663,15 +663,28 @@ DEV void chain(const V& Vx, const uint64_t* R, const uint32_t* RP, int jmin, int
         const int hi = ((tB - 2 * G) >> sh) + 2 * G;
         const int N = 1 << l0;
         const int wbl = wbase(jmin, l0);
+        if (lo >= 0 && hi < N) {
+            // every window cell lies in R (the descent's condition, or level jmin) and R is
+            // ranked by index within a level: one rank, then consecutive slots
+            const int w = wbl + (lo >> 6);
+            const int s0 = (int)RP[w] + __popcll(R[w] & ((1ull << (lo & 63)) - 1ull));
 #pragma unroll
-        for (int i = 0; i < WM; ++i) {
-            const int xx = bcx(lo + i, N, bc);
-            const int w = wbl + (xx >> 6);
-            const uint64_t rw = R[w];
-            const bool ok = (i <= hi - lo) && ((rw >> (xx & 63)) & 1ull);
-            const int s = ok ? (int)RP[w] + __popcll(rw & ((1ull << (xx & 63)) - 1ull)) : 0;
+            for (int i = 0; i < WM; ++i) {
+                const bool ok = i <= hi - lo;
 #pragma unroll
-            for (int m = 0; m < NP; ++m) win[m][i] = ok ? Vx.ld(PM::h(m), s) : (T)0;
+                for (int m = 0; m < NP; ++m) win[m][i] = ok ? Vx.ld(PM::h(m), s0 + i) : (T)0;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < WM; ++i) {
+                const int xx = bcx(lo + i, N, bc);
+                const int w = wbl + (xx >> 6);
+                const uint64_t rw = R[w];
+                const bool ok = (i <= hi - lo) && ((rw >> (xx & 63)) & 1ull);
+                const int s = ok ? (int)RP[w] + __popcll(rw & ((1ull << (xx & 63)) - 1ull)) : 0;
+#pragma unroll
+                for (int m = 0; m < NP; ++m) win[m][i] = ok ? Vx.ld(PM::h(m), s) : (T)0;
+            }
         }
     }
     // ascent; once a window level holds no cell of R(Lambda), no finer window level does

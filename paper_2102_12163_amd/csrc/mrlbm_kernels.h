@@ -562,11 +562,20 @@ struct Block {
             const int N = 1 << l;
             const uint32_t en = tab[e];
             const int s0 = (int)(en >> 16), sc = (int)(en & 0xFFFFu);
+            // the tree is graded: the cells within gamma of a split cell at its level are in R,
+            // so their slots follow from its own (R is ranked by index within a level); across
+            // the periodic seam from the level's first or last slot, under clamp the edge cell
             int sp_[G], sm_[G];
 #pragma unroll
             for (int a = 1; a <= G; ++a) {
-                sp_[a - 1] = rank_of(ro, rpo, jmin, l, bcx(p + a, N, bc));
-                sm_[a - 1] = rank_of(ro, rpo, jmin, l, bcx(p - a, N, bc));
+                const int qp = p + a, qm = p - a;
+                if (bc == PERIODIC) {
+                    sp_[a - 1] = qp < N ? s0 + a : (int)rpo[WB(l)] + (qp - N);
+                    sm_[a - 1] = qm >= 0 ? s0 - a : (int)rpo[WB(l + 1)] + qm;
+                } else {
+                    sp_[a - 1] = s0 + ((qp < N ? qp : N - 1) - p);
+                    sm_[a - 1] = s0 + ((qm >= 0 ? qm : 0) - p);
+                }
             }
             double D = 0.0;
             bool bad = false;
