@@ -144,3 +144,11 @@ def test_2d_timed_steps_and_the_seeded_workload():
         a.close()
         b.close()
     run_pair(p, u0, 12, 6, "2d seeded workload J7")
+
+
+def test_2d_bench_workload_at_full_size():
+    """The benchmark's 2D workload at its full size (D2Q4 Burgers box, J = 12, 2^24 finest
+    cells), two steps: split flags of every level bit-exact and the finest moments within
+    1e-12 (the oracle takes about half a minute per step at this size)."""
+    p, u0 = W.two_d(0, jmax=12)
+    run_pair(p, u0, 2, 1, "2d bench workload J12")
