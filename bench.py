@@ -815,8 +815,10 @@ def main():
         v0 = b.total_updates()
         mst = b.step_timed(args.steps)
         result["tuner"] = {"threads_capacity_schedule": [tb, tc, b.get_schedule()],
+                           "classes": [list(c) for c in b.get_classes()],
                            "updates_per_s": (b.total_updates() - v0) / (mst / 1e3),
-                           "note": "the built-in tuner's launch shape for the timed steps, timed on the same steps"}
+                           "note": "the built-in tuner's launch shape for the timed steps (threads and capacity "
+                                   "0 when it chose launch classes), timed on the same steps"}
         b.close()
         cbw = copy_bandwidth()
         result["roofline"]["measured_copy_gbs"] = cbw

@@ -191,11 +191,16 @@ int mrlbm_batch_get_block(mrlbm_batch_t b, int32_t* threads);
 int mrlbm_batch_set_capacity(mrlbm_batch_t b, int32_t cells);
 /* Built-in tuner: times trial_steps steps of the batch for every candidate launch shape
  * (threads per workgroup 128/256/384/512 x LDS capacity for 1, 2, 3, 4 or 8 runs per compute
- * unit, at most 32 waves per compute unit), then for every candidate schedule (see mrlbm_batch_set_schedule: identity, the
- * device's CU count, 8, heaviest first), restoring the runs' state after each trial, and
- * keeps the fastest (leaf-cell updates/s). The runs end in the state they had before the call. Allocates a
- * temporary snapshot of the handle's device memory. Chosen values are returned when the
- * pointers are non-NULL. */
+ * unit, at most 32 waves per compute unit), then for every candidate schedule (see
+ * mrlbm_batch_set_schedule: identity, the device's CU count, 8, heaviest first); when the
+ * runs' j_max span three levels or more, also three two-class launches (see
+ * mrlbm_batch_set_classes: the runs up to j_max - 2 or j_max - 1 in 128-thread workgroups
+ * sized for eight per compute unit, the others in 256-thread workgroups for four, or in
+ * 512-thread workgroups for two). It restores the runs' state after each trial and keeps the
+ * fastest (leaf-cell updates/s); the runs end in the state they had before the call.
+ * Allocates a temporary snapshot of the handle's device memory. The chosen block size and
+ * capacity are returned when the pointers are non-NULL, both 0 when launch classes won
+ * (mrlbm_batch_get_classes has them). */
 int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int32_t* cells);
 /* Workgroup-to-run schedule of the batched launch (results do not depend on it). stride 0:
  * workgroup i advances run i. stride s > 0: runs ranked heaviest first by a-priori cost
@@ -229,8 +234,8 @@ int mrlbm_batch_get_capacity(mrlbm_batch_t b, int32_t* cells);
  * compute unit's LDS. The class grids are forked from the handle's stream onto a second stream
  * of the same priority and joined back (in one captured graph), so they run side by side; within
  * a class the runs go heaviest first (mrlbm_batch_set_schedule then reorders within each class).
- * Results do not depend on the classes. n = 0 restores the single launch; mrlbm_batch_tune clears
- * the classes (it tunes a single launch); not available with the refinement predictor
+ * Results do not depend on the classes. n = 0 restores the single launch; mrlbm_batch_tune
+ * replaces the classes with its own choice; not available with the refinement predictor
  * (MRLBM_EINVAL either way). get_classes returns the number of classes in *n and, for cap_n >= *n,
  * the runs and the on-chip capacity of each class. */
 int mrlbm_batch_set_classes(mrlbm_batch_t b, int32_t n, const int32_t* j_upper, const int32_t* threads,

@@ -81,6 +81,7 @@ struct Engine {
     size_t lds_query = 0;  // dynamic LDS of the query kernel
     int cap = 0, capS = 0; // on-chip capacity in R(Lambda) cells and in leaves
     size_t lds_budget = 0; // LDS bytes one workgroup may use
+    size_t lds_full = 0;   // the device's budget for one workgroup (lds_budget at create)
     int cap_user = -1;     // user limit on the on-chip capacity (-1: none)
     int maxJ = 0;
     int nt = 0;          // threads per workgroup in use
@@ -520,12 +521,15 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
     (void)hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     // static LDS of the kernels (word bases, counters) is below 1 KB
     e->lds_budget = (size_t)std::max(0, maxlds - 1024);
+    e->lds_full = e->lds_budget;
     choose_capacity(e);
-    (void)hipFuncSetAttribute((const void*)sk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)e->lds);
+    // the dynamic-LDS limit of a kernel is shared by every handle that launches it, so it is
+    // set to the device's whole budget, which no launch (single, class or query) exceeds
+    (void)hipFuncSetAttribute((const void*)sk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)e->lds_full);
     if (e->any_recon)
         (void)hipFuncSetAttribute((const void*)rc_kernel(e->prec, e->scheme), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)e->lds);
-    (void)hipFuncSetAttribute((const void*)qk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)e->lds_query);
+                                  (int)e->lds_full);
+    (void)hipFuncSetAttribute((const void*)qk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)e->lds_full);
     e->nt = default_block(e->maxJ);
     *out = e;
     return MRLBM_OK;
@@ -872,8 +876,10 @@ int run_noalloc(const mrlbm_params* p, const double* d_m0, int32_t nsteps, doubl
     int cap = 0, capS = 0;
     size_t lds = 0, lds_query = 0;
     single_capacity(d, (int)tsz, (size_t)std::max(0, maxlds - 1024), &cap, &capS, &lds, &lds_query);
-    if (hipFuncSetAttribute((const void*)sk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
-        hipFuncSetAttribute((const void*)qk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_query) != hipSuccess)
+    // the kernels' dynamic-LDS limit is the device's whole budget, as for the handles
+    const int lim = std::max(0, maxlds - 1024);
+    if (hipFuncSetAttribute((const void*)sk, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
+        hipFuncSetAttribute((const void*)qk, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
         return MRLBM_EDEVICE;
     hipStream_t stream = (hipStream_t)stream_;
     const int nt = default_block(p->j_max);
@@ -1140,6 +1146,8 @@ static int set_schedule(Engine* e, int stride) {
     return MRLBM_OK;
 }
 
+static int set_classes(Engine* e, int n, const int32_t* jup, const int32_t* threads, const int32_t* per_cu);
+
 int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int32_t* cells) {
     if (!b || trial_steps <= 0) return MRLBM_EINVAL;
     Engine* e = b->e;
@@ -1185,7 +1193,7 @@ int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int
         return MRLBM_OK;
     };
     const int saved_nt = e->nt_user;
-    const size_t full_budget = e->lds_budget;
+    const size_t full_budget = e->lds_full;  // a tuned handle's budget may be smaller
     const int saved_stride = e->sched_stride;
     int best_nt = 0;
     size_t best_budget = full_budget;
@@ -1235,9 +1243,52 @@ int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int
             }
         }
     }
+    // launch classes for a batch of uneven j_max: the runs up to j_max - 2 (or - 1) in small
+    // workgroups sized for many per CU, the others in larger ones, against the best single
+    // launch on the same steps
+    int best_cls = -1;
+    if (rc == MRLBM_OK && best_rate >= 0 && !e->lrn) {
+        int jlo = 30, jhi = 0;
+        for (auto& p : e->P) {
+            jlo = std::min(jlo, p.j_max);
+            jhi = std::max(jhi, p.j_max);
+        }
+        if (jhi - jlo >= 2) {
+            e->nt_user = best_nt;
+            e->lds_budget = best_budget;
+            choose_capacity(e);
+            double best_single = -1.0;
+            if ((rc = set_schedule(e, best_stride)) == MRLBM_OK) rc = trial(&best_single);
+            const int32_t cj[3][2] = {{jhi - 2, jhi}, {jhi - 1, jhi}, {jhi - 2, jhi}};
+            const int32_t ct[3][2] = {{128, 256}, {128, 256}, {128, 512}};
+            const int32_t cp[3][2] = {{8, 4}, {8, 4}, {8, 2}};
+            double best_c = best_single;
+            for (int c = 0; c < 3 && rc == MRLBM_OK; ++c) {
+                if ((rc = set_classes(e, 2, cj[c], ct[c], cp[c])) != MRLBM_OK) break;
+                double rate = 0.0;
+                if ((rc = trial(&rate)) != MRLBM_OK) break;
+                if (rate > best_c) {
+                    best_c = rate;
+                    best_cls = c;
+                }
+            }
+            if (rc == MRLBM_OK && best_cls >= 0) rc = set_classes(e, 2, cj[best_cls], ct[best_cls], cp[best_cls]);
+            else if (rc == MRLBM_OK) rc = set_classes(e, 0, nullptr, nullptr, nullptr);
+        }
+    }
     if ((st = hipStreamSynchronize(e->stream)) != hipSuccess && rc == MRLBM_OK) rc = hip_fail(e, st, "tune");
     (void)hipFree(snap);
     (void)hipFree(ssnap);
+    if (rc != MRLBM_OK && !e->cls.empty()) (void)set_classes(e, 0, nullptr, nullptr, nullptr);
+    if (rc == MRLBM_OK && best_cls >= 0) {
+        // the classes carry their own shapes; the single-launch settings stay the best ones
+        e->nt_user = best_nt;
+        e->lds_budget = best_budget;
+        choose_capacity(e);
+        if (threads) *threads = 0;
+        if (cells) *cells = 0;
+        return check_numeric(e);
+    }
     if (rc != MRLBM_OK || best_rate < 0) {
         e->nt_user = saved_nt;
         e->lds_budget = full_budget;
@@ -1354,13 +1405,13 @@ static int set_classes(Engine* e, int n, const int32_t* jup, const int32_t* thre
     const int tsz = e->prec == MRLBM_FP64 ? 8 : 4;
     e->cls.clear();
     int jlo = -1;
-    size_t lds_max = e->lds;
+
     for (int c = 0; c < n; ++c) {
         Engine::LaunchClass k;
         k.jhi = jup[c];
         k.nt = threads[c];
         k.per_cu = per_cu[c];
-        const size_t budget = (e->lds_budget + 1024) / (size_t)per_cu[c] - 1024;
+        const size_t budget = (e->lds_full + 1024) / (size_t)per_cu[c] - 1024;
         int cg_max = 0, jmin_min = 30;
         bool any = false;
         for (auto& d : e->hd)
@@ -1387,16 +1438,10 @@ static int set_classes(Engine* e, int n, const int32_t* jup, const int32_t* thre
         k.cap = lo;
         k.capS = lo > 0 ? lo / 2 + (1 << jmin_min) : 0;
         k.lds = any ? total(lo) : 0;
-        lds_max = std::max(lds_max, k.lds);
         e->cls.push_back(k);
         jlo = k.jhi;
     }
-    StepK sk;
-    QueryK qk;
-    InitK ik;
-    kernels_for(e->prec, e->scheme, e->gamma, &sk, &qk, &ik);
-    if (e->any_recon) sk = rc_kernel(e->prec, e->scheme);
-    (void)hipFuncSetAttribute((const void*)sk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
+    // (the step kernel's dynamic-LDS limit, set at create, is the whole budget)
     ++e->cls_gen;
     e->gsteps = -1;
     // the schedule array now holds the class segments (heaviest first within each class)
@@ -1484,7 +1529,7 @@ static int set_predictor(Engine* e, const uint16_t* params, int32_t mode, double
     choose_capacity(e);
     if (e->lrn)
         (void)hipFuncSetAttribute((const void*)lrn_kernel(e->scheme), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)e->lds);
+                                  (int)e->lds_full);
     e->gsteps = -1;  // the captured graph is stale
     return MRLBM_OK;
 }
