@@ -221,21 +221,7 @@ __global__ void k2_transfer(P2 p, int l, const uint8_t* old_split_l, const uint8
     }
 }
 
-// leaves collision at level l (cells of R not split); counts the leaves (one atomic per wave)
-__global__ void k2_collide(P2 p, int l, const uint8_t* split_lm1, const uint8_t* split_l, double* F, unsigned long long* nleaf,
-                           int* nan_flag) {
-    const int n = 1 << l;
-    const size_t nn = (size_t)n * n;
-    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool leaf = false;
-    if (k < nn) {
-        const int i = (int)(k / n), j = (int)(k % n);
-        const bool inR = !split_lm1 || split_lm1[(size_t)(i >> 1) * (n >> 1) + (j >> 1)];
-        leaf = inR && !(split_l && split_l[k]);
-    }
-    const unsigned long long wl = __ballot(leaf);
-    if ((threadIdx.x & 63) == 0 && wl) atomicAdd(nleaf, (unsigned long long)__popcll(wl));
-    if (!leaf) return;
+__device__ __forceinline__ bool collide_cell(const P2& p, double* F, size_t nn, size_t k) {
     double f[Q2];
     for (int h = 0; h < Q2; ++h) f[h] = F[h * nn + k];
     collide4(p, f);
@@ -244,6 +230,40 @@ __global__ void k2_collide(P2 p, int l, const uint8_t* split_lm1, const uint8_t*
         bad = bad || (f[h] != f[h]);
         F[h * nn + k] = f[h];
     }
+    return bad;
+}
+
+// leaves collision at level l (cells of R not split): one thread per parent of level l - 1,
+// which collides those of its four children that are leaves when it is split (level j_min, with
+// no parent level, one thread per cell); counts the leaves (one atomic per wave)
+__global__ void k2_collide(P2 p, int l, const uint8_t* split_lm1, const uint8_t* split_l, double* F, unsigned long long* nleaf,
+                           int* nan_flag) {
+    const int n = 1 << l;
+    const size_t nn = (size_t)n * n;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int cnt = 0;
+    bool bad = false;
+    if (!split_lm1) {
+        if (t < nn && !(split_l && split_l[t])) {
+            bad = collide_cell(p, F, nn, t);
+            cnt = 1;
+        }
+    } else {
+        const int m = n >> 1;
+        if (t < (size_t)m * m && split_lm1[t]) {
+            const int pi = (int)(t / m), pj = (int)(t % m);
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    const size_t k = (size_t)(2 * pi + a) * n + 2 * pj + b;
+                    if (split_l && split_l[k]) continue;
+                    bad = collide_cell(p, F, nn, k) || bad;
+                    ++cnt;
+                }
+        }
+    }
+    const unsigned long long c = (unsigned long long)__popcll(__ballot(cnt & 1)) +
+                                 2ull * __popcll(__ballot(cnt & 2)) + 4ull * __popcll(__ballot(cnt & 4));
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(nleaf, c);
     if (bad) *nan_flag = 1;
 }
 
@@ -252,29 +272,85 @@ __global__ void k2_tally(unsigned long long* cnt) {
     if (threadIdx.x == 0) cnt[1] += cnt[0];
 }
 
+// Flags of the children a parent's reconstruction must form: bit a (a = 0, 1) the children
+// (2i + a, .) on the x-velocity planes, bit 2 + b the children (., 2j + b) on the y-velocity
+// planes; NEED_ALL every child on every plane.
+constexpr uint8_t NEED_ALL = 15;
+
 // reconstruction from level l to l + 1: G_{l+1} = prediction of G_l, stored values on R (one
-// thread per parent of level l: the children of a split cell are in R, the others predicted)
-__global__ void k2_reconstruct(P2 p, int l, const uint8_t* split_l, const double* Gl, const double* Fl1, double* Gl1) {
+// thread per parent of level l: the children of a split cell are in R, the others predicted).
+// With need_l, only the children and planes it flags (the others are left as they were).
+__global__ void k2_reconstruct(P2 p, int l, const uint8_t* split_l, const uint8_t* need_l, const double* Gl,
+                               const double* Fl1, double* Gl1) {
     const int n = 1 << l, m = 2 * n;
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (size_t)n * n) return;
+    const int nb = need_l ? need_l[k] : NEED_ALL;
+    if (!nb) return;
     const int i = (int)(k / n), j = (int)(k % n);
     const bool inR = split_l[k] != 0;
     for (int h = 0; h < Q2; ++h) {
-        const size_t o0 = ((size_t)h * m + 2 * i) * m + 2 * j, o1 = o0 + m;
-        if (inR) {
-            Gl1[o0] = Fl1[o0];
-            Gl1[o0 + 1] = Fl1[o0 + 1];
-            Gl1[o1] = Fl1[o1];
-            Gl1[o1 + 1] = Fl1[o1 + 1];
-        } else {
-            const Terms q = predict_terms(p, Gl, h, n, i, j);
-            Gl1[o0] = child_value(q, 0, 0);
-            Gl1[o0 + 1] = child_value(q, 0, 1);
-            Gl1[o1] = child_value(q, 1, 0);
-            Gl1[o1 + 1] = child_value(q, 1, 1);
+        const int hb = h < 2 ? (nb & 3) : (nb >> 2);
+        if (!hb) continue;
+        Terms q{0.0, 0.0, 0.0, 0.0};
+        if (!inR) q = predict_terms(p, Gl, h, n, i, j);
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                if (!((hb >> (h < 2 ? a : b)) & 1)) continue;
+                const size_t o = ((size_t)h * m + 2 * i + a) * m + 2 * j + b;
+                Gl1[o] = inR ? Fl1[o] : child_value(q, a, b);
+            }
+    }
+}
+
+// Split flags of every level below J, by value (J <= 12).
+struct Splits {
+    const uint8_t* s[13];
+};
+
+// Which children of the parents of level J - 1 the stream reads. On an x-velocity plane a
+// leaf's stream reads the finest cells of its first and last columns and the cells just
+// outside them; those outside cells lie in the last or first column of the neighbouring
+// leaves (dyadic squares meet edge to edge), so the x planes are read exactly in the first
+// and last columns of every leaf, and the y planes in the first and last rows. The children
+// of a split parent are finest leaves (their own first and last columns and rows); for the
+// other parents the flags follow from their place in the coarser leaf that holds them.
+__global__ void k2_need_finest(P2 p, Splits sp, uint8_t* need) {
+    const int J = p.J, n = 1 << (J - 1);
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)n * n) return;
+    const int i = (int)(k / n), j = (int)(k % n);
+    uint8_t v = NEED_ALL;
+    if (!sp.s[J - 1 - p.jmin][k]) {
+        // the leaf holding the cell: its finest ancestor level whose parent is split
+        int l = J - 1;
+        while (l > p.jmin && !sp.s[l - 1 - p.jmin][(size_t)(i >> (J - l)) * ((size_t)1 << (l - 1)) + (j >> (J - l))]) --l;
+        const int h = 1 << (J - 1 - l);  // the leaf's side in level-(J - 1) cells
+        const int a = i & (h - 1), b = j & (h - 1);
+        v = (uint8_t)((a == 0) | ((a == h - 1) << 1) | ((b == 0) << 2) | ((b == h - 1) << 3));
+    }
+    need[k] = v;
+}
+
+// need_{l-1} from need_l: G_l is needed at the children of a parent of level l - 1 when one
+// of them lies in the (2 gamma + 1)^2 prediction box of a flagged, unsplit parent of level l
+// (whose children are predicted from G_l). The four children's boxes together cover the
+// (2 gamma + 2)^2 cells from (2i - gamma, 2j - gamma); a gather, so every entry is written.
+__global__ void k2_need_up(P2 p, int l, const uint8_t* split_l, const uint8_t* need_l, uint8_t* need_lm1) {
+    const int n = 1 << l, m = n >> 1;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)m * m) return;
+    const int i = (int)(k / m), j = (int)(k % m);
+    const int G = p.gamma;
+    bool v = false;
+    for (int di = -G; di <= G + 1 && !v; ++di) {
+        const size_t row = (size_t)bci(2 * i + di, n, p.bc) * n;
+        for (int dj = -G; dj <= G + 1; ++dj) {
+            const size_t q = row + bci(2 * j + dj, n, p.bc);
+            v = v || (need_l[q] && !split_l[q]);
         }
     }
+    need_lm1[k] = v ? NEED_ALL : 0;
 }
 
 // compact stream of the leaf (l, i, j) from the finest reconstruction G (N_J x N_J): per
@@ -335,6 +411,56 @@ __global__ void k2_stream_cells(P2 p, int l, const uint8_t* split_lm1, const uin
     }
 }
 
+// The value of v in lane t of the wave (t a constant).
+__device__ __forceinline__ double lane_value(double v, int t) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, t);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), t);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// the leaves of level l with strips of 64 cells or more: one wave per cell and velocity. The
+// lanes load 64 strip positions at a time and every lane folds their terms in strip order, so
+// the sum is the one stream_leaf forms.
+__global__ void k2_stream_strips(P2 p, int l, const uint8_t* split_lm1, const uint8_t* split_l, const double* G,
+                                 double* F) {
+    const int n = 1 << l, NJ = 1 << p.J, L = 1 << (p.J - l);
+    const size_t wv = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    const size_t k = wv / Q2;
+    const int h = (int)(wv % Q2);
+    if (k >= (size_t)n * n) return;
+    const int i = (int)(k / n), j = (int)(k % n);
+    if (split_lm1 && !split_lm1[(size_t)(i >> 1) * (n >> 1) + (j >> 1)]) return;  // not in R
+    if (split_l && split_l[k]) return;                                              // not a leaf
+    const size_t nn = (size_t)n * n, NN = (size_t)NJ * NJ;
+    const int x0 = i * L, y0 = j * L, bc = p.bc;
+    const int wx = h == 0 ? 1 : (h == 1 ? -1 : 0), wy = h == 2 ? 1 : (h == 3 ? -1 : 0);
+    const bool pos = (wx + wy) > 0;
+    const double* g = G + h * NN;
+    double acc = 0.0;
+    for (int c = 0; c < L; c += 64) {
+        const int t = c + lane;
+        double a, b;
+        if (wx != 0) {
+            const int y = bci(y0 + t, NJ, bc);
+            a = g[(size_t)bci(wx > 0 ? x0 - 1 : x0, NJ, bc) * NJ + y];
+            b = g[(size_t)bci(wx > 0 ? x0 + L - 1 : x0 + L, NJ, bc) * NJ + y];
+        } else {
+            const int x = bci(x0 + t, NJ, bc);
+            a = g[(size_t)x * NJ + bci(wy > 0 ? y0 - 1 : y0, NJ, bc)];
+            b = g[(size_t)x * NJ + bci(wy > 0 ? y0 + L - 1 : y0 + L, NJ, bc)];
+        }
+        const double term = pos ? (a - b) : -(a - b);
+#pragma unroll
+        for (int u = 0; u < 64; ++u) {
+            const double x = lane_value(term, u);
+            acc = (c == 0 && u == 0) ? x : acc + x;
+        }
+    }
+    if (lane == 0) F[h * nn + k] = F[h * nn + k] + ldexp(acc, -2 * (p.J - l));
+}
+
 // the leaves of the finest level J > jmin (strips of one cell): one thread per parent of level
 // J - 1, which streams its four children when it is split
 __global__ void k2_stream_finest(P2 p, const uint8_t* split_jm1, const double* G, double* F) {
@@ -361,6 +487,7 @@ struct Run2D {
     std::vector<double*> F;      // per level, q x N_l x N_l
     std::vector<uint8_t*> split; // per level < J
     std::vector<uint8_t*> nsplit, keep, ruleb;
+    std::vector<uint8_t*> need;  // per level < J: parents whose children the stream needs
     double* G0 = nullptr;        // reconstruction ping-pong (finest size)
     double* G1 = nullptr;
     double* out = nullptr;       // finest conserved moment
@@ -446,7 +573,7 @@ int step2d(Run2D* r) {
     // 6. leaves collision (d_nleaf[0] counts this step's leaves)
     if (hipMemsetAsync(r->d_nleaf, 0, sizeof(unsigned long long), s) != hipSuccess) return MRLBM_EDEVICE;
     for (int l = jmin; l <= J; ++l)
-        hipLaunchKernelGGL(k2_collide, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l,
+        hipLaunchKernelGGL(k2_collide, dim3(blocks(l > jmin ? N(l - 1) * N(l - 1) : N(l) * N(l))), dim3(256), 0, s, p, l,
                            l > jmin ? r->split[l - 1 - jmin] : (const uint8_t*)nullptr,
                            l < J ? r->split[l - jmin] : (const uint8_t*)nullptr, r->F[l - jmin], r->d_nleaf, r->d_nan);
     hipLaunchKernelGGL(k2_tally, dim3(1), dim3(64), 0, s, r->d_nleaf);
@@ -454,20 +581,35 @@ int step2d(Run2D* r) {
     for (int l = J - 1; l >= jmin; --l)
         hipLaunchKernelGGL(k2_project, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, (int)N(l), r->split[l - jmin],
                            r->F[l + 1 - jmin], r->F[l - jmin]);
+    // the reconstruction is formed only where the stream reads it: the flags go from the
+    // finest level's boundary rings up through the prediction boxes
+    if (J > jmin) {
+        Splits sp{};
+        for (int l = jmin; l < J; ++l) sp.s[l - jmin] = r->split[l - jmin];
+        hipLaunchKernelGGL(k2_need_finest, dim3(blocks(N(J - 1) * N(J - 1))), dim3(256), 0, s, p, sp, r->need[J - 1 - jmin]);
+        for (int l = J - 1; l > jmin; --l)
+            hipLaunchKernelGGL(k2_need_up, dim3(blocks(N(l - 1) * N(l - 1))), dim3(256), 0, s, p, l, r->split[l - jmin],
+                               (const uint8_t*)r->need[l - jmin], r->need[l - 1 - jmin]);
+    }
     double* ga = r->G0;
     double* gb = r->G1;
     if (hipMemcpyAsync(ga, r->F[0], sizeof(double) * Q2 * N(jmin) * N(jmin), hipMemcpyDeviceToDevice, s) != hipSuccess)
         return MRLBM_EDEVICE;
     for (int l = jmin; l < J; ++l) {
         hipLaunchKernelGGL(k2_reconstruct, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l, r->split[l - jmin],
-                           ga, r->F[l + 1 - jmin], gb);
+                           (const uint8_t*)r->need[l - jmin], ga, r->F[l + 1 - jmin], gb);
         std::swap(ga, gb);
     }
     for (int l = jmin; l < J; ++l) {
+        const uint8_t* slm1 = l > jmin ? r->split[l - 1 - jmin] : (const uint8_t*)nullptr;
+        if (J - l >= 6) {  // strips of 64 cells or more: a wave per cell and velocity
+            hipLaunchKernelGGL(k2_stream_strips, dim3(blocks(N(l) * N(l) * Q2 * 64)), dim3(256), 0, s, p, l, slm1,
+                               r->split[l - jmin], ga, r->F[l - jmin]);
+            continue;
+        }
         const int pv = J - l >= 4 ? 1 : 0;  // strips of 16 cells or more: a thread per velocity
-        hipLaunchKernelGGL(k2_stream_cells, dim3(blocks(N(l) * N(l) * (pv ? Q2 : 1))), dim3(256), 0, s, p, l,
-                           l > jmin ? r->split[l - 1 - jmin] : (const uint8_t*)nullptr, r->split[l - jmin], ga,
-                           r->F[l - jmin], pv);
+        hipLaunchKernelGGL(k2_stream_cells, dim3(blocks(N(l) * N(l) * (pv ? Q2 : 1))), dim3(256), 0, s, p, l, slm1,
+                           r->split[l - jmin], ga, r->F[l - jmin], pv);
     }
     if (J > jmin)
         hipLaunchKernelGGL(k2_stream_finest, dim3(blocks(N(J - 1) * N(J - 1))), dim3(256), 0, s, p, r->split[J - 1 - jmin],
@@ -589,13 +731,14 @@ int mrlbm2d_create(const mrlbm2d_params* q, const double* u0, void* hip_stream, 
         if ((st = hipMemsetAsync(f, 0, sizeof(double) * Q2 * nn, r->stream)) != hipSuccess) return fail("hipMemset");
         r->F.push_back(static_cast<double*>(f));
         if (l < p.J) {
-            void* a[4] = {nullptr, nullptr, nullptr, nullptr};
-            for (int t = 0; t < 4; ++t)
+            void* a[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+            for (int t = 0; t < 5; ++t)
                 if (!dalloc(&a[t], nn)) return fail("hipMalloc(split)");
             r->split.push_back(static_cast<uint8_t*>(a[0]));
             r->nsplit.push_back(static_cast<uint8_t*>(a[1]));
             r->keep.push_back(static_cast<uint8_t*>(a[2]));
             r->ruleb.push_back(static_cast<uint8_t*>(a[3]));
+            r->need.push_back(static_cast<uint8_t*>(a[4]));
             hipLaunchKernelGGL(k2_fill, dim3(blocks(nn)), dim3(256), 0, r->stream, r->split.back(), nn, (uint8_t)1);
         }
     }
@@ -672,7 +815,7 @@ int mrlbm2d_moments(mrlbm2d_t h, double* out, int64_t cap) {
         return MRLBM_EDEVICE;
     for (int l = p.jmin; l < p.J; ++l) {
         hipLaunchKernelGGL(k2_reconstruct, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l,
-                           r->split[l - p.jmin], ga, r->F[l + 1 - p.jmin], gb);
+                           r->split[l - p.jmin], (const uint8_t*)nullptr, ga, r->F[l + 1 - p.jmin], gb);
         std::swap(ga, gb);
     }
     hipLaunchKernelGGL(k2_moment, dim3(blocks(NJ * NJ)), dim3(256), 0, s, (int)NJ, (const double*)ga, r->out);
