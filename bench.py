@@ -641,7 +641,7 @@ def two_d_form(mrlbm, jmax=12, warmup=5, steps=50):
             "updates_per_s": upd / (ms / 1e3), "ms_per_step": ms / steps, "leaves_at_end": st["leaves"],
             "compression_pct": 100.0 * (1.0 - st["leaves"] / 4.0 ** jmax), "bytes_per_update": bpu,
             "algorithmic_gbs": upd * bpu / (ms / 1e3) / 1e9,
-            "note": "dense levels in HBM, one kernel per phase and level: O(4^J) work per step"}
+            "note": "dense levels in HBM, level-wide phases (independent levels fused, coarse levels in one workgroup): O(4^J) work per step"}
 
 
 def ensemble_fp32(mrlbm, runs, warmup, steps):

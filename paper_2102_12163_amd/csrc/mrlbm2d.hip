@@ -5,11 +5,14 @@
 //
 // Layout: dense levels in device memory. Level l (J_min <= l <= J) holds q planes of
 // N_l x N_l values (index (h * N_l + i) * N_l + j, i along x) and, below J, one byte per cell
-// for "split" (the cell has four children). A step is a sequence of level-wide kernels:
+// for "split" (the cell has four children). A step is a sequence of level-wide phases:
 // projection up the tree, details and thresholds, the two enlargement rules, the grading
 // sweep from fine to coarse, the data transfer from coarse to fine, the leaves collision, the
-// projection of the collided values, the reconstruction on the finest level and the compact
-// stream (for each leaf and velocity the difference of the strips entering and leaving it).
+// projection of the collided values, the reconstruction on the finest level (only of the cells
+// the stream reads) and the compact stream (for each leaf and velocity the difference of the
+// strips entering and leaving it). A phase whose levels are independent runs as one launch
+// over all of them; a level-serial phase runs one launch per fine level and sweeps the coarse
+// levels in a single workgroup.
 // Every expression is written in the order the FP64 checks use, with no contraction into
 // fused multiply-adds (the build passes -ffp-contract=off), so that the threshold decisions
 // and the values agree bit for bit.
@@ -130,29 +133,38 @@ __global__ void k2_fill(uint8_t* s, size_t n, uint8_t v) {
     if (k < n) s[k] = v;
 }
 
-// projection of the split cells of level l from level l + 1
-__global__ void k2_project(int n, const uint8_t* split, const double* fine, double* coarse) {
-    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+// ---- The phases, per cell: k is the cell's index on its level (or its parent's, as stated).
+// Each phase runs as one kernel per level, as one kernel over several levels at once where
+// the levels are independent, or, for the level-serial phases on the coarse levels, in one
+// workgroup that sweeps them with a barrier between levels.
+
+// projection of the split cell k of level l from level l + 1
+__device__ void project_at(int l, const uint8_t* split, const double* fine, double* coarse, size_t k) {
+    const int n = 1 << l;
     if (k >= (size_t)n * n || !split[k]) return;
     const int i = (int)(k / n), j = (int)(k % n);
     const int m = 2 * n;
+    // every load before the stores (the compiler cannot tell the arrays apart)
+    double v[Q2];
     for (int h = 0; h < Q2; ++h) {
         const double* g = fine + (size_t)h * m * m;
         const double a = g[(size_t)(2 * i) * m + 2 * j], b = g[(size_t)(2 * i + 1) * m + 2 * j];
         const double c = g[(size_t)(2 * i) * m + 2 * j + 1], d = g[(size_t)(2 * i + 1) * m + 2 * j + 1];
-        coarse[((size_t)h * n + i) * n + j] = (((a + b) + c) + d) * 0.25;
+        v[h] = (((a + b) + c) + d) * 0.25;
     }
+    for (int h = 0; h < Q2; ++h) coarse[((size_t)h * n + i) * n + j] = v[h];
 }
 
-// details of the split cells of level l: keep (T_eps) and rule-(b) flags
-__global__ void k2_details(P2 p, int l, const uint8_t* split, const double* coarse, const double* fine, uint8_t* keep,
-                           uint8_t* ruleb, int* nan_flag) {
+// details of cell k of level l: keep (T_eps) and rule-(b) flags, and the new tree's split flag,
+// which starts as keep (the enlargement adds to it); true when a detail is not a number
+__device__ bool details_at(const P2& p, int l, const uint8_t* split, const double* coarse, const double* fine,
+                           uint8_t* keep, uint8_t* ruleb, uint8_t* nsplit, size_t k) {
     const int n = 1 << l;
-    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= (size_t)n * n) return;
+    if (k >= (size_t)n * n) return false;
     keep[k] = 0;
     ruleb[k] = 0;
-    if (!split[k]) return;
+    nsplit[k] = 0;
+    if (!split[k]) return false;
     const int i = (int)(k / n), j = (int)(k % n);
     const int m = 2 * n;
     double D = 0.0;
@@ -167,19 +179,20 @@ __global__ void k2_details(P2 p, int l, const uint8_t* split, const double* coar
                 D = d > D ? d : D;
             }
     }
-    if (bad) *nan_flag = 1;
     const double thr = ldexp(p.eps, 2 * (l + 1 - p.J));
     const double thrb = ldexp(thr, p.mu_bar + 2);
     const bool kb = bad || D >= thr;
     keep[k] = kb;
+    nsplit[k] = kb;
     ruleb[k] = kb && (l + 1 < p.J) && (bad || D >= thrb);
+    return bad;
 }
 
 // rule (a): the kept cells' children put their sigma-box (sigma = 1) into R, i.e. their parents
 // p -+ 1 split; rule (b): the four children of a flagged cell split
-__global__ void k2_enlarge(P2 p, int l, const uint8_t* keep, const uint8_t* ruleb, uint8_t* nsplit_l, uint8_t* nsplit_l1) {
+__device__ void enlarge_at(const P2& p, int l, const uint8_t* keep, const uint8_t* ruleb, uint8_t* nsplit_l,
+                           uint8_t* nsplit_l1, size_t k) {
     const int n = 1 << l;
-    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (size_t)n * n || !keep[k]) return;
     const int i = (int)(k / n), j = (int)(k % n);
     const int m = 2 * n;
@@ -196,9 +209,8 @@ __global__ void k2_enlarge(P2 p, int l, const uint8_t* keep, const uint8_t* rule
 }
 
 // grading at level a: every split (a, p) puts its gamma-box into R (the parents split)
-__global__ void k2_grade(int a, int gamma, int bc, const uint8_t* sa, uint8_t* sa1) {
+__device__ void grade_at(int a, int gamma, int bc, const uint8_t* sa, uint8_t* sa1, size_t k) {
     const int n = 1 << a;
-    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (size_t)n * n || !sa[k]) return;
     const int i = (int)(k / n), j = (int)(k % n);
     const int h = n >> 1;
@@ -208,17 +220,16 @@ __global__ void k2_grade(int a, int gamma, int bc, const uint8_t* sa, uint8_t* s
 
 // transfer at level l + 1: the children of cells split in the new tree and not in the old one
 // are predicted (one thread per parent of level l)
-__global__ void k2_transfer(P2 p, int l, const uint8_t* old_split_l, const uint8_t* new_split_l, const double* coarse,
-                            double* fine) {
+__device__ void transfer_at(const P2& p, int l, const uint8_t* old_split_l, const uint8_t* new_split_l,
+                            const double* coarse, double* fine, size_t k) {
     const int n = 1 << l, m = 2 * n;
-    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (size_t)n * n || !new_split_l[k] || old_split_l[k]) return;
     const int i = (int)(k / n), j = (int)(k % n);
-    for (int h = 0; h < Q2; ++h) {
-        const Terms q = predict_terms(p, coarse, h, n, i, j);
+    Terms q[Q2];  // every load before the stores
+    for (int h = 0; h < Q2; ++h) q[h] = predict_terms(p, coarse, h, n, i, j);
+    for (int h = 0; h < Q2; ++h)
         for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) fine[((size_t)h * m + 2 * i + a) * m + 2 * j + b] = child_value(q, a, b);
-    }
+            for (int b = 0; b < 2; ++b) fine[((size_t)h * m + 2 * i + a) * m + 2 * j + b] = child_value(q[h], a, b);
 }
 
 __device__ __forceinline__ bool collide_cell(const P2& p, double* F, size_t nn, size_t k) {
@@ -233,16 +244,14 @@ __device__ __forceinline__ bool collide_cell(const P2& p, double* F, size_t nn, 
     return bad;
 }
 
-// leaves collision at level l (cells of R not split): one thread per parent of level l - 1,
-// which collides those of its four children that are leaves when it is split (level j_min, with
-// no parent level, one thread per cell); counts the leaves (one atomic per wave)
-__global__ void k2_collide(P2 p, int l, const uint8_t* split_lm1, const uint8_t* split_l, double* F, unsigned long long* nleaf,
-                           int* nan_flag) {
+// leaves collision at level l (cells of R not split): k is a parent of level l - 1, which
+// collides those of its four children that are leaves when it is split (level j_min, with no
+// parent level: k is the cell); returns the leaves collided, bad set when a value is not a number
+__device__ int collide_at(const P2& p, int l, const uint8_t* split_lm1, const uint8_t* split_l, double* F, size_t t,
+                          bool& bad) {
     const int n = 1 << l;
     const size_t nn = (size_t)n * n;
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     int cnt = 0;
-    bool bad = false;
     if (!split_lm1) {
         if (t < nn && !(split_l && split_l[t])) {
             bad = collide_cell(p, F, nn, t);
@@ -261,10 +270,14 @@ __global__ void k2_collide(P2 p, int l, const uint8_t* split_lm1, const uint8_t*
                 }
         }
     }
+    return cnt;
+}
+
+// the leaf count of a wave into the step's total (one atomic per wave)
+__device__ void count_leaves(int cnt, unsigned long long* nleaf) {
     const unsigned long long c = (unsigned long long)__popcll(__ballot(cnt & 1)) +
                                  2ull * __popcll(__ballot(cnt & 2)) + 4ull * __popcll(__ballot(cnt & 4));
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(nleaf, c);
-    if (bad) *nan_flag = 1;
 }
 
 // leaf count of the step into the running total (cnt[0]: this step, cnt[1]: all steps)
@@ -280,26 +293,33 @@ constexpr uint8_t NEED_ALL = 15;
 // reconstruction from level l to l + 1: G_{l+1} = prediction of G_l, stored values on R (one
 // thread per parent of level l: the children of a split cell are in R, the others predicted).
 // With need_l, only the children and planes it flags (the others are left as they were).
-__global__ void k2_reconstruct(P2 p, int l, const uint8_t* split_l, const uint8_t* need_l, const double* Gl,
-                               const double* Fl1, double* Gl1) {
+__device__ void reconstruct_at(const P2& p, int l, const uint8_t* split_l, const uint8_t* need_l, const double* Gl,
+                               const double* Fl1, double* Gl1, size_t k) {
     const int n = 1 << l, m = 2 * n;
-    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (size_t)n * n) return;
     const int nb = need_l ? need_l[k] : NEED_ALL;
     if (!nb) return;
     const int i = (int)(k / n), j = (int)(k % n);
     const bool inR = split_l[k] != 0;
+    // every load before the stores (the compiler cannot tell the arrays apart)
+    double v[Q2][4];
     for (int h = 0; h < Q2; ++h) {
         const int hb = h < 2 ? (nb & 3) : (nb >> 2);
         if (!hb) continue;
-        Terms q{0.0, 0.0, 0.0, 0.0};
-        if (!inR) q = predict_terms(p, Gl, h, n, i, j);
+        if (inR) {
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) v[h][2 * a + b] = Fl1[((size_t)h * m + 2 * i + a) * m + 2 * j + b];
+        } else {
+            const Terms q = predict_terms(p, Gl, h, n, i, j);
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) v[h][2 * a + b] = child_value(q, a, b);
+        }
+    }
+    for (int h = 0; h < Q2; ++h) {
+        const int hb = h < 2 ? (nb & 3) : (nb >> 2);
         for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) {
-                if (!((hb >> (h < 2 ? a : b)) & 1)) continue;
-                const size_t o = ((size_t)h * m + 2 * i + a) * m + 2 * j + b;
-                Gl1[o] = inR ? Fl1[o] : child_value(q, a, b);
-            }
+            for (int b = 0; b < 2; ++b)
+                if ((hb >> (h < 2 ? a : b)) & 1) Gl1[((size_t)h * m + 2 * i + a) * m + 2 * j + b] = v[h][2 * a + b];
     }
 }
 
@@ -336,9 +356,10 @@ __global__ void k2_need_finest(P2 p, Splits sp, uint8_t* need) {
 // of them lies in the (2 gamma + 1)^2 prediction box of a flagged, unsplit parent of level l
 // (whose children are predicted from G_l). The four children's boxes together cover the
 // (2 gamma + 2)^2 cells from (2i - gamma, 2j - gamma); a gather, so every entry is written.
-__global__ void k2_need_up(P2 p, int l, const uint8_t* split_l, const uint8_t* need_l, uint8_t* need_lm1) {
+// (k: the parent of level l - 1)
+__device__ void need_up_at(const P2& p, int l, const uint8_t* split_l, const uint8_t* need_l, uint8_t* need_lm1,
+                           size_t k) {
     const int n = 1 << l, m = n >> 1;
-    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (size_t)m * m) return;
     const int i = (int)(k / m), j = (int)(k % m);
     const int G = p.gamma;
@@ -394,10 +415,9 @@ __device__ void stream_leaf(const P2& p, int l, int i, int j, const double* G, d
 
 // the leaves of level l < J, or of a J with no coarser level: one thread per cell, or with
 // per_velocity one per cell and velocity (long strips: the four sums side by side)
-__global__ void k2_stream_cells(P2 p, int l, const uint8_t* split_lm1, const uint8_t* split_l, const double* G,
-                                double* F, int per_velocity) {
+__device__ void stream_cells_at(const P2& p, int l, const uint8_t* split_lm1, const uint8_t* split_l, const double* G,
+                                double* F, bool per_velocity, size_t t) {
     const int n = 1 << l;
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t k = per_velocity ? t / Q2 : t;
     if (k >= (size_t)n * n) return;
     const int i = (int)(k / n), j = (int)(k % n);
@@ -422,11 +442,12 @@ __device__ __forceinline__ double lane_value(double v, int t) {
 // the leaves of level l with strips of 64 cells or more: one wave per cell and velocity. The
 // lanes load 64 strip positions at a time and every lane folds their terms in strip order, so
 // the sum is the one stream_leaf forms.
-__global__ void k2_stream_strips(P2 p, int l, const uint8_t* split_lm1, const uint8_t* split_l, const double* G,
-                                 double* F) {
+// (t: the thread of the level; the level's threads start at a multiple of 64)
+__device__ void stream_strips_at(const P2& p, int l, const uint8_t* split_lm1, const uint8_t* split_l, const double* G,
+                                 double* F, size_t t) {
     const int n = 1 << l, NJ = 1 << p.J, L = 1 << (p.J - l);
-    const size_t wv = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
+    const size_t wv = t >> 6;
+    const int lane = (int)(t & 63);
     const size_t k = wv / Q2;
     const int h = (int)(wv % Q2);
     if (k >= (size_t)n * n) return;
@@ -470,6 +491,145 @@ __global__ void k2_stream_finest(P2 p, const uint8_t* split_jm1, const double* G
     const int pi = (int)(k / np), pj = (int)(k % np);
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) stream_leaf(p, p.J, 2 * pi + a, 2 * pj + b, G, F);
+}
+
+// A run's per-level arrays by value (J <= 12), index l - j_min: values, the current tree's
+// split flags (the old tree before the transfer, the new one after it), the new tree's, the
+// keep and rule-(b) flags and the reconstruction flags.
+constexpr int MAXL2 = 13;
+struct Lv2 {
+    double* F[MAXL2];
+    const uint8_t* split[MAXL2];
+    uint8_t* nsplit[MAXL2];
+    uint8_t* keep[MAXL2];
+    uint8_t* ruleb[MAXL2];
+    uint8_t* need[MAXL2];
+};
+
+// Threads of one launch over several levels: level l0 + i owns the threads off[i] .. off[i+1] - 1
+// (each a multiple of the workgroup size, so that no workgroup spans two levels).
+struct Sweep {
+    int l0, nl;
+    unsigned long long off[MAXL2 + 1];
+};
+
+__device__ __forceinline__ int sweep_level(const Sweep& sw, unsigned long long t, unsigned long long& k) {
+    int i = 0;
+    while (i + 1 < sw.nl && t >= sw.off[i + 1]) ++i;
+    k = t - sw.off[i];
+    return sw.l0 + i;
+}
+
+__device__ __forceinline__ unsigned long long gtid() { return (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; }
+
+// ---- one level per launch
+__global__ void k2_project(int l, const uint8_t* split, const double* fine, double* coarse) {
+    project_at(l, split, fine, coarse, gtid());
+}
+__global__ void k2_grade(int a, int gamma, int bc, const uint8_t* sa, uint8_t* sa1) { grade_at(a, gamma, bc, sa, sa1, gtid()); }
+__global__ void k2_transfer(P2 p, int l, const uint8_t* old_split_l, const uint8_t* new_split_l, const double* coarse,
+                            double* fine) {
+    transfer_at(p, l, old_split_l, new_split_l, coarse, fine, gtid());
+}
+__global__ void k2_need_up(P2 p, int l, const uint8_t* split_l, const uint8_t* need_l, uint8_t* need_lm1) {
+    need_up_at(p, l, split_l, need_l, need_lm1, gtid());
+}
+__global__ void k2_reconstruct(P2 p, int l, const uint8_t* split_l, const uint8_t* need_l, const double* Gl,
+                               const double* Fl1, double* Gl1) {
+    reconstruct_at(p, l, split_l, need_l, Gl, Fl1, Gl1, gtid());
+}
+
+// ---- the independent levels of a phase in one launch
+__global__ void k2_details_all(P2 p, Sweep sw, Lv2 L, int* nan_flag) {
+    unsigned long long k;
+    const int l = sweep_level(sw, gtid(), k);
+    const int li = l - p.jmin;
+    if (details_at(p, l, L.split[li], L.F[li], L.F[li + 1], L.keep[li], L.ruleb[li], L.nsplit[li], k)) *nan_flag = 1;
+}
+__global__ void k2_enlarge_all(P2 p, Sweep sw, Lv2 L) {
+    unsigned long long k;
+    const int l = sweep_level(sw, gtid(), k);
+    const int li = l - p.jmin;
+    enlarge_at(p, l, L.keep[li], L.ruleb[li], L.nsplit[li], l + 1 < p.J ? L.nsplit[li + 1] : nullptr, k);
+}
+__global__ void k2_collide_all(P2 p, Sweep sw, Lv2 L, unsigned long long* nleaf, int* nan_flag) {
+    unsigned long long k;
+    const int l = sweep_level(sw, gtid(), k);
+    const int li = l - p.jmin;
+    bool bad = false;
+    const int cnt = collide_at(p, l, l > p.jmin ? L.split[li - 1] : nullptr, l < p.J ? L.split[li] : nullptr, L.F[li], k, bad);
+    count_leaves(cnt, nleaf);
+    if (bad) *nan_flag = 1;
+}
+__global__ void k2_stream_cells_all(P2 p, Sweep sw, Lv2 L, const double* G) {
+    unsigned long long k;
+    const int l = sweep_level(sw, gtid(), k);
+    const int li = l - p.jmin;
+    stream_cells_at(p, l, l > p.jmin ? L.split[li - 1] : nullptr, l < p.J ? L.split[li] : nullptr, G, L.F[li],
+                    p.J - l >= 4, k);
+}
+__global__ void k2_stream_strips_all(P2 p, Sweep sw, Lv2 L, const double* G) {
+    unsigned long long k;
+    const int l = sweep_level(sw, gtid(), k);
+    const int li = l - p.jmin;
+    stream_strips_at(p, l, l > p.jmin ? L.split[li - 1] : nullptr, L.split[li], G, L.F[li], k);
+}
+
+// ---- the coarse levels of a level-serial phase in one workgroup: levels of at most 4096 cells
+// for the light phases, of at most 256 for the reconstruction and its flags, whose cells each
+// wait on several dependent loads (one workgroup hides little of that latency)
+constexpr int COARSE_CELLS = 4096;
+constexpr int COARSE_CELLS_HEAVY = 256;
+constexpr int COARSE_THREADS = 1024;
+
+__global__ __launch_bounds__(COARSE_THREADS) void k2_project_coarse(Lv2 L, int jmin, int lhi, int llo) {
+    for (int l = lhi; l >= llo; --l) {
+        const size_t nn = (size_t)1 << (2 * l);
+        for (size_t k = threadIdx.x; k < nn; k += blockDim.x) project_at(l, L.split[l - jmin], L.F[l + 1 - jmin], L.F[l - jmin], k);
+        __syncthreads();
+    }
+}
+__global__ __launch_bounds__(COARSE_THREADS) void k2_grade_coarse(P2 p, Lv2 L, int ahi, int alo) {
+    for (int a = ahi; a >= alo; --a) {
+        const size_t nn = (size_t)1 << (2 * a);
+        for (size_t k = threadIdx.x; k < nn; k += blockDim.x)
+            grade_at(a, p.gamma, p.bc, L.nsplit[a - p.jmin], L.nsplit[a - 1 - p.jmin], k);
+        __syncthreads();
+    }
+}
+__global__ __launch_bounds__(COARSE_THREADS) void k2_transfer_coarse(P2 p, Lv2 L, int llo, int lhi) {
+    for (int l = llo; l <= lhi; ++l) {
+        const int li = l - p.jmin;
+        const size_t nn = (size_t)1 << (2 * l);
+        for (size_t k = threadIdx.x; k < nn; k += blockDim.x) transfer_at(p, l, L.split[li], L.nsplit[li], L.F[li], L.F[li + 1], k);
+        __syncthreads();
+    }
+}
+__global__ __launch_bounds__(COARSE_THREADS) void k2_need_up_coarse(P2 p, Lv2 L, int lhi, int llo) {
+    for (int l = lhi; l >= llo; --l) {
+        const int li = l - p.jmin;
+        const size_t nn = (size_t)1 << (2 * (l - 1));
+        for (size_t k = threadIdx.x; k < nn; k += blockDim.x) need_up_at(p, l, L.split[li], L.need[li], L.need[li - 1], k);
+        __syncthreads();
+    }
+}
+// G of level j_min is its stored values; then levels llo = j_min .. lhi, G alternating between ga
+// and gb (level l + 1 lands in gb when l - j_min is even)
+__global__ __launch_bounds__(COARSE_THREADS) void k2_reconstruct_coarse(P2 p, Lv2 L, int lhi, int use_need, double* ga,
+                                                                        double* gb) {
+    const size_t n0 = (size_t)Q2 << (2 * p.jmin);
+    for (size_t k = threadIdx.x; k < n0; k += blockDim.x) ga[k] = L.F[0][k];
+    __syncthreads();
+    for (int l = p.jmin; l <= lhi; ++l) {
+        const int li = l - p.jmin;
+        const size_t nn = (size_t)1 << (2 * l);
+        for (size_t k = threadIdx.x; k < nn; k += blockDim.x)
+            reconstruct_at(p, l, L.split[li], use_need ? L.need[li] : nullptr, ga, L.F[li + 1], gb, k);
+        __syncthreads();
+        double* t = ga;
+        ga = gb;
+        gb = t;
+    }
 }
 
 // conserved moment u on the finest level from the reconstruction
@@ -541,82 +701,149 @@ int validate2d(const mrlbm2d_params* q, std::string* why) {
     return MRLBM_OK;
 }
 
+Lv2 levels2d(const Run2D* r) {
+    Lv2 L{};
+    const int nlev = r->p.J - r->p.jmin;
+    for (int li = 0; li <= nlev; ++li) {
+        L.F[li] = r->F[li];
+        if (li < nlev) {
+            L.split[li] = r->split[li];
+            L.nsplit[li] = r->nsplit[li];
+            L.keep[li] = r->keep[li];
+            L.ruleb[li] = r->ruleb[li];
+            L.need[li] = r->need[li];
+        }
+    }
+    return L;
+}
+
+// A launch over levels lo..hi with cnt(l) threads each: returns the total thread count.
+template <class C>
+unsigned long long make_sweep(int lo, int hi, C cnt, Sweep& sw) {
+    sw.l0 = lo;
+    sw.nl = hi - lo + 1;
+    unsigned long long o = 0;
+    for (int i = 0; i < sw.nl; ++i) {
+        sw.off[i] = o;
+        o += ((unsigned long long)cnt(lo + i) + 255ull) / 256ull * 256ull;
+    }
+    sw.off[sw.nl] = o;
+    return o;
+}
+
+// The finest level of at most `cells` cells (the coarse single-workgroup kernels' range).
+int coarse_top(int cells = COARSE_CELLS) {
+    int l = 0;
+    while (((size_t)1 << (2 * (l + 1))) <= (size_t)cells) ++l;
+    return l;
+}
+
+size_t cells2(int l) { return (size_t)1 << (2 * l); }
+
+// projection up the tree of the current split flags: the fine levels one launch each, the
+// coarse ones in one workgroup
+void project2d(Run2D* r, const Lv2& L) {
+    const int J = r->p.J, jmin = r->p.jmin, lc = coarse_top();
+    for (int l = J - 1; l >= jmin && l > lc; --l)
+        hipLaunchKernelGGL(k2_project, dim3(blocks(cells2(l))), dim3(256), 0, r->stream, l, L.split[l - jmin],
+                           (const double*)L.F[l + 1 - jmin], L.F[l - jmin]);
+    const int top = std::min(lc, J - 1);
+    if (top >= jmin) hipLaunchKernelGGL(k2_project_coarse, dim3(1), dim3(COARSE_THREADS), 0, r->stream, L, jmin, top, jmin);
+}
+
+// the reconstruction of the finest level into G0 / G1 (use_need: only what the stream reads);
+// returns the buffer that holds it
+double* reconstruct2d(Run2D* r, const Lv2& L, int use_need) {
+    const P2& p = r->p;
+    const int J = p.J, jmin = p.jmin, lc = coarse_top(COARSE_CELLS_HEAVY);
+    double* ga = r->G0;
+    double* gb = r->G1;
+    const int top = std::min(lc, J - 1);
+    hipLaunchKernelGGL(k2_reconstruct_coarse, dim3(1), dim3(COARSE_THREADS), 0, r->stream, p, L, top, use_need, ga, gb);
+    if (top >= jmin && (top - jmin) % 2 == 0) std::swap(ga, gb);
+    for (int l = std::max(jmin, lc + 1); l < J; ++l) {
+        hipLaunchKernelGGL(k2_reconstruct, dim3(blocks(cells2(l))), dim3(256), 0, r->stream, p, l, L.split[l - jmin],
+                           use_need ? (const uint8_t*)L.need[l - jmin] : (const uint8_t*)nullptr, (const double*)ga,
+                           (const double*)L.F[l + 1 - jmin], gb);
+        std::swap(ga, gb);
+    }
+    return ga;
+}
+
 int step2d(Run2D* r) {
     const P2& p = r->p;
-    const int J = p.J, jmin = p.jmin;
+    const int J = p.J, jmin = p.jmin, lc = coarse_top();
     hipStream_t s = r->stream;
-    auto N = [](int l) { return (size_t)1 << l; };
+    Lv2 L = levels2d(r);
+    Sweep sw;
     // 1. projection of f^n up the tree
-    for (int l = J - 1; l >= jmin; --l)
-        hipLaunchKernelGGL(k2_project, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, (int)N(l), r->split[l - jmin],
-                           r->F[l + 1 - jmin], r->F[l - jmin]);
-    // 2. details, T_eps and rule-(b) flags
-    for (int l = jmin; l < J; ++l)
-        hipLaunchKernelGGL(k2_details, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l, r->split[l - jmin],
-                           r->F[l - jmin], r->F[l + 1 - jmin], r->keep[l - jmin], r->ruleb[l - jmin], r->d_nan);
-    // 3. enlargement: new = keep, then rules (a) and (b)
-    for (int l = jmin; l < J; ++l)
-        if (hipMemcpyAsync(r->nsplit[l - jmin], r->keep[l - jmin], N(l) * N(l), hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return MRLBM_EDEVICE;
-    for (int l = jmin; l < J; ++l)
-        hipLaunchKernelGGL(k2_enlarge, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l, r->keep[l - jmin],
-                           r->ruleb[l - jmin], r->nsplit[l - jmin], l + 1 < J ? r->nsplit[l + 1 - jmin] : nullptr);
-    // 4. grading, fine to coarse
-    for (int a = J - 1; a > jmin; --a)
-        hipLaunchKernelGGL(k2_grade, dim3(blocks(N(a) * N(a))), dim3(256), 0, s, a, p.gamma, p.bc, r->nsplit[a - jmin],
-                           r->nsplit[a - 1 - jmin]);
-    // 5. transfer, coarse to fine; then the new tree replaces the old one
-    for (int l = jmin; l < J; ++l)
-        hipLaunchKernelGGL(k2_transfer, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l, r->split[l - jmin],
-                           r->nsplit[l - jmin], r->F[l - jmin], r->F[l + 1 - jmin]);
+    project2d(r, L);
+    if (J > jmin) {
+        // 2. details, T_eps and rule-(b) flags; the new tree starts as the kept cells
+        unsigned long long nt = make_sweep(jmin, J - 1, cells2, sw);
+        hipLaunchKernelGGL(k2_details_all, dim3((unsigned)(nt / 256)), dim3(256), 0, s, p, sw, L, r->d_nan);
+        // 3. enlargement, rules (a) and (b)
+        nt = make_sweep(jmin, J - 1, cells2, sw);
+        hipLaunchKernelGGL(k2_enlarge_all, dim3((unsigned)(nt / 256)), dim3(256), 0, s, p, sw, L);
+        // 4. grading, fine to coarse
+        for (int a = J - 1; a > jmin && a > lc; --a)
+            hipLaunchKernelGGL(k2_grade, dim3(blocks(cells2(a))), dim3(256), 0, s, a, p.gamma, p.bc,
+                               (const uint8_t*)r->nsplit[a - jmin], r->nsplit[a - 1 - jmin]);
+        int top = std::min(lc, J - 1);
+        if (top > jmin) hipLaunchKernelGGL(k2_grade_coarse, dim3(1), dim3(COARSE_THREADS), 0, s, p, L, top, jmin + 1);
+        // 5. transfer, coarse to fine
+        if (top >= jmin) hipLaunchKernelGGL(k2_transfer_coarse, dim3(1), dim3(COARSE_THREADS), 0, s, p, L, jmin, top);
+        for (int l = std::max(jmin, lc + 1); l < J; ++l)
+            hipLaunchKernelGGL(k2_transfer, dim3(blocks(cells2(l))), dim3(256), 0, s, p, l, (const uint8_t*)r->split[l - jmin],
+                               (const uint8_t*)r->nsplit[l - jmin], (const double*)r->F[l - jmin], r->F[l + 1 - jmin]);
+    }
+    // the new tree replaces the old one
     std::swap(r->split, r->nsplit);
+    L = levels2d(r);
     // 6. leaves collision (d_nleaf[0] counts this step's leaves)
     if (hipMemsetAsync(r->d_nleaf, 0, sizeof(unsigned long long), s) != hipSuccess) return MRLBM_EDEVICE;
-    for (int l = jmin; l <= J; ++l)
-        hipLaunchKernelGGL(k2_collide, dim3(blocks(l > jmin ? N(l - 1) * N(l - 1) : N(l) * N(l))), dim3(256), 0, s, p, l,
-                           l > jmin ? r->split[l - 1 - jmin] : (const uint8_t*)nullptr,
-                           l < J ? r->split[l - jmin] : (const uint8_t*)nullptr, r->F[l - jmin], r->d_nleaf, r->d_nan);
+    {
+        const unsigned long long nt =
+            make_sweep(jmin, J, [jmin](int l) { return l > jmin ? cells2(l - 1) : cells2(l); }, sw);
+        hipLaunchKernelGGL(k2_collide_all, dim3((unsigned)(nt / 256)), dim3(256), 0, s, p, sw, L, r->d_nleaf, r->d_nan);
+    }
     hipLaunchKernelGGL(k2_tally, dim3(1), dim3(64), 0, s, r->d_nleaf);
-    // 7. projection of the collided values, reconstruction on the finest level, stream
-    for (int l = J - 1; l >= jmin; --l)
-        hipLaunchKernelGGL(k2_project, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, (int)N(l), r->split[l - jmin],
-                           r->F[l + 1 - jmin], r->F[l - jmin]);
-    // the reconstruction is formed only where the stream reads it: the flags go from the
-    // finest level's boundary rings up through the prediction boxes
+    // 7. projection of the collided values
+    project2d(r, L);
+    // 8. the reconstruction, formed only where the stream reads it: the flags go from the
+    // finest level's first and last columns and rows of the leaves up through the prediction boxes
     if (J > jmin) {
         Splits sp{};
         for (int l = jmin; l < J; ++l) sp.s[l - jmin] = r->split[l - jmin];
-        hipLaunchKernelGGL(k2_need_finest, dim3(blocks(N(J - 1) * N(J - 1))), dim3(256), 0, s, p, sp, r->need[J - 1 - jmin]);
-        for (int l = J - 1; l > jmin; --l)
-            hipLaunchKernelGGL(k2_need_up, dim3(blocks(N(l - 1) * N(l - 1))), dim3(256), 0, s, p, l, r->split[l - jmin],
+        hipLaunchKernelGGL(k2_need_finest, dim3(blocks(cells2(J - 1))), dim3(256), 0, s, p, sp, r->need[J - 1 - jmin]);
+        const int lh = coarse_top(COARSE_CELLS_HEAVY);
+        for (int l = J - 1; l > jmin && l > lh; --l)
+            hipLaunchKernelGGL(k2_need_up, dim3(blocks(cells2(l - 1))), dim3(256), 0, s, p, l, (const uint8_t*)r->split[l - jmin],
                                (const uint8_t*)r->need[l - jmin], r->need[l - 1 - jmin]);
+        const int top = std::min(lh, J - 1);
+        if (top > jmin) hipLaunchKernelGGL(k2_need_up_coarse, dim3(1), dim3(COARSE_THREADS), 0, s, p, L, top, jmin + 1);
     }
-    double* ga = r->G0;
-    double* gb = r->G1;
-    if (hipMemcpyAsync(ga, r->F[0], sizeof(double) * Q2 * N(jmin) * N(jmin), hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return MRLBM_EDEVICE;
-    for (int l = jmin; l < J; ++l) {
-        hipLaunchKernelGGL(k2_reconstruct, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l, r->split[l - jmin],
-                           (const uint8_t*)r->need[l - jmin], ga, r->F[l + 1 - jmin], gb);
-        std::swap(ga, gb);
+    const double* G = reconstruct2d(r, L, 1);
+    // 9. stream: strips of 64 cells or more a wave per cell and velocity, 16 or more a thread per
+    // cell and velocity, shorter ones a thread per cell; the finest leaves per parent
+    const int ls = J - 6;  // the finest level with strips of 64 cells
+    if (ls >= jmin) {
+        const unsigned long long nt = make_sweep(jmin, ls, [](int l) { return cells2(l) * Q2 * 64; }, sw);
+        hipLaunchKernelGGL(k2_stream_strips_all, dim3((unsigned)(nt / 256)), dim3(256), 0, s, p, sw, L, G);
     }
-    for (int l = jmin; l < J; ++l) {
-        const uint8_t* slm1 = l > jmin ? r->split[l - 1 - jmin] : (const uint8_t*)nullptr;
-        if (J - l >= 6) {  // strips of 64 cells or more: a wave per cell and velocity
-            hipLaunchKernelGGL(k2_stream_strips, dim3(blocks(N(l) * N(l) * Q2 * 64)), dim3(256), 0, s, p, l, slm1,
-                               r->split[l - jmin], ga, r->F[l - jmin]);
-            continue;
-        }
-        const int pv = J - l >= 4 ? 1 : 0;  // strips of 16 cells or more: a thread per velocity
-        hipLaunchKernelGGL(k2_stream_cells, dim3(blocks(N(l) * N(l) * (pv ? Q2 : 1))), dim3(256), 0, s, p, l, slm1,
-                           r->split[l - jmin], ga, r->F[l - jmin], pv);
+    if (J - 1 >= std::max(jmin, ls + 1)) {
+        const int J_ = J;
+        const unsigned long long nt = make_sweep(
+            std::max(jmin, ls + 1), J - 1, [J_](int l) { return cells2(l) * (J_ - l >= 4 ? Q2 : 1); }, sw);
+        hipLaunchKernelGGL(k2_stream_cells_all, dim3((unsigned)(nt / 256)), dim3(256), 0, s, p, sw, L, G);
     }
-    if (J > jmin)
-        hipLaunchKernelGGL(k2_stream_finest, dim3(blocks(N(J - 1) * N(J - 1))), dim3(256), 0, s, p, r->split[J - 1 - jmin],
-                           ga, r->F[J - jmin]);
-    else
-        hipLaunchKernelGGL(k2_stream_cells, dim3(blocks(N(J) * N(J))), dim3(256), 0, s, p, J, (const uint8_t*)nullptr,
-                           (const uint8_t*)nullptr, ga, r->F[0], 0);
+    if (J > jmin) {
+        hipLaunchKernelGGL(k2_stream_finest, dim3(blocks(cells2(J - 1))), dim3(256), 0, s, p, r->split[J - 1 - jmin], G,
+                           r->F[J - jmin]);
+    } else {
+        const unsigned long long nt = make_sweep(J, J, cells2, sw);
+        hipLaunchKernelGGL(k2_stream_cells_all, dim3((unsigned)(nt / 256)), dim3(256), 0, s, p, sw, L, G);
+    }
     hipError_t st = hipGetLastError();
     if (st != hipSuccess) return fail2d(r, st, "step launch");
     r->steps += 1;
@@ -805,19 +1032,9 @@ int mrlbm2d_moments(mrlbm2d_t h, double* out, int64_t cap) {
     const size_t NJ = (size_t)1 << p.J;
     if (cap < (int64_t)(NJ * NJ)) return MRLBM_ECAPACITY;
     hipStream_t s = r->stream;
-    auto N = [](int l) { return (size_t)1 << l; };
-    for (int l = p.J - 1; l >= p.jmin; --l)
-        hipLaunchKernelGGL(k2_project, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, (int)N(l), r->split[l - p.jmin],
-                           r->F[l + 1 - p.jmin], r->F[l - p.jmin]);
-    double* ga = r->G0;
-    double* gb = r->G1;
-    if (hipMemcpyAsync(ga, r->F[0], sizeof(double) * Q2 * N(p.jmin) * N(p.jmin), hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return MRLBM_EDEVICE;
-    for (int l = p.jmin; l < p.J; ++l) {
-        hipLaunchKernelGGL(k2_reconstruct, dim3(blocks(N(l) * N(l))), dim3(256), 0, s, p, l,
-                           r->split[l - p.jmin], (const uint8_t*)nullptr, ga, r->F[l + 1 - p.jmin], gb);
-        std::swap(ga, gb);
-    }
+    const Lv2 L = levels2d(r);
+    project2d(r, L);
+    const double* ga = reconstruct2d(r, L, 0);
     hipLaunchKernelGGL(k2_moment, dim3(blocks(NJ * NJ)), dim3(256), 0, s, (int)NJ, (const double*)ga, r->out);
     hipError_t st = hipMemcpyAsync(out, r->out, sizeof(double) * NJ * NJ, hipMemcpyDeviceToHost, s);
     if (st == hipSuccess) st = hipStreamSynchronize(s);
