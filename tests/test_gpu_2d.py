@@ -90,6 +90,20 @@ def test_2d_rule_b_and_finer_levels():
     run_pair(p, datum(7, "box", seed=5), 30, 10, "2d rule b J7")
 
 
+@pytest.mark.parametrize("J,jmin,gamma,bc,nsteps,every", [
+    (4, 4, 1, A.PERIODIC, 20, 10),  # a single level: no tree, every cell a leaf
+    (5, 4, 1, A.CLAMP, 20, 10),     # one level of splits
+    (9, 3, 2, A.CLAMP, 8, 4),       # wave-summed strips on one level only
+    (10, 2, 1, A.PERIODIC, 8, 4),   # every launch form: coarse sweeps, per-level launches, all stream forms
+])
+def test_2d_level_ranges(J, jmin, gamma, bc, nsteps, every):
+    """The step's launches depend on the range of levels (coarse levels swept in one
+    workgroup, the finer ones launched one by one, strips summed by waves from 64 cells):
+    each range here against the oracle, trees bit-exact and moments to 1e-12."""
+    p = params(A.BURGERS, J, 1e-3, bc=bc, gamma=gamma, jmin=jmin)
+    run_pair(p, datum(J, "box", seed=11), nsteps, every, f"2d levels {jmin}..{J} gamma {gamma} bc {bc}")
+
+
 def test_2d_eps_zero_is_the_uniform_scheme():
     p = params(A.BURGERS, 6, 0.0)
     u0 = datum(6, "box", seed=2)
