@@ -323,10 +323,19 @@ __device__ void reconstruct_at(const P2& p, int l, const uint8_t* split_l, const
     }
 }
 
-// Split flags of every level below J, by value (J <= 12).
-struct Splits {
-    const uint8_t* s[13];
+// A run's per-level arrays by value (J <= 12), index l - j_min: values, the current tree's
+// split flags (the old tree before the transfer, the new one after it), the new tree's, the
+// keep and rule-(b) flags and the reconstruction flags.
+constexpr int MAXL2 = 13;
+struct Lv2 {
+    double* F[MAXL2];
+    const uint8_t* split[MAXL2];
+    uint8_t* nsplit[MAXL2];
+    uint8_t* keep[MAXL2];
+    uint8_t* ruleb[MAXL2];
+    uint8_t* need[MAXL2];
 };
+
 
 // Which children of the parents of level J - 1 the stream reads. On an x-velocity plane a
 // leaf's stream reads the finest cells of its first and last columns and the cells just
@@ -335,16 +344,16 @@ struct Splits {
 // and last columns of every leaf, and the y planes in the first and last rows. The children
 // of a split parent are finest leaves (their own first and last columns and rows); for the
 // other parents the flags follow from their place in the coarser leaf that holds them.
-__global__ void k2_need_finest(P2 p, Splits sp, uint8_t* need) {
+__global__ void k2_need_finest(P2 p, Lv2 L, uint8_t* need) {
     const int J = p.J, n = 1 << (J - 1);
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (size_t)n * n) return;
     const int i = (int)(k / n), j = (int)(k % n);
     uint8_t v = NEED_ALL;
-    if (!sp.s[J - 1 - p.jmin][k]) {
+    if (!L.split[J - 1 - p.jmin][k]) {
         // the leaf holding the cell: its finest ancestor level whose parent is split
         int l = J - 1;
-        while (l > p.jmin && !sp.s[l - 1 - p.jmin][(size_t)(i >> (J - l)) * ((size_t)1 << (l - 1)) + (j >> (J - l))]) --l;
+        while (l > p.jmin && !L.split[l - 1 - p.jmin][(size_t)(i >> (J - l)) * ((size_t)1 << (l - 1)) + (j >> (J - l))]) --l;
         const int h = 1 << (J - 1 - l);  // the leaf's side in level-(J - 1) cells
         const int a = i & (h - 1), b = j & (h - 1);
         v = (uint8_t)((a == 0) | ((a == h - 1) << 1) | ((b == 0) << 2) | ((b == h - 1) << 3));
@@ -492,19 +501,6 @@ __global__ void k2_stream_finest(P2 p, const uint8_t* split_jm1, const double* G
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) stream_leaf(p, p.J, 2 * pi + a, 2 * pj + b, G, F);
 }
-
-// A run's per-level arrays by value (J <= 12), index l - j_min: values, the current tree's
-// split flags (the old tree before the transfer, the new one after it), the new tree's, the
-// keep and rule-(b) flags and the reconstruction flags.
-constexpr int MAXL2 = 13;
-struct Lv2 {
-    double* F[MAXL2];
-    const uint8_t* split[MAXL2];
-    uint8_t* nsplit[MAXL2];
-    uint8_t* keep[MAXL2];
-    uint8_t* ruleb[MAXL2];
-    uint8_t* need[MAXL2];
-};
 
 // Threads of one launch over several levels: level l0 + i owns the threads off[i] .. off[i+1] - 1
 // (each a multiple of the workgroup size, so that no workgroup spans two levels).
@@ -813,9 +809,7 @@ int step2d(Run2D* r) {
     // 8. the reconstruction, formed only where the stream reads it: the flags go from the
     // finest level's first and last columns and rows of the leaves up through the prediction boxes
     if (J > jmin) {
-        Splits sp{};
-        for (int l = jmin; l < J; ++l) sp.s[l - jmin] = r->split[l - jmin];
-        hipLaunchKernelGGL(k2_need_finest, dim3(blocks(cells2(J - 1))), dim3(256), 0, s, p, sp, r->need[J - 1 - jmin]);
+        hipLaunchKernelGGL(k2_need_finest, dim3(blocks(cells2(J - 1))), dim3(256), 0, s, p, L, r->need[J - 1 - jmin]);
         const int lh = coarse_top(COARSE_CELLS_HEAVY);
         for (int l = J - 1; l > jmin && l > lh; --l)
             hipLaunchKernelGGL(k2_need_up, dim3(blocks(cells2(l - 1))), dim3(256), 0, s, p, l, (const uint8_t*)r->split[l - jmin],
