@@ -90,7 +90,7 @@ typedef struct {
                             third-moment equilibrium alpha lambda^2 u (D1Q5: of the
                             fourth-moment equilibrium alpha lambda^2 hu)                  */
     double x_min, x_max; /* domain [a, b], a < b (Sec. 2)                                  */
-    int32_t j_min;       /* coarsest level, 1 <= j_min <= j_max                            */
+    int32_t j_min;       /* coarsest level, 0 <= j_min <= j_max (periodic: see below)      */
     int32_t j_max;       /* finest level J <= MRLBM_MAX_J                                   */
     int32_t gamma;       /* prediction half-width 1..3 (Sec. 3.1)                          */
     int32_t mu_bar;      /* regularity guess of enlargement rule (b), 0..30 (Sec. 4.2)      */

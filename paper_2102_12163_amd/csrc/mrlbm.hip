@@ -167,7 +167,7 @@ int validate(const mrlbm_params* p, std::string* why) {
         if (!(p->s[i] > 0.0 && p->s[i] <= 2.0)) return bad("relaxation rates must lie in (0, 2]");
     if (!isfinite(p->x_min) || !isfinite(p->x_max) || !(p->x_max > p->x_min)) return bad("need x_min < x_max");
     if (p->gamma < 1 || p->gamma > 3) return bad("gamma must be 1, 2 or 3");
-    if (p->j_min < 1 || p->j_min > p->j_max) return bad("need 1 <= j_min <= j_max");
+    if (p->j_min < 0 || p->j_min > p->j_max) return bad("need 0 <= j_min <= j_max");
     if (p->bc == MRLBM_PERIODIC && (1 << p->j_min) < 2 * p->gamma + 1)
         return bad("periodic coarsest level needs 2^j_min >= 2 gamma + 1");
     if (p->mu_bar < 0 || p->mu_bar > 30) return bad("mu_bar must be in 0..30");

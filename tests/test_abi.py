@@ -70,7 +70,7 @@ def good():
 @pytest.mark.parametrize("field,value", [
     ("abi_version", 99), ("scheme", 7), ("physics", 9), ("bc", 5), ("precision", 3), ("lam", 0.0),
     ("lam", -1.0), ("lam", float("inf")), ("s", [0.0]), ("s", [2.5]), ("s", [1.0, 1.0, 1.0]),
-    ("x_max", -2.0), ("jmin", 0), ("jmin", 9), ("gamma", 0), ("gamma", 4), ("mu_bar", -1), ("eps", -1e-3),
+    ("x_max", -2.0), ("jmin", -1), ("jmin", 9), ("gamma", 0), ("gamma", 4), ("mu_bar", -1), ("eps", -1e-3),
     ("eps", float("nan")), ("flags", 2), ("flags", 0x80000000),
 ])
 def test_validation_rejects(field, value):
@@ -87,6 +87,15 @@ def test_validation_reconstructed_collision_flag():
     assert mrlbm.validate(p) == mrlbm.OK
     p["gamma"] = 2
     p["jmin"] = 3
+    assert mrlbm.validate(p) == mrlbm.EINVAL
+
+
+def test_validation_coarsest_level_zero():
+    """J_min = 0 (a one-cell coarsest level) is accepted under clamp and refused when periodic."""
+    p = good()
+    p["jmin"], p["bc"] = 0, 1
+    assert mrlbm.validate(p) == mrlbm.OK
+    p["bc"] = 0
     assert mrlbm.validate(p) == mrlbm.EINVAL
 
 

@@ -80,6 +80,18 @@ def test_step_parity_mu_bar_and_clamp():
 
 
 @pytest.mark.parametrize("kind", KINDS)
+def test_step_parity_coarsest_level_zero(kind):
+    """J_min = 0: the coarsest level is one cell (under clamp; a periodic coarsest level needs
+    2 gamma + 1 cells). Every family against the oracle, and gamma = 2 on the first."""
+    p, mc = W.small_case(kind, seed=3, jmax=9)
+    p["jmin"], p["bc"] = 0, 1  # clamp
+    run_pair(p, mc, 60, 10, f"{kind} jmin 0")
+    if kind == KINDS[0]:
+        p["gamma"] = 2
+        run_pair(p, mc, 40, 10, f"{kind} jmin 0 gamma 2")
+
+
+@pytest.mark.parametrize("kind", KINDS)
 def test_eps_zero_is_uniform_scheme(kind):
     p, mc = W.small_case(kind, seed=1, jmax=8)
     p["eps"] = 0.0
