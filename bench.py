@@ -17,7 +17,7 @@ is timed: two launch classes, the runs with J <= 12 in workgroups of 128 threads
 per compute unit and the J = 13, 14 runs in workgroups of 256 threads sized for four, the
 heaviest class first and both grids side by side, heaviest instances first within each (the
 step is latency bound: more, smaller workgroups per CU hide more of it); the built-in tuner's
-single-launch choice is reported beside it.
+choice for the same steps (which, on this batch, is this shape) is reported beside it.
 
 Reported next to the throughput:
 * ``roofline``: algorithmic bytes (2 q s_b + 8 = 40 per leaf-cell update for D1Q2 FP64:

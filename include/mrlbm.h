@@ -305,7 +305,7 @@ const char* mrlbm_mlp_last_error(mrlbm_mlp_t m);
  * (0, +-1); moments u, m1 = lambda (f0 - f1), m2 = lambda (f2 - f3), m3 = lambda^2 (f0 + f1 - f2 - f3);
  * equilibria phi_x(u), phi_y(u), 0 with phi = (Vx u, Vy u) for advection, (u^2/2, u^2/2) for
  * Burgers): the paper leaves multi-D schemes to a companion work. Levels are held densely in
- * device memory (one kernel per phase and level); J <= 12. Conventions of the 1D handle apply
+ * device memory and stepped by level-wide kernels; J <= 12. Conventions of the 1D handle apply
  * (status codes, host validation, caller-owned host buffers, calls ordered on the stream). */
 typedef struct {
     int32_t abi_version; /* MRLBM_ABI_VERSION                                   */
