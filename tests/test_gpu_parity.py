@@ -213,6 +213,30 @@ def test_batch_equals_single_runs():
     b.close()
 
 
+def test_batch_of_uneven_coarsest_levels():
+    """Runs whose J_min differ (0 to 3, clamp) share one launch, each with its own LDS layout:
+    the batch equals the oracle run by run, on chip and on the HBM path (capacity 0)."""
+    cases = []
+    for s_, jmin in enumerate((0, 1, 2, 3, 0, 2)):
+        p, mc = W.batch_instance(s_, steps=0)
+        p["jmin"], p["bc"] = jmin, 1  # clamp
+        cases.append((p, mc))
+    ps, ms = [c[0] for c in cases], [c[1] for c in cases]
+    announce("batch jmin", [(p["jmin"], p["jmax"]) for p in ps])
+    for cap in (-1, 0):
+        b = mrlbm.Batch(ps, ms)
+        if cap == 0:
+            b.set_capacity(0)
+        b.step(40)
+        for i, (p, mc) in enumerate(cases):
+            ora = make_oracle(p, mc).step(40)
+            lv, ix = b.leaves(i)
+            olv, oix = ora.leaf_list()
+            assert np.array_equal(lv, olv) and np.array_equal(ix, oix), (cap, i)
+            assert rel_err(b.moments(i), ora.leaf_conserved()) <= 1e-12, (cap, i)
+        b.close()
+
+
 def test_full_size_burgers_d1q3():
     """The D1Q3 Burgers workload at its full size (J = 14, 16384 finest cells)."""
     p, mc = W.burgers(0, jmax=14, eps=1e-4, s=1.9)
