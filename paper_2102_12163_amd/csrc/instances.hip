@@ -18,6 +18,13 @@ template __global__ void k_steps<MRL_T, MRL_S, 3>(const Desc*, State*, const int
 template __global__ void k_query<MRL_T, MRL_S, 1>(const Desc*, State*, int, int, double*);
 template __global__ void k_query<MRL_T, MRL_S, 2>(const Desc*, State*, int, int, double*);
 template __global__ void k_query<MRL_T, MRL_S, 3>(const Desc*, State*, int, int, double*);
+// variants for runs whose tree arrays live in device memory (J above the on-chip limit)
+template __global__ void k_steps<MRL_T, MRL_S, 1, false, false, true>(const Desc*, State*, const int*, int, int, int, int);
+template __global__ void k_steps<MRL_T, MRL_S, 2, false, false, true>(const Desc*, State*, const int*, int, int, int, int);
+template __global__ void k_steps<MRL_T, MRL_S, 3, false, false, true>(const Desc*, State*, const int*, int, int, int, int);
+template __global__ void k_query<MRL_T, MRL_S, 1, true>(const Desc*, State*, int, int, double*);
+template __global__ void k_query<MRL_T, MRL_S, 2, true>(const Desc*, State*, int, int, double*);
+template __global__ void k_query<MRL_T, MRL_S, 3, true>(const Desc*, State*, int, int, double*);
 // variant that can run the reconstructed collision (gamma = 1)
 template __global__ void k_steps<MRL_T, MRL_S, 1, false, true>(const Desc*, State*, const int*, int, int, int, int);
 #if MRL_LRN

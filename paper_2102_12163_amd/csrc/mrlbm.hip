@@ -33,6 +33,12 @@ namespace mrl {
     extern template __global__ void k_query<T, S, 2>(const Desc*, State*, int, int, double*);    \
     extern template __global__ void k_query<T, S, 3>(const Desc*, State*, int, int, double*);          \
     extern template __global__ void k_steps<T, S, 1, true>(const Desc*, State*, const int*, int, int, int, int); \
+    extern template __global__ void k_steps<T, S, 1, false, false, true>(const Desc*, State*, const int*, int, int, int, int); \
+    extern template __global__ void k_steps<T, S, 2, false, false, true>(const Desc*, State*, const int*, int, int, int, int); \
+    extern template __global__ void k_steps<T, S, 3, false, false, true>(const Desc*, State*, const int*, int, int, int, int); \
+    extern template __global__ void k_query<T, S, 1, true>(const Desc*, State*, int, int, double*);   \
+    extern template __global__ void k_query<T, S, 2, true>(const Desc*, State*, int, int, double*);   \
+    extern template __global__ void k_query<T, S, 3, true>(const Desc*, State*, int, int, double*);   \
     extern template __global__ void k_steps<T, S, 1, false, true>(const Desc*, State*, const int*, int, int, int, int);
 MRL_EXTERN(double, 0)
 MRL_EXTERN(double, 1)
@@ -48,6 +54,12 @@ MRL_EXTERN(double, 4)
     extern template __global__ void k_query<T, S, 1>(const Desc*, State*, int, int, double*);    \
     extern template __global__ void k_query<T, S, 2>(const Desc*, State*, int, int, double*);    \
     extern template __global__ void k_query<T, S, 3>(const Desc*, State*, int, int, double*);         \
+    extern template __global__ void k_steps<T, S, 1, false, false, true>(const Desc*, State*, const int*, int, int, int, int); \
+    extern template __global__ void k_steps<T, S, 2, false, false, true>(const Desc*, State*, const int*, int, int, int, int); \
+    extern template __global__ void k_steps<T, S, 3, false, false, true>(const Desc*, State*, const int*, int, int, int, int); \
+    extern template __global__ void k_query<T, S, 1, true>(const Desc*, State*, int, int, double*);   \
+    extern template __global__ void k_query<T, S, 2, true>(const Desc*, State*, int, int, double*);   \
+    extern template __global__ void k_query<T, S, 3, true>(const Desc*, State*, int, int, double*);   \
     extern template __global__ void k_steps<T, S, 1, false, true>(const Desc*, State*, const int*, int, int, int, int);
 MRL_EXTERN32(float, 0)
 MRL_EXTERN32(float, 1)
@@ -106,6 +118,7 @@ struct Engine {
     hipStream_t side = nullptr;           // second stream: class launches run side by side
     hipEvent_t evf = nullptr, evj = nullptr;
     // refinement predictor
+    bool big = false;             // runs beyond the on-chip J: tree arrays in device memory
     bool lrn = false;             // launch the predictor-capable kernels
     bool any_recon = false;       // some run uses the reconstructed collision
     uint16_t* d_mlp = nullptr;
@@ -176,6 +189,8 @@ int validate(const mrlbm_params* p, std::string* why) {
         return bad("flags: only MRLBM_FLAG_RECONSTRUCTED_COLLISION is defined");
     if ((p->flags & MRLBM_FLAG_RECONSTRUCTED_COLLISION) && p->gamma != 1)
         return bad("the reconstructed collision runs with gamma = 1");
+    if ((p->flags & MRLBM_FLAG_RECONSTRUCTED_COLLISION) && p->j_max > MRLBM_ONCHIP_MAX_J)
+        return bad("the reconstructed collision runs with j_max <= MRLBM_ONCHIP_MAX_J");
     if (p->physics == MRLBM_SHALLOW_WATER && !(p->phys[1] > 0.0)) return bad("gravity must be > 0");
     if (p->physics == MRLBM_EULER && !(p->phys[2] > 1.0)) return bad("gamma_gas must be > 1");
     if (p->scheme == MRLBM_D1Q3 && p->physics == MRLBM_BURGERS && !(p->phys[3] > 0.0))
@@ -241,6 +256,11 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Largest on-chip capacity (cells of R(Lambda)) whose LDS layout fits the budget for every
 // run of the batch; never more than the full tree of the largest run.
 void choose_capacity(Engine* e) {
+    if (e->big) {  // tree arrays and values in device memory: nothing on chip
+        e->cap = e->capS = 0;
+        e->lds = e->lds_query = 0;
+        return;
+    }
     int cg_max = 0;
     for (auto& d : e->hd) cg_max = std::max(cg_max, (1 << (d.jmax + 1)) - (1 << d.jmin));
     const int tsz = e->prec == MRLBM_FP64 ? 8 : 4;
@@ -275,9 +295,9 @@ typedef void (*QueryK)(const Desc*, State*, int, int, double*);
 typedef void (*InitK)(const Desc*, State*, const double*, long long);
 
 template <typename T, int S, int G>
-void pick(StepK* s, QueryK* q) {
-    *s = k_steps<T, S, G>;
-    *q = k_query<T, S, G>;
+void pick(bool big, StepK* s, QueryK* q) {
+    *s = big ? k_steps<T, S, G, false, false, true> : k_steps<T, S, G>;
+    *q = big ? k_query<T, S, G, true> : k_query<T, S, G>;
 }
 
 StepK lrn_kernel(int scheme) {
@@ -310,13 +330,13 @@ StepK rc_kernel(int prec, int scheme) {
     }
 }
 
-bool kernels_for(int prec, int scheme, int gamma, StepK* s, QueryK* q, InitK* in) {
-#define MRL_CASE(P, TT, SS)                                          \
-    if (prec == P && scheme == SS) {                                 \
-        *in = k_init<TT, SS>;                                        \
-        if (gamma == 1) { pick<TT, SS, 1>(s, q); return true; }      \
-        if (gamma == 2) { pick<TT, SS, 2>(s, q); return true; }      \
-        if (gamma == 3) { pick<TT, SS, 3>(s, q); return true; }      \
+bool kernels_for(int prec, int scheme, int gamma, bool big, StepK* s, QueryK* q, InitK* in) {
+#define MRL_CASE(P, TT, SS)                                               \
+    if (prec == P && scheme == SS) {                                      \
+        *in = k_init<TT, SS>;                                             \
+        if (gamma == 1) { pick<TT, SS, 1>(big, s, q); return true; }      \
+        if (gamma == 2) { pick<TT, SS, 2>(big, s, q); return true; }      \
+        if (gamma == 3) { pick<TT, SS, 3>(big, s, q); return true; }      \
     }
     MRL_CASE(0, double, 0)
     MRL_CASE(0, double, 1)
@@ -404,10 +424,11 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
     e->scheme = ps[0].scheme;
     e->gamma = ps[0].gamma;
     e->P.assign(ps, ps + n);
+    for (int i = 0; i < n; ++i) e->big = e->big || ps[i].j_max > MRLBM_ONCHIP_MAX_J;
     StepK sk;
     QueryK qk;
     InitK ik;
-    kernels_for(e->prec, e->scheme, e->gamma, &sk, &qk, &ik);
+    kernels_for(e->prec, e->scheme, e->gamma, e->big, &sk, &qk, &ik);
     int dev_count = 0;
     hipError_t st = hipGetDeviceCount(&dev_count);
     if (st != hipSuccess || dev_count == 0) {
@@ -420,7 +441,7 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
     size_t off = 0;
     size_t maxNJ = 0, maxq = 0;
     e->hd.resize(n);
-    std::vector<size_t> o_va(n), o_vb(n), o_split(n), o_list(n), o_pairs(n);
+    std::vector<size_t> o_va(n), o_vb(n), o_split(n), o_list(n), o_pairs(n), o_tree(n);
     for (int i = 0; i < n; ++i) {
         const mrlbm_params& p = ps[i];
         SchemeInfo si;
@@ -437,6 +458,10 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
         off = align256(off + NJ * 4);
         o_pairs[i] = off;
         off = align256(off + 2 * (size_t)si.nm * (NJ + 1) * tsz);
+        // runs too large for LDS: the tree arrays of the step, in device memory
+        o_tree[i] = off;
+        if (e->big)
+            off = align256(off + make_layout(p.j_min, p.j_max, 0, 0, si.q, si.nm, (int)tsz, false).total);
         maxNJ = std::max(maxNJ, NJ);
         maxq = std::max(maxq, (size_t)si.q);
         e->maxJ = std::max(e->maxJ, p.j_max);
@@ -486,6 +511,7 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
         d.split = reinterpret_cast<uint64_t*>(e->pool + o_split[i]);
         d.list = reinterpret_cast<uint32_t*>(e->pool + o_list[i]);
         d.pairs = e->pool + o_pairs[i];
+        d.gtree = e->big ? reinterpret_cast<uint8_t*>(e->pool + o_tree[i]) : nullptr;
     }
     if ((st = hipMemcpyAsync(e->dd, e->hd.data(), sizeof(Desc) * n, hipMemcpyHostToDevice, e->stream)) != hipSuccess)
         return fail(st, "hipMemcpy(desc)");
@@ -567,7 +593,7 @@ static int prepare_graph(Engine* e, int nsteps) {
     StepK sk;
     QueryK qk;
     InitK ik;
-    kernels_for(e->prec, e->scheme, e->gamma, &sk, &qk, &ik);
+    kernels_for(e->prec, e->scheme, e->gamma, e->big, &sk, &qk, &ik);
     if (e->lrn) sk = lrn_kernel(e->scheme);
     else if (e->any_recon) sk = rc_kernel(e->prec, e->scheme);
     const int nt = e->nt_user ? e->nt_user : e->nt;
@@ -621,7 +647,7 @@ static int launch_once(Engine* e, int nsteps, int mode, bool use_graph) {
     StepK sk;
     QueryK qk;
     InitK ik;
-    kernels_for(e->prec, e->scheme, e->gamma, &sk, &qk, &ik);
+    kernels_for(e->prec, e->scheme, e->gamma, e->big, &sk, &qk, &ik);
     if (e->lrn) sk = lrn_kernel(e->scheme);
     else if (e->any_recon) sk = rc_kernel(e->prec, e->scheme);
     const int nt = e->nt_user ? e->nt_user : e->nt;
@@ -655,7 +681,7 @@ int run_query(Engine* e, int inst, int where, int what, int64_t* n_out) {
     StepK sk;
     QueryK qk;
     InitK ik;
-    kernels_for(e->prec, e->scheme, e->gamma, &sk, &qk, &ik);
+    kernels_for(e->prec, e->scheme, e->gamma, e->big, &sk, &qk, &ik);
     const int nt = e->nt_user ? e->nt_user : e->nt;
     hipLaunchKernelGGL(qk, dim3(1), dim3(nt), e->lds_query, e->stream, (const Desc*)(e->dd + inst), e->ds + inst,
                        where, what, e->stage);
@@ -823,7 +849,7 @@ int run_noalloc(const mrlbm_params* p, const double* d_m0, int32_t nsteps, doubl
     StepK sk;
     QueryK qk;
     InitK ik;
-    if (!kernels_for(p->precision, p->scheme, p->gamma, &sk, &qk, &ik)) return MRLBM_EINVAL;
+    if (!kernels_for(p->precision, p->scheme, p->gamma, false, &sk, &qk, &ik)) return MRLBM_EINVAL;
     const bool recon = (p->flags & MRLBM_FLAG_RECONSTRUCTED_COLLISION) != 0;
     if (recon) sk = rc_kernel(p->precision, p->scheme);
     const size_t tsz = p->precision == MRLBM_FP64 ? 8 : 4;
@@ -1152,6 +1178,10 @@ int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int
     if (!b || trial_steps <= 0) return MRLBM_EINVAL;
     Engine* e = b->e;
     if (e->numeric) return MRLBM_ENUMERIC;
+    if (e->big) {
+        e->err = "tune: runs beyond MRLBM_ONCHIP_MAX_J keep nothing on chip; set the block size instead";
+        return MRLBM_ESTATE;
+    }
     if (!e->cls.empty()) {  // the tuner chooses the shape of a single launch
         e->cls.clear();
         ++e->cls_gen;
@@ -1370,6 +1400,10 @@ static int set_classes(Engine* e, int n, const int32_t* jup, const int32_t* thre
         e->err = "classes: not with the refinement predictor";
         return MRLBM_EINVAL;
     }
+    if (e->big && n > 0) {
+        e->err = "classes: runs beyond MRLBM_ONCHIP_MAX_J keep nothing on chip";
+        return MRLBM_ESTATE;
+    }
     int maxj = 0;
     for (auto& p : e->P) maxj = std::max(maxj, p.j_max);
     for (int c = 0; c < n; ++c) {
@@ -1482,6 +1516,10 @@ static int set_predictor(Engine* e, const uint16_t* params, int32_t mode, double
     if (mode != MRLBM_PRED_OFF && (e->prec != MRLBM_FP64 || e->gamma != 1)) {
         e->err = "the refinement predictor runs with FP64 storage and gamma = 1";
         return MRLBM_EINVAL;
+    }
+    if (mode != MRLBM_PRED_OFF && e->big) {
+        e->err = "the refinement predictor runs with j_max <= MRLBM_ONCHIP_MAX_J";
+        return MRLBM_ESTATE;
     }
     if (mode != MRLBM_PRED_OFF && e->any_recon) {
         e->err = "the refinement predictor runs with the leaves collision only";

@@ -49,6 +49,7 @@ struct Desc {
     uint64_t* split;
     uint32_t* list;
     void* pairs;
+    uint8_t* gtree;  // the run's tree arrays in device memory, for runs too large for LDS (else null)
     // refinement predictor (shared by the runs of a handle)
     const uint16_t* mlp;    // bfloat16 parameters, or null
     int pmode;              // 0 off, 1 learned rule (b) with judge, 2 record training samples

@@ -107,7 +107,9 @@ struct Block {
     static constexpr int NOFF = 24;  // offset entries in front of the table (levels + 1 <= 17)
     T cc[3];
 
-    DEV Block(const Desc& dd, const Layout& L, uint8_t* lds, uint32_t* red_, int* cnts)
+    // tb: base of the tree arrays (the workgroup's LDS, or the run's device-memory copy for
+    // runs too large for LDS); lds: base of the on-chip value arrays
+    DEV Block(const Desc& dd, const Layout& L, uint8_t* tb, uint8_t* lds, uint32_t* red_, int* cnts)
         : d(dd), lay(L), red(red_) {
         tid = threadIdx.x;
         NT = blockDim.x;
@@ -119,7 +121,7 @@ struct Block {
         bc = d.bc;
         wt = L.wt;
         ws = L.ws;
-        uint64_t* bits = reinterpret_cast<uint64_t*>(lds + L.bits);
+        uint64_t* bits = reinterpret_cast<uint64_t*>(tb + L.bits);
         split = bits;
         nsplit = bits + ws;
         keep = bits + 2 * ws;
@@ -127,12 +129,12 @@ struct Block {
         ro = ruleb + wt;
         forced = LRN ? ro + wt : nullptr;
         declined = LRN ? ro + wt + ws : nullptr;
-        E = reinterpret_cast<uint64_t*>(lds + L.E);
-        uint32_t* rp = reinterpret_cast<uint32_t*>(lds + L.rp);
+        E = reinterpret_cast<uint64_t*>(tb + L.E);
+        uint32_t* rp = reinterpret_cast<uint32_t*>(tb + L.rp);
         rpo = rp;
         rpn = rp + wt + 1;
-        scanE = reinterpret_cast<uint32_t*>(lds + L.scanE);
-        uint16_t* wl = reinterpret_cast<uint16_t*>(lds + L.wl);
+        scanE = reinterpret_cast<uint32_t*>(tb + L.scanE);
+        uint16_t* wl = reinterpret_cast<uint16_t*>(tb + L.wl);
         swl = {wl, cnts};
         nswl = {wl + ws, cnts + 32};
         lwl = {wl + 2 * ws, cnts + 64};
@@ -1051,7 +1053,9 @@ DEV T* hbm_vals(const Desc& d, int which) { return reinterpret_cast<T*>(which ? 
 // R(Lambda) cells and in leaves (0 = always use the HBM arrays). LRN: the variant that can run
 // the refinement predictor (d.pmode != 0). RC: the variant that can run the reconstructed
 // collision (runs with d.recon set; the others in the same launch use the leaves collision).
-template <typename T, int S, int G, bool LRN = false, bool RC = false>
+// BIG: the variant for runs whose tree arrays exceed LDS (J > 16): the tree arrays live in the
+// run's device-memory copy d.gtree, the values in HBM, and no slot table is built.
+template <typename T, int S, int G, bool LRN = false, bool RC = false, bool BIG = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && !LRN && !RC && S <= 1) ? 4 : 1))) void k_steps(const Desc* __restrict__ descs, State* __restrict__ states,
                                                const int* __restrict__ sched, int nsteps, int mode, int cap, int capS) {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -1066,8 +1070,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
     // the run of this workgroup: the launch schedule maps workgroups to runs (identity when null)
     const int run = sched ? sched[blockIdx.x] : (int)blockIdx.x;
     const Desc& d = descs[run];
+    if constexpr (BIG) {
+        cap = 0;
+        capS = 0;
+    }
     const Layout lay = make_layout(d.jmin, d.jmax, cap, capS, d.q, d.nm, (int)sizeof(T), LRN);
-    B_t B(d, lay, lds, s_red, s_cnt);
+    B_t B(d, lay, BIG ? d.gtree : lds, lds, s_red, s_cnt);
     B.any_declined = &s_dec;
     const int Cg = (1 << (d.jmax + 1)) - (1 << d.jmin);  // slots of an HBM array
     if (threadIdx.x == 0) {
@@ -1412,7 +1420,7 @@ __global__ void k_init(const Desc* __restrict__ descs, State* __restrict__ state
 // Queries on the home copy: leaf list of the current tree, then per leaf (where = 0) its
 // conserved moments (what = 0) or populations (what = 1), or (where = 1) the reconstruction on
 // every finest cell followed by its conserved moments or populations. Output [component][position].
-template <typename T, int S, int G>
+template <typename T, int S, int G, bool BIG = false>
 __global__ __launch_bounds__(512) void k_query(const Desc* __restrict__ descs, State* __restrict__ states,
                                                int where, int what, double* __restrict__ out) {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -1422,7 +1430,7 @@ __global__ __launch_bounds__(512) void k_query(const Desc* __restrict__ descs, S
     constexpr int Q = B_t::Q;
     const Desc& d = descs[blockIdx.x];
     const Layout lay = make_layout(d.jmin, d.jmax, 0, 0, d.q, d.nm, (int)sizeof(T));
-    B_t B(d, lay, lds, s_red, s_cnt);
+    B_t B(d, lay, BIG ? d.gtree : lds, lds, s_red, s_cnt);
     const int Cg = (1 << (d.jmax + 1)) - (1 << d.jmin);
     if (threadIdx.x < 24) s_red[threadIdx.x] = 0;
     for (int w = threadIdx.x; w < lay.ws; w += blockDim.x) B.split[w] = d.split[w];

@@ -108,6 +108,23 @@ def test_validation_rejects_small_periodic_coarse_level():
     assert mrlbm.validate(p) == mrlbm.OK
 
 
+def test_level_limits_match_the_header():
+    """MAX_J and ONCHIP_MAX_J of the binding are the header's; J above the on-chip limit is
+    accepted, the reconstructed collision there is not."""
+    import re
+    from pathlib import Path
+    hdr = (Path(__file__).resolve().parents[1] / "include" / "mrlbm.h").read_text()
+    assert int(re.search(r"#define MRLBM_MAX_J (\d+)", hdr).group(1)) == mrlbm.MAX_J
+    assert int(re.search(r"#define MRLBM_ONCHIP_MAX_J (\d+)", hdr).group(1)) == mrlbm.ONCHIP_MAX_J
+    p = good()
+    p["jmax"] = mrlbm.MAX_J
+    assert mrlbm.validate(p) == mrlbm.OK
+    p["collision"] = "reconstructed"
+    assert mrlbm.validate(p) == mrlbm.EINVAL
+    p["jmax"] = mrlbm.ONCHIP_MAX_J
+    assert mrlbm.validate(p) == mrlbm.OK
+
+
 def test_validation_capacity_limit():
     p = good()
     p["jmax"] = mrlbm.MAX_J + 1

@@ -150,3 +150,52 @@ def test_shallow_water_j16_1000_steps():
         assert run.stats()["leaf_updates"] == ora.leaf_updates
     finally:
         run.close()
+
+
+@pytest.mark.parametrize("kind,J,nsteps", [
+    ("burgers", 18, 12),      # D1Q3
+    ("advection", 20, 8),     # D1Q2
+    ("shallow", 22, 4),       # D1Q2^2 at the largest J
+])
+def test_beyond_the_on_chip_levels(kind, J, nsteps):
+    """J above MRLBM_ONCHIP_MAX_J: tree arrays and values in device memory. Leaf sets bit-exact
+    and moments within 1e-12 against the oracle after every step (the first from the full
+    tree of 2^(J+1) - 2^J_min cells)."""
+    p, mc = W.small_case(kind, seed=4, jmax=J)
+    assert J > mrlbm.ONCHIP_MAX_J
+    announce("beyond on-chip J", kind, J)
+    run = mrlbm.MRLBM(p, mc)
+    ora = make_oracle(p, mc)
+    try:
+        for s in range(1, nsteps + 1):
+            run.step(1)
+            ora.step(1)
+            compare_run(run, ora, f"{kind} J{J} step {s}")
+        assert run.stats()["leaf_updates"] == ora.leaf_updates
+    finally:
+        run.close()
+
+
+def test_batch_beyond_the_on_chip_levels():
+    """A batch with one run above MRLBM_ONCHIP_MAX_J: every run then keeps its tree in device
+    memory, and each matches the oracle; the shapes that need LDS are refused."""
+    cases = [W.small_case("burgers", seed=s, jmax=J) for s, J in ((5, 10), (6, 17), (7, 13))]
+    announce("batch beyond on-chip J", [p["jmax"] for p, _ in cases])
+    b = mrlbm.Batch([p for p, _ in cases], [mc for _, mc in cases])
+    try:
+        with pytest.raises(mrlbm.MRLBMError):
+            b.tune(3)
+        with pytest.raises(mrlbm.MRLBMError):
+            b.set_classes([13, 17], [128, 256], [8, 4])
+        with pytest.raises(mrlbm.MRLBMError):
+            b.set_predictor(None, mrlbm.PRED_RECORD, sample_capacity=10)
+        b.set_block(256)
+        b.step(15)
+        for i, (p, mc) in enumerate(cases):
+            ora = make_oracle(p, mc).step(15)
+            lv, ix = b.leaves(i)
+            olv, oix = ora.leaf_list()
+            assert np.array_equal(lv, olv) and np.array_equal(ix, oix), i
+            assert rel_err(b.moments(i), ora.leaf_conserved()) <= 1e-12, i
+    finally:
+        b.close()
