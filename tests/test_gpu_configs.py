@@ -199,3 +199,30 @@ def test_batch_beyond_the_on_chip_levels():
             assert rel_err(b.moments(i), ora.leaf_conserved()) <= 1e-12, i
     finally:
         b.close()
+
+
+def test_beyond_the_on_chip_levels_fp32_and_wider_prediction():
+    """The device-memory tree instances for FP32 storage and for gamma = 2, 3: FP32 Burgers at
+    J = 18 within 1e-5 relative plus the eps bound of the FP64 oracle; gamma = 2 (clamp) and
+    gamma = 3 at J = 18 bit-exact in leaf sets, moments within 1e-12."""
+    p, mc = W.small_case("burgers", seed=8, jmax=18)
+    announce("beyond on-chip J fp32")
+    run = mrlbm.MRLBM(dict(p, precision=mrlbm.FP32_STORAGE), mc)
+    try:
+        run.step(10)
+        check_fp32("burgers J18 fp32", p, mc, run.moments(mrlbm.FINEST), 10, run.leaves())
+    finally:
+        run.close()
+    for gamma, bc in ((2, 1), (3, 0)):
+        q, mq = W.small_case("advection", seed=9, jmax=18)
+        q["gamma"], q["bc"], q["jmin"] = gamma, bc, 3
+        announce("beyond on-chip J gamma", gamma)
+        run = mrlbm.MRLBM(q, mq)
+        ora = make_oracle(q, mq)
+        try:
+            for s in range(1, 9):
+                run.step(1)
+                ora.step(1)
+                compare_run(run, ora, f"J18 gamma {gamma} step {s}")
+        finally:
+            run.close()
