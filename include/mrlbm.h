@@ -63,9 +63,8 @@ enum mrlbm_where { MRLBM_LEAVES = 0, MRLBM_FINEST = 1 };
 /* Largest finest level. Up to MRLBM_ONCHIP_MAX_J a run's tree arrays live in its workgroup's
  * LDS; above it (a handle with such a run) every run of the handle keeps its tree arrays and
  * values in device memory. That mode is much slower and has no launch classes, tuner,
- * refinement predictor or reconstructed collision (ESTATE / EINVAL). A word's index inside its
- * level is kept in 16 bits (2^16 words of 64 cells), which bounds J at 22. */
-#define MRLBM_MAX_J 22
+ * refinement predictor or reconstructed collision (ESTATE / EINVAL). */
+#define MRLBM_MAX_J 24
 #define MRLBM_ONCHIP_MAX_J 16
 
 /* Collision of the adaptive step (mrlbm_params.flags). Default (0): the leaves collision

@@ -461,7 +461,7 @@ int engine_create(const mrlbm_params* ps, int n, const double* const* m0, void* 
         // runs too large for LDS: the tree arrays of the step, in device memory
         o_tree[i] = off;
         if (e->big)
-            off = align256(off + make_layout(p.j_min, p.j_max, 0, 0, si.q, si.nm, (int)tsz, false).total);
+            off = align256(off + make_layout(p.j_min, p.j_max, 0, 0, si.q, si.nm, (int)tsz, false, 4).total);
         maxNJ = std::max(maxNJ, NJ);
         maxq = std::max(maxq, (size_t)si.q);
         e->maxJ = std::max(e->maxJ, p.j_max);

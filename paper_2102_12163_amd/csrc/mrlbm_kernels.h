@@ -29,8 +29,10 @@ struct Layout {
     unsigned bits, E, VA, VB, PP, rp, scanE, LL, wl, total;
 };
 __host__ __device__ inline unsigned al16(unsigned x) { return (x + 15u) & ~15u; }
+// wlsz: bytes of a word-list entry (a word's index inside its level): 2, or 4 for levels of more
+// than 2^16 words
 __host__ __device__ inline Layout make_layout(int jmin, int J, int cap, int capS, int q, int nm, int tsz,
-                                              bool learned = false) {
+                                              bool learned = false, int wlsz = 2) {
     Layout L;
     L.wt = wbase(jmin, J + 1);
     L.ws = wbase(jmin, J);  // levels Jmin..J-1: the split-bit arrays (no split cell at J)
@@ -60,20 +62,24 @@ __host__ __device__ inline Layout make_layout(int jmin, int J, int cap, int capS
     L.LL = o;
     if (learned) o = al16(o + (unsigned)capS * 4u);
     L.wl = o;
-    o = al16(o + (2u * (unsigned)L.ws + (unsigned)L.wt) * 2u);  // split words: levels < J
+    o = al16(o + (2u * (unsigned)L.ws + (unsigned)L.wt) * (unsigned)wlsz);  // split words: levels < J
     L.total = o;
     return L;
 }
 
 // Per-level word lists: the words of level l that carry set bits are
 // list[WB(l) .. WB(l) + count[l]) (any order inside a level).
-struct WordList {
-    uint16_t* w;
+template <typename W>
+struct WordListT {
+    W* w;
     int* c;
 };
 
-template <typename T, int S, int G, bool LRN = false>
+// WIDE: 32-bit word-list entries (levels of more than 2^16 words, J > 22)
+template <typename T, int S, int G, bool LRN = false, bool WIDE = false>
 struct Block {
+    typedef typename std::conditional<WIDE, uint32_t, uint16_t>::type WLT;
+    typedef WordListT<WLT> WordList;
     static constexpr int Q = Sch<S>::Q;
     static constexpr int NM = Sch<S>::NM;
     typedef typename LdsT<T>::type LT;
@@ -134,7 +140,7 @@ struct Block {
         rpo = rp;
         rpn = rp + wt + 1;
         scanE = reinterpret_cast<uint32_t*>(tb + L.scanE);
-        uint16_t* wl = reinterpret_cast<uint16_t*>(tb + L.wl);
+        WLT* wl = reinterpret_cast<WLT*>(tb + L.wl);
         swl = {wl, cnts};
         nswl = {wl + ws, cnts + 32};
         lwl = {wl + 2 * ws, cnts + 64};
@@ -215,7 +221,7 @@ struct Block {
             const uint64_t spw = (l < J) ? sp[w] : 0ull;
             if (spw) {
                 const int pos = atomicAdd(&sl.c[l], 1);
-                sl.w[WB(l) + pos] = (uint16_t)lw;
+                sl.w[WB(l) + pos] = (WLT)lw;
             }
             if (LW) {
                 const uint64_t lf = r & ~spw;
@@ -223,7 +229,7 @@ struct Block {
                 if (lf) {
                     nleaf += (uint32_t)__popcll(lf);
                     const int pos = atomicAdd(&ll.c[l], 1);
-                    ll.w[WB(l) + pos] = (uint16_t)lw;
+                    ll.w[WB(l) + pos] = (WLT)lw;
                 }
             }
         }
@@ -1064,7 +1070,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
     __shared__ int s_nan;
     __shared__ int s_miss;
     __shared__ int s_dec;
-    typedef Block<T, S, G, LRN> B_t;
+    typedef Block<T, S, G, LRN, BIG> B_t;
     typedef typename B_t::LT LT;
     constexpr int Q = B_t::Q;
     // the run of this workgroup: the launch schedule maps workgroups to runs (identity when null)
@@ -1074,7 +1080,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((G == 1 && 
         cap = 0;
         capS = 0;
     }
-    const Layout lay = make_layout(d.jmin, d.jmax, cap, capS, d.q, d.nm, (int)sizeof(T), LRN);
+    const Layout lay = make_layout(d.jmin, d.jmax, cap, capS, d.q, d.nm, (int)sizeof(T), LRN, BIG ? 4 : 2);
     B_t B(d, lay, BIG ? d.gtree : lds, lds, s_red, s_cnt);
     B.any_declined = &s_dec;
     const int Cg = (1 << (d.jmax + 1)) - (1 << d.jmin);  // slots of an HBM array
@@ -1426,10 +1432,10 @@ __global__ __launch_bounds__(512) void k_query(const Desc* __restrict__ descs, S
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t s_red[24];
     __shared__ int s_cnt[96];
-    typedef Block<T, S, G> B_t;
+    typedef Block<T, S, G, false, BIG> B_t;
     constexpr int Q = B_t::Q;
     const Desc& d = descs[blockIdx.x];
-    const Layout lay = make_layout(d.jmin, d.jmax, 0, 0, d.q, d.nm, (int)sizeof(T));
+    const Layout lay = make_layout(d.jmin, d.jmax, 0, 0, d.q, d.nm, (int)sizeof(T), false, BIG ? 4 : 2);
     B_t B(d, lay, BIG ? d.gtree : lds, lds, s_red, s_cnt);
     const int Cg = (1 << (d.jmax + 1)) - (1 << d.jmin);
     if (threadIdx.x < 24) s_red[threadIdx.x] = 0;

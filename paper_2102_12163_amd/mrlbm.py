@@ -21,7 +21,7 @@ PERIODIC, CLAMP = 0, 1
 FP64, FP32_STORAGE = 0, 1
 FLAG_RECONSTRUCTED_COLLISION = 1  # mrlbm_params.flags: reconstructed collision (Sec. 4.3.1)
 LEAVES, FINEST = 0, 1
-MAX_J = 22
+MAX_J = 24
 ONCHIP_MAX_J = 16
 PRED_OFF, PRED_LEARNED, PRED_RECORD = 0, 1, 2
 MLP_INPUTS, MLP_PARAMS = 32, 6337

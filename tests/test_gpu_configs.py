@@ -155,7 +155,8 @@ def test_shallow_water_j16_1000_steps():
 @pytest.mark.parametrize("kind,J,nsteps", [
     ("burgers", 18, 12),      # D1Q3
     ("advection", 20, 8),     # D1Q2
-    ("shallow", 22, 4),       # D1Q2^2 at the largest J
+    ("shallow", 22, 4),       # D1Q2^2
+    ("advection", 24, 3),     # D1Q2 at the largest J (32-bit word lists)
 ])
 def test_beyond_the_on_chip_levels(kind, J, nsteps):
     """J above MRLBM_ONCHIP_MAX_J: tree arrays and values in device memory. Leaf sets bit-exact
