@@ -319,7 +319,7 @@ typedef struct {
     double lambda;       /* lattice velocity > 0                                 */
     double s[3];         /* relaxation rates of m1, m2, m3, in (0, 2]            */
     double V[2];         /* advection velocity (advection only)                  */
-    int32_t j_min, j_max;/* 1 <= j_min <= j_max <= 12                            */
+    int32_t j_min, j_max;/* 0 <= j_min <= j_max <= 12 (periodic: 2^j_min >= 2 gamma + 1) */
     int32_t mu_bar;      /* regularity guess of rule (b), 0..30                  */
     int32_t reserved;
     double eps;          /* threshold eps >= 0                                   */

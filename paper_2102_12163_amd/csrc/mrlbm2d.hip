@@ -685,7 +685,7 @@ int validate2d(const mrlbm2d_params* q, std::string* why) {
         if (!(q->s[i] > 0.0 && q->s[i] <= 2.0)) return bad("relaxation rates must lie in (0, 2]");
     if (!isfinite(q->V[0]) || !isfinite(q->V[1])) return bad("V must be finite");
     if (q->gamma < 1 || q->gamma > 3) return bad("gamma must be 1, 2 or 3");
-    if (q->j_min < 1 || q->j_min > q->j_max) return bad("need 1 <= j_min <= j_max");
+    if (q->j_min < 0 || q->j_min > q->j_max) return bad("need 0 <= j_min <= j_max");
     if (q->j_max > 12) {
         if (why) *why = "j_max beyond 12";
         return MRLBM_ECAPACITY;

@@ -95,6 +95,8 @@ def test_2d_rule_b_and_finer_levels():
     (5, 4, 1, A.CLAMP, 20, 10),     # one level of splits
     (9, 3, 2, A.CLAMP, 8, 4),       # wave-summed strips on one level only
     (10, 2, 1, A.PERIODIC, 8, 4),   # every launch form: coarse sweeps, per-level launches, all stream forms
+    (7, 0, 1, A.CLAMP, 20, 10),     # a one-cell coarsest level
+    (8, 0, 2, A.CLAMP, 12, 6),      # the same with gamma = 2
 ])
 def test_2d_level_ranges(J, jmin, gamma, bc, nsteps, every):
     """The step's launches depend on the range of levels (coarse levels swept in one
@@ -129,8 +131,10 @@ def test_2d_validation():
     """Refused on the host: a bad parameter set, J beyond 12, a wrongly shaped datum."""
     p = params(A.ADVECTION, 6, 1e-3)
     L = mrlbm.lib()
-    for key, val in (("gamma", 4), ("jmin", 0), ("eps", -1.0), ("lam", 0.0), ("s", [2.5, 1.0, 1.0])):
+    for key, val in (("gamma", 4), ("jmin", -1), ("jmin", 0), ("eps", -1.0), ("lam", 0.0), ("s", [2.5, 1.0, 1.0])):
         assert L.mrlbm2d_validate(mrlbm.make_params2d(dict(p, **{key: val}))) == mrlbm.EINVAL, key
+    # a one-cell coarsest level is accepted under clamp (periodic needs 2 gamma + 1 cells)
+    assert L.mrlbm2d_validate(mrlbm.make_params2d(dict(p, jmin=0, bc=A.CLAMP))) == mrlbm.OK
     assert L.mrlbm2d_validate(mrlbm.make_params2d(dict(p, jmax=13))) == mrlbm.ECAPACITY
     with pytest.raises(ValueError):
         mrlbm.MRLBM2D(p, np.zeros((32, 32)))
