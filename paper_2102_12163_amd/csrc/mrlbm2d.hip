@@ -273,10 +273,36 @@ __device__ int collide_at(const P2& p, int l, const uint8_t* split_lm1, const ui
     return cnt;
 }
 
-// the leaf count of a wave into the step's total (one atomic per wave)
+// the same for four parents of level l - 1 per thread (t: the group), whose split flags one
+// 32-bit load reads (a level of at least four parents; the flag arrays are 256-byte aligned)
+__device__ int collide_quad_at(const P2& p, int l, const uint8_t* split_lm1, const uint8_t* split_l, double* F,
+                               size_t t, bool& bad) {
+    const int n = 1 << l, m = n >> 1;
+    const size_t nn = (size_t)n * n;
+    if (t >= (size_t)m * m / 4) return 0;
+    const uint32_t w = reinterpret_cast<const uint32_t*>(split_lm1)[t];
+    if (!w) return 0;
+    int cnt = 0;
+    for (int e = 0; e < 4; ++e) {
+        if (!((w >> (8 * e)) & 0xFFu)) continue;
+        const size_t q = 4 * t + e;
+        const int pi = (int)(q / m), pj = (int)(q % m);
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                const size_t k = (size_t)(2 * pi + a) * n + 2 * pj + b;
+                if (split_l && split_l[k]) continue;
+                bad = collide_cell(p, F, nn, k) || bad;
+                ++cnt;
+            }
+    }
+    return cnt;
+}
+
+// the leaf count of a wave into the step's total (one atomic per wave; at most 16 per thread)
 __device__ void count_leaves(int cnt, unsigned long long* nleaf) {
     const unsigned long long c = (unsigned long long)__popcll(__ballot(cnt & 1)) +
-                                 2ull * __popcll(__ballot(cnt & 2)) + 4ull * __popcll(__ballot(cnt & 4));
+                                 2ull * __popcll(__ballot(cnt & 2)) + 4ull * __popcll(__ballot(cnt & 4)) +
+                                 8ull * __popcll(__ballot(cnt & 8)) + 16ull * __popcll(__ballot(cnt & 16));
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(nleaf, c);
 }
 
@@ -492,7 +518,8 @@ __device__ void stream_strips_at(const P2& p, int l, const uint8_t* split_lm1, c
 }
 
 // the leaves of the finest level J > jmin (strips of one cell): one thread per parent of level
-// J - 1, which streams its four children when it is split
+// J - 1, which streams its four children when it is split (split parents cluster along fronts,
+// so grouping parents per thread would serialise their streams)
 __global__ void k2_stream_finest(P2 p, const uint8_t* split_jm1, const double* G, double* F) {
     const int n = 1 << p.J, np = n >> 1;
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -517,6 +544,7 @@ __device__ __forceinline__ int sweep_level(const Sweep& sw, unsigned long long t
 }
 
 __device__ __forceinline__ unsigned long long gtid() { return (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ unsigned long long cells_of(int l) { return 1ull << (2 * l); }
 
 // ---- one level per launch
 __global__ void k2_project(int l, const uint8_t* split, const double* fine, double* coarse) {
@@ -536,24 +564,52 @@ __global__ void k2_reconstruct(P2 p, int l, const uint8_t* split_l, const uint8_
 }
 
 // ---- the independent levels of a phase in one launch
+// Levels of at least four cells take four consecutive cells per thread in the level-wide
+// sweeps: one 32-bit load of their flags (the byte arrays are 256-byte aligned) skips the
+// group when none of them is split (details) or kept (enlargement).
+__device__ __forceinline__ bool quad_level(int l) { return l >= 1; }
+
 __global__ void k2_details_all(P2 p, Sweep sw, Lv2 L, int* nan_flag) {
     unsigned long long k;
     const int l = sweep_level(sw, gtid(), k);
     const int li = l - p.jmin;
-    if (details_at(p, l, L.split[li], L.F[li], L.F[li + 1], L.keep[li], L.ruleb[li], L.nsplit[li], k)) *nan_flag = 1;
+    if (!quad_level(l)) {
+        if (details_at(p, l, L.split[li], L.F[li], L.F[li + 1], L.keep[li], L.ruleb[li], L.nsplit[li], k)) *nan_flag = 1;
+        return;
+    }
+    if (k >= cells_of(l) / 4) return;
+    if (!reinterpret_cast<const uint32_t*>(L.split[li])[k]) {
+        reinterpret_cast<uint32_t*>(L.keep[li])[k] = 0u;
+        reinterpret_cast<uint32_t*>(L.ruleb[li])[k] = 0u;
+        reinterpret_cast<uint32_t*>(L.nsplit[li])[k] = 0u;
+        return;
+    }
+    bool bad = false;
+    for (int e = 0; e < 4; ++e)
+        bad = details_at(p, l, L.split[li], L.F[li], L.F[li + 1], L.keep[li], L.ruleb[li], L.nsplit[li], 4 * k + e) || bad;
+    if (bad) *nan_flag = 1;
 }
 __global__ void k2_enlarge_all(P2 p, Sweep sw, Lv2 L) {
     unsigned long long k;
     const int l = sweep_level(sw, gtid(), k);
     const int li = l - p.jmin;
-    enlarge_at(p, l, L.keep[li], L.ruleb[li], L.nsplit[li], l + 1 < p.J ? L.nsplit[li + 1] : nullptr, k);
+    uint8_t* nl1 = l + 1 < p.J ? L.nsplit[li + 1] : nullptr;
+    if (!quad_level(l)) {
+        enlarge_at(p, l, L.keep[li], L.ruleb[li], L.nsplit[li], nl1, k);
+        return;
+    }
+    if (k >= cells_of(l) / 4 || !reinterpret_cast<const uint32_t*>(L.keep[li])[k]) return;
+    for (int e = 0; e < 4; ++e) enlarge_at(p, l, L.keep[li], L.ruleb[li], L.nsplit[li], nl1, 4 * k + e);
 }
 __global__ void k2_collide_all(P2 p, Sweep sw, Lv2 L, unsigned long long* nleaf, int* nan_flag) {
     unsigned long long k;
     const int l = sweep_level(sw, gtid(), k);
     const int li = l - p.jmin;
     bool bad = false;
-    const int cnt = collide_at(p, l, l > p.jmin ? L.split[li - 1] : nullptr, l < p.J ? L.split[li] : nullptr, L.F[li], k, bad);
+    const int cnt = l > p.jmin && l >= 2
+                        ? collide_quad_at(p, l, L.split[li - 1], l < p.J ? L.split[li] : nullptr, L.F[li], k, bad)
+                        : collide_at(p, l, l > p.jmin ? L.split[li - 1] : nullptr, l < p.J ? L.split[li] : nullptr,
+                                     L.F[li], k, bad);
     count_leaves(cnt, nleaf);
     if (bad) *nan_flag = 1;
 }
@@ -776,10 +832,11 @@ int step2d(Run2D* r) {
     project2d(r, L);
     if (J > jmin) {
         // 2. details, T_eps and rule-(b) flags; the new tree starts as the kept cells
-        unsigned long long nt = make_sweep(jmin, J - 1, cells2, sw);
+        auto quad = [](int l) { return l >= 1 ? cells2(l) / 4 : cells2(l); };  // as quad_level
+        unsigned long long nt = make_sweep(jmin, J - 1, quad, sw);
         hipLaunchKernelGGL(k2_details_all, dim3((unsigned)(nt / 256)), dim3(256), 0, s, p, sw, L, r->d_nan);
         // 3. enlargement, rules (a) and (b)
-        nt = make_sweep(jmin, J - 1, cells2, sw);
+        nt = make_sweep(jmin, J - 1, quad, sw);
         hipLaunchKernelGGL(k2_enlarge_all, dim3((unsigned)(nt / 256)), dim3(256), 0, s, p, sw, L);
         // 4. grading, fine to coarse
         for (int a = J - 1; a > jmin && a > lc; --a)
@@ -800,7 +857,7 @@ int step2d(Run2D* r) {
     if (hipMemsetAsync(r->d_nleaf, 0, sizeof(unsigned long long), s) != hipSuccess) return MRLBM_EDEVICE;
     {
         const unsigned long long nt =
-            make_sweep(jmin, J, [jmin](int l) { return l > jmin ? cells2(l - 1) : cells2(l); }, sw);
+            make_sweep(jmin, J, [jmin](int l) { return l > jmin ? (l >= 2 ? cells2(l - 1) / 4 : cells2(l - 1)) : cells2(l); }, sw);
         hipLaunchKernelGGL(k2_collide_all, dim3((unsigned)(nt / 256)), dim3(256), 0, s, p, sw, L, r->d_nleaf, r->d_nan);
     }
     hipLaunchKernelGGL(k2_tally, dim3(1), dim3(64), 0, s, r->d_nleaf);
