@@ -204,7 +204,8 @@ int mrlbm_batch_set_capacity(mrlbm_batch_t b, int32_t cells);
  * fastest (leaf-cell updates/s); the runs end in the state they had before the call.
  * Allocates a temporary snapshot of the handle's device memory. The chosen block size and
  * capacity are returned when the pointers are non-NULL, both 0 when launch classes won
- * (mrlbm_batch_get_classes has them). */
+ * (mrlbm_batch_get_classes has them). MRLBM_ESTATE for a handle with a run beyond
+ * MRLBM_ONCHIP_MAX_J (nothing on chip to tune). */
 int mrlbm_batch_tune(mrlbm_batch_t b, int32_t trial_steps, int32_t* threads, int32_t* cells);
 /* Workgroup-to-run schedule of the batched launch (results do not depend on it). stride 0:
  * workgroup i advances run i. stride s > 0: runs ranked heaviest first by a-priori cost
@@ -240,7 +241,8 @@ int mrlbm_batch_get_capacity(mrlbm_batch_t b, int32_t* cells);
  * a class the runs go heaviest first (mrlbm_batch_set_schedule then reorders within each class).
  * Results do not depend on the classes. n = 0 restores the single launch; mrlbm_batch_tune
  * replaces the classes with its own choice; not available with the refinement predictor
- * (MRLBM_EINVAL either way). get_classes returns the number of classes in *n and, for cap_n >= *n,
+ * (MRLBM_EINVAL either way) or for a handle with a run beyond MRLBM_ONCHIP_MAX_J (MRLBM_ESTATE).
+ * get_classes returns the number of classes in *n and, for cap_n >= *n,
  * the runs and the on-chip capacity of each class. */
 int mrlbm_batch_set_classes(mrlbm_batch_t b, int32_t n, const int32_t* j_upper, const int32_t* threads,
                             const int32_t* runs_per_cu);
@@ -270,7 +272,8 @@ enum mrlbm_predictor_mode { MRLBM_PRED_OFF = 0, MRLBM_PRED_LEARNED = 1, MRLBM_PR
  * when the pair's detail after the step still reaches the rule-(b) threshold, i.e. when
  * declining it would have been a miss), up to
  * sample_capacity samples (the buffer restarts empty at each call). MRLBM_PRED_OFF restores
- * the plain method. */
+ * the plain method. FP64 storage and gamma = 1 only (MRLBM_EINVAL); MRLBM_ESTATE for a handle
+ * with a run beyond MRLBM_ONCHIP_MAX_J. */
 int mrlbm_set_predictor(mrlbm_t h, const uint16_t* bf16_params, int32_t mode, double gate, int64_t sample_capacity);
 int mrlbm_batch_set_predictor(mrlbm_batch_t b, const uint16_t* bf16_params, int32_t mode, double gate,
                               int64_t sample_capacity);
