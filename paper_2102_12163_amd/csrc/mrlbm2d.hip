@@ -389,24 +389,26 @@ __global__ void k2_need_finest(P2 p, Lv2 L, uint8_t* need) {
 
 // need_{l-1} from need_l: G_l is needed at the children of a parent of level l - 1 when one
 // of them lies in the (2 gamma + 1)^2 prediction box of a flagged, unsplit parent of level l
-// (whose children are predicted from G_l). The four children's boxes together cover the
-// (2 gamma + 2)^2 cells from (2i - gamma, 2j - gamma); a gather, so every entry is written.
-// (k: the parent of level l - 1)
+// (whose children are predicted from G_l). A plane's prediction reads that plane only, so the
+// x planes and the y planes are flagged apart (all children of the x planes: bits 0-1, of the
+// y planes: bits 2-3). The four children's boxes together cover the (2 gamma + 2)^2 cells from
+// (2i - gamma, 2j - gamma); a gather, so every entry is written. (k: the parent of level l - 1)
 __device__ void need_up_at(const P2& p, int l, const uint8_t* split_l, const uint8_t* need_l, uint8_t* need_lm1,
                            size_t k) {
     const int n = 1 << l, m = n >> 1;
     if (k >= (size_t)m * m) return;
     const int i = (int)(k / m), j = (int)(k % m);
     const int G = p.gamma;
-    bool v = false;
-    for (int di = -G; di <= G + 1 && !v; ++di) {
+    int v = 0;
+    for (int di = -G; di <= G + 1 && v != NEED_ALL; ++di) {
         const size_t row = (size_t)bci(2 * i + di, n, p.bc) * n;
         for (int dj = -G; dj <= G + 1; ++dj) {
             const size_t q = row + bci(2 * j + dj, n, p.bc);
-            v = v || (need_l[q] && !split_l[q]);
+            const int nq = need_l[q];
+            if (nq && !split_l[q]) v |= ((nq & 3) ? 3 : 0) | ((nq & 12) ? 12 : 0);
         }
     }
-    need_lm1[k] = v ? NEED_ALL : 0;
+    need_lm1[k] = (uint8_t)v;
 }
 
 // compact stream of the leaf (l, i, j) from the finest reconstruction G (N_J x N_J): per
