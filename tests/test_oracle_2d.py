@@ -93,6 +93,17 @@ def test_eps_zero_is_the_uniform_scheme_bitwise(sch):
     assert np.array_equal(a.finest_conserved(), r.conserved())
 
 
+def test_eps_zero_with_a_one_cell_coarsest_level():
+    """J_min = 0 under clamp: eps = 0 keeps the full tree and equals the uniform 2D scheme bit
+    for bit."""
+    J = 5
+    u0 = bump(J, "box")
+    a = A.Adaptive2D(SCH[1], 0, J, 1, 0.0, 0, A.CLAMP, u0).step(10)
+    r = A.Uniform2D(SCH[1], J, A.CLAMP, u0).step(10)
+    assert a.n_leaves() == 4 ** J
+    assert np.array_equal(a.finest_conserved(), r.conserved())
+
+
 @pytest.mark.parametrize("bc", [A.PERIODIC, A.CLAMP])
 def test_compact_stream_equals_the_mean_over_the_leaf(bc):
     """The strip form of the stream equals the mean of the shifted reconstruction over the

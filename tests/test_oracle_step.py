@@ -55,6 +55,27 @@ def test_dense_oracle_matches_set_twin(kind, seed):
             assert np.max(np.abs(fa - fb)) <= 1e-13 * max(1.0, np.max(np.abs(fb)))
 
 
+@pytest.mark.parametrize("kind", ["advection", "burgers", "shallow_d1q5"])
+def test_coarsest_level_zero_matches_set_twin(kind):
+    """J_min = 0 (a one-cell coarsest level, clamped): the dense oracle against the literal set
+    twin at every step (identical leaf sets, values within rounding), and eps = 0 equal to the
+    reference scheme bit for bit."""
+    p, mc = W.small_case(kind, seed=2, jmax=6)
+    p["jmin"], p["bc"] = 0, 1
+    a = build(p, mc, eps=1e-3)
+    b = build(p, mc, eps=1e-3, cls=BruteMRLBM)
+    for _ in range(15):
+        a.step(1)
+        b.step()
+        la = {l: list(np.nonzero(m)[0]) for l, m in a.leaves().items() if m.any()}
+        assert la == b.leaf_levels()
+        fa, fb = a.finest_populations(), b.finest_populations()
+        assert np.max(np.abs(fa - fb)) <= 1e-13 * max(1.0, np.max(np.abs(fb)))
+    z = build(p, mc, eps=0.0).step(20)
+    r = UniformLBM(scheme_from_params(p), p["jmax"], p["bc"], mc).step(20)
+    assert np.array_equal(z.finest_populations(), r.F)
+
+
 def check_tree_invariants(a):
     J, jmin, g = a.jmax, a.jmin, a.gamma
     R = a.complete_tree()
